@@ -1,0 +1,230 @@
+"""Oracle processors in torch float64 (paper Sec. 3, "Differentiable Audio Processors").
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Every processor maps an input u of shape [2, T] (left, right; the paper's default is stereo)
+and one parameter row p to an output y of shape [2, T]. Gradients come from torch autograd; the
+one exception is the one-pole envelope, computed by the textbook recursion (scipy's `lfilter`)
+and wrapped with its adjoint recursion (pinned by finite differences and by the convolution
+form of Eq. 9).
+
+Readings of passages the paper leaves open (each is listed with its reason in the design notes):
+* EQ tap range: 2047 taps centred at 0 (n = -1023..1023); the printed bound would give 2049.
+* EQ magnitudes: the 1024 log-magnitudes are the independent bins of a real, even response of
+  odd length 2047 (bin N-k mirrors bin k).
+* EQ window: symmetric Hann centred at 0, v[n] = 0.5 + 0.5 cos(pi n / 1023).
+* EQ alignment: centred ("same") convolution, zero input outside [0, T).
+* compressor mid signal: u_l + u_r (a sum, as printed); the envelope starts from g[-1] = 0;
+  G_u = ln(g + 1e-8); the FIR of Eq. 9 is untruncated, i.e. equal to the one-pole recursion;
+  the gain exp(G_y - G_u) multiplies the amplitude as printed; W <= 0 means a hard knee.
+* delay (Eq. 14, limited to 500 ms): five 100 ms slots of 4410 samples per channel; the delay
+  inside slot m is read from the phase of z as rint(-arg(z) * 4410 / 2 pi) mod 4410, computed in
+  float32 because it decides an integer; each slot's 39-tap filter follows the EQ recipe with
+  N = 39 and 20 log-magnitudes; the output is the wet signal only.
+* tanh distortion (not in the paper): y = tanh(exp(p) u).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.signal
+import torch
+
+F64 = torch.float64
+EPS_ENV = 1e-8
+
+
+# ---------------------------------------------------------------------------------------------
+# gain / panning (Eq. 2) and stereo imager (Eq. 3)
+
+def gain_pan(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """y_c = exp(p_c) u_c, one log-gain per channel."""
+    return torch.exp(p)[:, None] * u
+
+
+def imager(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """Mid = l + r, side = exp(p) (l - r); back to stereo as ((m+s)/2, (m-s)/2)."""
+    m = u[0] + u[1]
+    s = torch.exp(p[0]) * (u[0] - u[1])
+    return torch.stack([(m + s) / 2, (m - s) / 2])
+
+
+# ---------------------------------------------------------------------------------------------
+# zero-phase FIR design (Eq. 4): shared by the EQ (N = 2047) and the delay taps (N = 39)
+
+def zero_phase_fir(logmag: torch.Tensor, N: int, windowed: bool = True) -> torch.Tensor:
+    """Length-N (odd) zero-phase FIR from (N+1)/2 log-magnitudes: the inverse DFT of the real,
+    even magnitude response exp(logmag) (bin N-k mirrors bin k), times a symmetric Hann window
+    (omitted when `windowed` is False). Returns taps for n = -(N-1)/2 .. (N-1)/2."""
+    M = (N - 1) // 2
+    assert logmag.shape[-1] == M + 1
+    A = torch.exp(logmag)
+    n = torch.arange(-M, M + 1, dtype=F64)
+    k = torch.arange(1, M + 1, dtype=F64)
+    # inverse DFT of an even spectrum: (A_0 + 2 sum_k A_k cos(2 pi k n / N)) / N
+    cosmat = torch.cos(2.0 * math.pi * torch.outer(n, k) / N)
+    h0 = (A[0] + 2.0 * (cosmat @ A[1:])) / N
+    if not windowed:
+        return h0
+    window = 0.5 + 0.5 * torch.cos(math.pi * n / M)
+    return window * h0
+
+
+def linear_conv_centred(u: torch.Tensor, h: torch.Tensor, offset: int) -> torch.Tensor:
+    """y[t] = sum_j h[j] u[t - (j + offset)] over a [C, T] input, zero input outside [0, T):
+    tap j of `h` sits at lag j + offset. Computed as a float64 FFT linear convolution."""
+    C, T = u.shape
+    L = h.shape[-1]
+    n = 1
+    while n < T + L:
+        n *= 2
+    Uf = torch.fft.rfft(u, n=n)
+    Hf = torch.fft.rfft(h, n=n)
+    full = torch.fft.irfft(Uf * Hf, n=n)  # full[t'] = sum_j h[j] u[t' - j]
+    # y[t] = full[t - offset]
+    start = -offset
+    if start >= 0:
+        return full[..., start:start + T]
+    pad = torch.zeros(u.shape[:-1] + (-start,), dtype=u.dtype)
+    return torch.cat([pad, full[..., :T + start]], dim=-1)
+
+
+def eq(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """Zero-phase FIR EQ (Eqs. 4-5): 2047 taps from 1024 log-magnitudes, same FIR on both
+    channels, centred convolution."""
+    h = zero_phase_fir(p, 2047)
+    return linear_conv_centred(u, h, -1023)
+
+
+def eq_direct(u: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """Direct-sum form of the EQ for small inputs (numpy float64), used to cross-check the FFT
+    convolution: y_c[t] = sum_{n=-1023}^{1023} h[n] u_c[t - n]."""
+    h = zero_phase_fir(torch.as_tensor(p, dtype=F64), 2047).numpy()
+    C, T = u.shape
+    y = np.zeros((C, T))
+    for t in range(T):
+        lo, hi = max(0, t - 1023), min(T - 1, t + 1023)
+        for s in range(lo, hi + 1):
+            y[:, t] += h[t - s + 1023] * u[:, s]
+    return y
+
+
+# ---------------------------------------------------------------------------------------------
+# compressor (Eqs. 8-12)
+
+class _OnePole(torch.autograd.Function):
+    """g[t] = alpha g[t-1] + (1 - alpha) x[t], g[-1] = 0 (Eq. 8 with equal attack and release),
+    by the textbook recursion. Adjoint: lambda[t] = gbar[t] + alpha lambda[t+1];
+    xbar = (1 - alpha) lambda; alphabar = sum_t lambda[t] (g[t-1] - x[t])."""
+
+    @staticmethod
+    def forward(ctx, x, alpha):
+        a = float(alpha)
+        g = scipy.signal.lfilter([1.0 - a], [1.0, -a], x.detach().numpy())
+        g = torch.as_tensor(g, dtype=F64)
+        ctx.save_for_backward(x, alpha, g)
+        return g
+
+    @staticmethod
+    def backward(ctx, gbar):
+        x, alpha, g = ctx.saved_tensors
+        a = float(alpha)
+        lam = scipy.signal.lfilter([1.0], [1.0, -a], gbar.detach().numpy()[::-1])[::-1].copy()
+        lam = torch.as_tensor(lam, dtype=F64)
+        gprev = torch.cat([torch.zeros(1, dtype=F64), g[:-1]])
+        return (1.0 - alpha) * lam, (lam * (gprev - x)).sum().reshape(alpha.shape)
+
+
+def one_pole(x: torch.Tensor, alpha: torch.Tensor) -> torch.Tensor:
+    return _OnePole.apply(x, alpha)
+
+
+def one_pole_fir(x: torch.Tensor, alpha: torch.Tensor) -> torch.Tensor:
+    """Eq. 9 form: the envelope as the convolution of x with h[n] = (1 - alpha) alpha^n, taken
+    untruncated (length >= T), by FFT. Used to pin the recursion."""
+    T = x.shape[-1]
+    n = torch.arange(T, dtype=F64)
+    h = (1.0 - alpha) * torch.exp(n * torch.log(alpha))
+    return linear_conv_centred(x[None], h, 0)[0]
+
+
+def gain_computer(Gu, thr, knee, ratio):
+    """Quadratic-knee static curve (Eqs. 10-11): returns G_y for log-energy G_u."""
+    above = thr + (Gu - thr) / ratio
+    if float(torch.as_tensor(knee).detach()) <= 0.0:
+        return torch.where(Gu < thr, Gu, above)
+    mid = Gu + (1.0 / ratio - 1.0) * (Gu - thr + knee) ** 2 / (4.0 * knee)
+    return torch.where(Gu < thr - knee, Gu, torch.where(Gu < thr + knee, mid, above))
+
+
+def compressor(u: torch.Tensor, p: torch.Tensor, envelope=one_pole) -> torch.Tensor:
+    """Feed-forward compressor: x = (u_l + u_r)^2, one-pole energy envelope g, G_u = ln(g+eps),
+    quadratic-knee curve, y = exp(G_y - G_u) u (Eq. 12). p = (alpha, T, W, R)."""
+    alpha, thr, knee, ratio = p[0], p[1], p[2], p[3]
+    x = (u[0] + u[1]) ** 2
+    g = envelope(x, alpha)
+    Gu = torch.log(g + EPS_ENV)
+    Gy = gain_computer(Gu, thr, knee, ratio)
+    return torch.exp(Gy - Gu)[None, :] * u
+
+
+def envelope_loop(x: np.ndarray, alpha: float) -> np.ndarray:
+    """Literal per-sample loop of Eq. 8 (pure Python; small inputs only)."""
+    g = np.zeros_like(x, dtype=np.float64)
+    prev = 0.0
+    for t in range(x.shape[0]):
+        prev = alpha * prev + (1.0 - alpha) * float(x[t])
+        g[t] = prev
+    return g
+
+
+# ---------------------------------------------------------------------------------------------
+# multitap delay (Eq. 14), limited to five 100 ms slots
+
+DELAY_SLOT = 4410
+DELAY_TAPS = 5
+DELAY_BINS = 20
+
+
+def delay_offsets(p: np.ndarray) -> np.ndarray:
+    """Integer delay per (channel, slot), decided in float32 from the phase of z."""
+    q = np.asarray(p, dtype=np.float32).reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
+    ph = np.arctan2(q[..., 1], q[..., 0]).astype(np.float32)
+    frac = np.rint(-ph * np.float32(DELAY_SLOT / (2.0 * math.pi))).astype(np.int64)
+    d = np.mod(frac, DELAY_SLOT)
+    return d + DELAY_SLOT * np.arange(DELAY_TAPS)[None, :]
+
+
+def delay(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j]: per channel, five
+    integer delays, each followed by its own 39-tap zero-phase FIR. Delays are not
+    differentiable here (the surrogate gradient of Eq. 15 is not part of this path)."""
+    d = delay_offsets(p.detach().numpy())
+    q = p.reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
+    span = int(d.max()) + 39
+    ys = []
+    for c in range(2):
+        h = torch.zeros(span, dtype=F64)
+        for m in range(DELAY_TAPS):
+            taps = zero_phase_fir(q[c, m, 2:], 39)
+            start = int(d[c, m])  # tap j=-19 sits at lag d - 19 -> index d
+            h = h + torch.nn.functional.pad(taps, (start, span - start - 39))
+        ys.append(linear_conv_centred(u[c:c + 1], h, -19)[0])
+    return torch.stack(ys)
+
+
+# ---------------------------------------------------------------------------------------------
+# tanh distortion (not in the paper; drive in natural-log amplitude units)
+
+def tanh_dist(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    return torch.tanh(torch.exp(p[0]) * u)
+
+
+def identity(u: torch.Tensor, p=None) -> torch.Tensor:
+    return u
+
+
+PROCESS = {2: identity, 3: gain_pan, 4: eq, 5: compressor, 6: imager, 7: delay, 8: tanh_dist,
+           1: identity}
+N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1}

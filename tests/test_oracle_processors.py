@@ -1,0 +1,240 @@
+"""Pins of the oracle processors against closed forms, special cases, library routines and brute
+force (paper Sec. 3: Eqs. 2-5, 8-12, 14; tanh distortion is not in the paper)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.signal
+import torch
+
+from oracle import processors as P
+
+F64 = torch.float64
+
+
+def _rand(shape, seed=0):
+    return torch.as_tensor(np.random.default_rng(seed).uniform(-0.5, 0.5, size=shape), dtype=F64)
+
+
+# --- EQ (Eqs. 4-5) -----------------------------------------------------------------------------
+
+def test_flat_eq_is_identity():
+    # p = 0: the inverse DFT of a flat unit response is a unit impulse; the window is 1 at n=0
+    u = _rand((2, 5000))
+    y = P.eq(u, torch.zeros(1024, dtype=F64))
+    assert torch.max(torch.abs(y - u)) < 1e-12
+
+
+def test_eq_spectrum_is_exp_logmag():
+    # the unwindowed FIR's DFT at the N = 2047 design frequencies is exp(p_k) (bin N-k = bin k)
+    p = torch.as_tensor(np.random.default_rng(1).uniform(-1.4, 1.4, 1024), dtype=F64)
+    h0 = P.zero_phase_fir(p, 2047, windowed=False).numpy()
+    n = np.arange(-1023, 1024)
+    for k in (0, 1, 7, 500, 1023):
+        Hk = np.sum(h0 * np.exp(-2j * np.pi * k * n / 2047))
+        assert abs(Hk - math.exp(float(p[k]))) < 1e-12
+        assert abs(Hk.imag) < 1e-12
+
+
+def test_single_bin_eq_closed_form():
+    # p_j = a, others 0 -> h0[n] = delta[n] + (2/N)(e^a - 1) cos(2 pi j n / N)
+    N, j, a = 2047, 37, 0.8
+    p = torch.zeros(1024, dtype=F64)
+    p[j] = a
+    h0 = P.zero_phase_fir(p, N, windowed=False).numpy()
+    n = np.arange(-1023, 1024)
+    ref = (n == 0).astype(float) + (2.0 / N) * (math.exp(a) - 1.0) * np.cos(2 * np.pi * j * n / N)
+    assert np.max(np.abs(h0 - ref)) < 1e-13
+    h = P.zero_phase_fir(p, N).numpy()
+    win = h / np.where(np.abs(h0) > 0, h0, 1.0)
+    assert abs(h[1023] - h0[1023]) < 1e-15  # window is 1 at the centre
+    assert h[0] == 0.0 and h[-1] == 0.0  # and 0 at both ends (symmetric Hann)
+    assert np.allclose(win[1:-1][::-1], win[1:-1])  # even
+
+
+def test_eq_fft_equals_direct_sum():
+    rng = np.random.default_rng(2)
+    u = rng.uniform(-0.5, 0.5, (2, 2500))
+    p = rng.uniform(-1.0, 1.0, 1024)
+    y = P.eq(torch.as_tensor(u), torch.as_tensor(p)).numpy()
+    y_direct = P.eq_direct(u, p)
+    assert np.max(np.abs(y - y_direct)) < 1e-12
+
+
+def test_eq_matches_numpy_convolve():
+    rng = np.random.default_rng(3)
+    u = rng.uniform(-0.5, 0.5, (2, 7000))
+    p = rng.uniform(-1.0, 1.0, 1024)
+    h = P.zero_phase_fir(torch.as_tensor(p), 2047).numpy()
+    y = P.eq(torch.as_tensor(u), torch.as_tensor(p)).numpy()
+    for c in range(2):
+        ref = np.convolve(u[c], h, mode="same")  # "same" centres the odd-length kernel
+        assert np.max(np.abs(y[c] - ref)) < 1e-12
+
+
+# --- compressor (Eqs. 8-12) --------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha", [0.5, 0.99, 0.99977])
+def test_envelope_step_response(alpha):
+    c, T = 0.3, 3000
+    g = P.one_pole(torch.full((T,), c, dtype=F64), torch.tensor(alpha, dtype=F64)).numpy()
+    t = np.arange(T)
+    assert np.max(np.abs(g - c * (1 - alpha ** (t + 1)))) < 1e-13
+
+
+def test_envelope_recursion_forms_agree():
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 1, 1500) ** 2
+    a = 0.997
+    loop = P.envelope_loop(x, a)
+    lf = P.one_pole(torch.as_tensor(x), torch.tensor(a, dtype=F64)).numpy()
+    fir = P.one_pole_fir(torch.as_tensor(x), torch.tensor(a, dtype=F64)).numpy()
+    assert np.max(np.abs(lf - loop)) < 1e-13
+    assert np.max(np.abs(fir - loop)) < 1e-12
+
+
+def test_envelope_gradient_matches_fd_and_fir_form():
+    rng = np.random.default_rng(5)
+    x = torch.as_tensor(rng.uniform(0, 1, 300) ** 2).requires_grad_(True)
+    a = torch.tensor(0.95, dtype=F64, requires_grad=True)
+    assert torch.autograd.gradcheck(P.one_pole, (x, a), eps=1e-6, atol=1e-8)
+    w = torch.as_tensor(rng.normal(size=300))
+    gx1, ga1 = torch.autograd.grad((P.one_pole(x, a) * w).sum(), (x, a))
+    gx2, ga2 = torch.autograd.grad((P.one_pole_fir(x, a) * w).sum(), (x, a))
+    assert torch.max(torch.abs(gx1 - gx2)) < 1e-10 and abs(float(ga1 - ga2)) < 1e-8
+
+
+def test_compressor_below_threshold_is_identity():
+    u = _rand((2, 4000))
+    p = torch.tensor([0.99, 10.0, 0.69, 4.0], dtype=F64)  # T far above any ln(g)
+    y = P.compressor(u, p)
+    assert torch.equal(y, u)
+
+
+def test_compressor_ratio_one_is_identity():
+    u = _rand((2, 4000), 1) * 8
+    p = torch.tensor([0.99, -3.0, 0.69, 1.0], dtype=F64)
+    assert torch.max(torch.abs(P.compressor(u, p) - u)) < 1e-15 * 8
+
+
+def test_knee_continuity():
+    thr, knee, ratio = -2.0, 0.7, 4.0
+    Gu = torch.tensor([thr - knee, thr + knee], dtype=F64)
+    eps = 1e-9
+    lo = P.gain_computer(Gu - eps, thr, knee, ratio)
+    hi = P.gain_computer(Gu + eps, thr, knee, ratio)
+    assert torch.max(torch.abs(hi - lo)) < 1e-8
+    assert abs(float(P.gain_computer(Gu[1:], thr, knee, ratio)) - (thr + knee / ratio)) < 1e-12
+    # slopes: 1 below, 1/R above, continuous at both knee edges
+    for edge, left_slope, right_slope in ((thr - knee, 1.0, 1.0), (thr + knee, 1 / ratio, 1 / ratio)):
+        x = torch.tensor([edge - 2e-6, edge - 1e-6, edge + 1e-6, edge + 2e-6], dtype=F64)
+        y = P.gain_computer(x, thr, knee, ratio)
+        sl = float((y[1] - y[0]) / 1e-6)
+        sr = float((y[3] - y[2]) / 1e-6)
+        assert abs(sl - left_slope) < 1e-5 and abs(sr - right_slope) < 1e-5
+
+
+def test_compressor_static_gain_closed_form():
+    # constant input far beyond the envelope's settling time: g -> x, so the gain is the static
+    # curve above the knee: y/u = exp((1/R - 1)(ln(x + eps) - T))
+    T_, c = 20000, 0.4
+    u = torch.full((2, T_), c, dtype=F64)
+    alpha, thr, knee, ratio = 0.9, -3.0, 0.5, 3.0
+    y = P.compressor(u, torch.tensor([alpha, thr, knee, ratio], dtype=F64))
+    x = (2 * c) ** 2
+    expect = math.exp((1 / ratio - 1) * (math.log(x + 1e-8) - thr))
+    assert abs(float(y[0, -1]) / c - expect) < 1e-12
+
+
+# --- gain/pan, imager, tanh (Eqs. 2-3) ----------------------------------------------------------
+
+def test_gain_pan_and_imager_closed_forms():
+    u = _rand((2, 100), 6)
+    y = P.gain_pan(u, torch.tensor([math.log(2.0), math.log(0.5)], dtype=F64))
+    assert torch.allclose(y[0], 2 * u[0], atol=0, rtol=1e-15)
+    assert torch.allclose(y[1], 0.5 * u[1], atol=0, rtol=1e-15)
+    assert torch.max(torch.abs(P.imager(u, torch.zeros(1, dtype=F64)) - u)) < 1e-16
+    y = P.imager(u, torch.tensor([math.log(3.0)], dtype=F64))
+    m, s = y[0] + y[1], y[0] - y[1]
+    assert torch.max(torch.abs(m - (u[0] + u[1]))) < 1e-15
+    assert torch.max(torch.abs(s - 3 * (u[0] - u[1]))) < 1e-15
+    y = P.imager(u, torch.tensor([-60.0], dtype=F64))  # side removed: mono
+    assert torch.max(torch.abs(y[0] - y[1])) < 1e-15
+
+
+def test_tanh():
+    u = _rand((2, 100), 7)
+    y = P.tanh_dist(u, torch.tensor([math.log(3.0)], dtype=F64)).numpy()
+    assert np.max(np.abs(y - np.tanh(3 * u.numpy()))) < 1e-15
+    small = u * 1e-3
+    y = P.tanh_dist(small, torch.zeros(1, dtype=F64))
+    assert torch.max(torch.abs(y - (small - small ** 3 / 3))) < 1e-15
+
+
+# --- delay (Eq. 14) ------------------------------------------------------------------------------
+
+def _delay_p(d, logmags):
+    """d [2,5] integer delays inside their slots, logmags [2,5,20]."""
+    p = np.zeros((2, 5, 22))
+    ph = -2 * np.pi * np.asarray(d) / 4410
+    p[..., 0], p[..., 1] = np.cos(ph), np.sin(ph)
+    p[..., 2:] = logmags
+    return p.reshape(220).astype(np.float32)
+
+
+def test_delay_offsets_from_phasor():
+    rng = np.random.default_rng(8)
+    d = rng.integers(0, 4410, (2, 5))
+    d[0, 0], d[0, 1], d[1, 0] = 0, 2205, 4409
+    off = P.delay_offsets(_delay_p(d, np.zeros((2, 5, 20))))
+    assert np.array_equal(off, d + 4410 * np.arange(5)[None, :])
+
+
+def test_delay_single_flat_tap_is_pure_shift():
+    rng = np.random.default_rng(9)
+    d = rng.integers(0, 4410, (2, 5))
+    lm = np.full((2, 5, 20), -1000.0)  # exp(-1000) = 0 to double precision
+    lm[0, 2] = 0.0
+    lm[1, 0] = math.log(0.5)
+    p32 = _delay_p(d, lm)
+    p = torch.as_tensor(p32, dtype=F64)
+    T = 30000
+    u = _rand((2, T), 10)
+    y = P.delay(u, p).numpy()
+    sh0 = int(d[0, 2]) + 2 * 4410
+    sh1 = int(d[1, 0])
+    half = math.exp(float(p32.reshape(2, 5, 22)[1, 0, 2]))  # float32-rounded ln(0.5)
+    assert np.max(np.abs(y[0, sh0:] - u.numpy()[0, :T - sh0])) < 1e-12
+    assert np.max(np.abs(y[0, :sh0])) < 1e-12
+    assert np.max(np.abs(y[1, sh1:] - half * u.numpy()[1, :T - sh1])) < 1e-12
+
+
+def test_delay_direct_sum():
+    rng = np.random.default_rng(11)
+    d = rng.integers(0, 4410, (2, 5))
+    lm = rng.uniform(-2, 0, (2, 5, 20))
+    p32 = _delay_p(d, lm)
+    p = torch.as_tensor(p32, dtype=F64)
+    T = 23000
+    u = _rand((2, T), 12).numpy()
+    y = P.delay(torch.as_tensor(u), p).numpy()
+    off = P.delay_offsets(p32)
+    q = p.reshape(2, 5, 22)
+    for c in range(2):
+        for t in (0, 5, 4500, 13000, 22999):
+            acc = 0.0
+            for m in range(5):
+                taps = P.zero_phase_fir(q[c, m, 2:], 39).numpy()
+                for j in range(-19, 20):
+                    s = t - int(off[c, m]) - j
+                    if 0 <= s < T:
+                        acc += taps[j + 19] * u[c, s]
+            assert abs(acc - y[c, t]) < 1e-12
+
+
+def test_lfilter_reference_for_delay_free_compressor_path():
+    # scipy's lfilter with the same one-pole coefficients as an independent library routine
+    rng = np.random.default_rng(13)
+    x = rng.uniform(0, 1, 500)
+    g = P.envelope_loop(x, 0.9)
+    assert np.max(np.abs(g - scipy.signal.lfilter([0.1], [1, -0.9], x))) < 1e-14
