@@ -1,0 +1,235 @@
+/*
+ * grafx.h -- C ABI of libgrafx: batched forward render and adjoint of an audio processing graph
+ * on one AMD MI355X (gfx950).
+ *
+ * The data contract follows the paper's tensor representation of a graph (GRAFX, Lee et al.,
+ * DAFx-24, arXiv 2408.03204, Sec. 2 "Graph representations"): a node type vector T_V, an edge
+ * index E (2 x |E|), an optional edge type tensor T_E, one parameter matrix P[t] per node type
+ * (|V_t| rows, N_t columns) and a source tensor S (K x C x L), all in one shared node order: the
+ * k-th source feeds the k-th input node, the l-th row of P[t] belongs to the l-th type-t node.
+ * The render follows Algorithm 1 of the paper: schedule, reorder, build read/write indices
+ * (host, grafx_schedule), then one batched processor call per schedule step on the GPU
+ * (grafx_render). grafx_render_backward is the adjoint of grafx_render.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns a grafx_status. On an error, grafx_last_error() gives a message for the
+ *   calling thread, and the call has had no side effect: all arguments are checked before any
+ *   device work is enqueued.
+ * - Ownership: the caller owns all device memory (plan, signal buffers, workspaces, gradients);
+ *   the library never allocates or frees device memory and never synchronises a stream. A
+ *   schedule handle owns host memory only; it is immutable after creation and may be shared by
+ *   threads and streams.
+ * - Device work is enqueued on the caller's stream and runs asynchronously. Two calls that share
+ *   a workspace must be ordered on one stream (or otherwise synchronised) by the caller.
+ * - Signals are float32, stereo (C = 2), time-contiguous: a node's row is [2][T] (channel-major,
+ *   time fastest); node rows are contiguous.
+ * - Any T >= 1 is accepted.
+ *
+ * Node types (codes) and parameter rows (N_t floats per node):
+ *   0 in         --   emits its source row of S
+ *   1 out        --   sum of inputs; the graph outputs Y
+ *   2 mix        --   sum of inputs
+ *   3 gain_pan   2    y_c = exp(p_c) u_c                                  (paper Eq. 2)
+ *   4 eq         1024 zero-phase 2047-tap FIR from 1024 log-magnitudes    (Eqs. 4-5)
+ *   5 compressor 4    (alpha, T, W, R): one-pole energy envelope, quadratic knee (Eqs. 8-12)
+ *   6 imager     1    mid/side width                                     (Eq. 3)
+ *   7 delay      220  [channel 2][slot 5][re z, im z, 20 log-magnitudes]  (Eq. 14, <= 500 ms)
+ *   8 tanh       1    y = tanh(exp(p) u)                                  (not in the paper)
+ * The node input is the sum over incoming edges of the source node outputs (Eq. 1b), parallel
+ * edges counted once each, summed in original edge order.
+ */
+#ifndef GRAFX_H_
+#define GRAFX_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum grafx_status {
+  GRAFX_OK = 0,
+  GRAFX_E_ARG = 1,       /* null pointer, negative count, bad method or beam width         */
+  GRAFX_E_GRAPH = 2,     /* edge to a missing node, edge into `in`, out of `out`, no `out` */
+  GRAFX_E_CYCLE = 3,     /* the graph has a cycle                                          */
+  GRAFX_E_TYPE = 4,      /* unknown node type, or a non-zero edge type (SISO only)         */
+  GRAFX_E_SHAPE = 5,     /* T < 1, size mismatch, misaligned buffer, missing parameters    */
+  GRAFX_E_LIMIT = 6,     /* optimal schedule search exceeded its state limit               */
+  GRAFX_E_WORKSPACE = 7, /* workspace or plan buffer too small                             */
+  GRAFX_E_HIP = 8        /* a HIP runtime call or kernel launch failed                     */
+} grafx_status;
+
+enum {
+  GRAFX_IN = 0, GRAFX_OUT = 1, GRAFX_MIX = 2, GRAFX_GAIN_PAN = 3, GRAFX_EQ = 4,
+  GRAFX_COMPRESSOR = 5, GRAFX_IMAGER = 6, GRAFX_DELAY = 7, GRAFX_TANH = 8,
+  GRAFX_NUM_TYPES = 9
+};
+
+/* Schedule search methods (paper Sec. 2 "Type scheduling"; Sec. 4 "Speed benchmark"). */
+typedef enum grafx_sched_method {
+  GRAFX_SCHED_ONE_BY_ONE = 0, /* one node per step: the ready node with the smallest id        */
+  GRAFX_SCHED_GREEDY = 1,     /* the type with the most ready nodes, ties to the smallest code */
+  GRAFX_SCHED_BEAM = 2,       /* beam search over type strings (32 in the paper's benchmark)   */
+  GRAFX_SCHED_OPTIMAL = 3     /* exhaustive breadth-first search over computed-node sets       */
+} grafx_sched_method;
+
+typedef struct grafx_schedule_t grafx_schedule_t; /* opaque; host memory only */
+
+typedef struct grafx_schedule_sizes {
+  int32_t num_nodes;   /* |V|                                                  */
+  int32_t num_edges;   /* |E|                                                  */
+  int32_t num_steps;   /* N: steps 0..N; step 0 = inputs, step N = outputs     */
+  int32_t num_inputs;  /* K                                                    */
+  int32_t num_outputs; /* |V_N|                                                */
+  int32_t type_count[GRAFX_NUM_TYPES]; /* nodes per type                       */
+  int64_t plan_bytes;  /* device bytes needed by grafx_plan_upload             */
+} grafx_schedule_sizes;
+
+/*
+ * grafx_schedule -- ScheduleBatchedProcessing, OptimizeNodeOrder, Reorder and GetReadWriteIndex
+ * of Algorithm 1 (paper Sec. 2, "Type scheduling" and "Implementation details"), on the host.
+ *
+ * Splits the nodes into steps V_0..V_N that form a partition, are causal and hold one type each
+ * (Sec. 2, "Batched processing"); V_0 holds every input and V_N every output node. For the
+ * greedy, beam and optimal methods each step is the maximal set of ready nodes of its type, so a
+ * schedule is a type string. Ties: greedy prefers the smallest type code; a beam keeps, per set
+ * of computed nodes, the lexicographically smallest string, ranks by (more nodes computed, then
+ * smaller string) and keeps `beam_width` states; it ends at the first depth where a state has
+ * computed every non-output node, choosing the smallest such string. Optimal is the beam without
+ * a width cap. Nodes are then reordered by (step, original id) ("sigma"), and the read/write
+ * index lists are built as CSR arrays in that order.
+ *
+ *   num_nodes, node_type    host int32[num_nodes], codes 0..8
+ *   num_edges, edge_src/dst host int32[num_edges] each (may be NULL when num_edges == 0)
+ *   edge_type               host int32[2*num_edges] or NULL; must be all zero (SISO graphs)
+ *   method                  grafx_sched_method
+ *   beam_width              >= 1, used by GRAFX_SCHED_BEAM only
+ *   state_limit             >= 1, used by GRAFX_SCHED_OPTIMAL only: the search fails with
+ *                           GRAFX_E_LIMIT when more states than this are live at one depth
+ *   out                     receives a new handle; release it with grafx_schedule_free
+ * Errors: GRAFX_E_ARG, GRAFX_E_TYPE, GRAFX_E_GRAPH, GRAFX_E_CYCLE, GRAFX_E_LIMIT (checked in
+ * that order: types, edge endpoints, edge types, edge directions, outputs, cycles, search).
+ */
+grafx_status grafx_schedule(int32_t num_nodes, const int32_t* node_type, int32_t num_edges,
+                            const int32_t* edge_src, const int32_t* edge_dst,
+                            const int32_t* edge_type, int32_t method, int32_t beam_width,
+                            int64_t state_limit, grafx_schedule_t** out);
+
+void grafx_schedule_free(grafx_schedule_t* sched);
+
+/* Sizes of a schedule (host only). */
+grafx_status grafx_schedule_query(const grafx_schedule_t* sched, grafx_schedule_sizes* out);
+
+/*
+ * Host copies of the schedule arrays (every pointer may be NULL to skip that array):
+ *   step_type int32[N+1]  type of each step (step 0 = in, step N = out)
+ *   step_ptr  int32[N+2]  step n holds reordered positions [step_ptr[n], step_ptr[n+1])
+ *   perm      int32[V]    perm[i] = original id of the node at reordered position i
+ *   in_ptr    int32[V+1], in_src int32[E]: inputs of position i, as reordered positions of the
+ *                         sources, in original edge order (the gather/aggregate indices)
+ *   out_ptr   int32[V+1], out_dst int32[E]: outputs of position i, as reordered positions
+ *   param_row int32[V]    row of position i's node in P[type] (and, for inputs, in S; for
+ *                         outputs, in Y)
+ */
+grafx_status grafx_schedule_export(const grafx_schedule_t* sched, int32_t* step_type,
+                                   int32_t* step_ptr, int32_t* perm, int32_t* in_ptr,
+                                   int32_t* in_src, int32_t* out_ptr, int32_t* out_dst,
+                                   int32_t* param_row);
+
+/*
+ * Copy the index lists to caller-owned device memory `dev_plan` (>= plan_bytes bytes, 256-byte
+ * aligned) with an asynchronous host-to-device copy on `stream`. The host arrays belong to the
+ * handle, which must outlive the copy.
+ */
+grafx_status grafx_plan_upload(const grafx_schedule_t* sched, void* dev_plan, size_t bytes,
+                               hipStream_t stream);
+
+/* Workspace bytes for grafx_render (with_backward = 0) or for a render followed by
+ * grafx_render_backward on the same workspace (with_backward = 1), for signals of length T. */
+grafx_status grafx_workspace_bytes(const grafx_schedule_t* sched, int64_t T,
+                                   int32_t with_backward, size_t* bytes);
+
+/*
+ * grafx_render -- the batched render loop of Algorithm 1 (paper Sec. 2, "Implementation
+ * details"): for each step n = 1..N, gather and sum the inputs of the step's nodes from U,
+ * run the step's processor on all of them at once with their parameter rows, store the outputs
+ * in U.
+ *
+ *   dev_plan  device copy of the plan (grafx_plan_upload)
+ *   T         signal length (samples per channel), >= 1
+ *   S         device float32 [K][2][T], sources in node order of the input nodes
+ *   P         host array of GRAFX_NUM_TYPES device pointers; P[t] is float32 [|V_t|][N_t], rows
+ *             in node order (the paper's convention); may be NULL for types without nodes or
+ *             without parameters
+ *   U         device float32 [|V|][2][T] in reordered (sigma) order. Rows of processed nodes
+ *             (positions >= K) are written; rows [0, K) are neither read nor written: input
+ *             rows are read from S. The graph output is Y = U + step_ptr[N] * 2 * T, one row per
+ *             output node in node order.
+ *   ws        device workspace of >= grafx_workspace_bytes(sched, T, with_backward) bytes,
+ *             256-byte aligned; a later grafx_render_backward needs the same workspace contents
+ * Errors: GRAFX_E_ARG (null handle/pointers), GRAFX_E_SHAPE (T < 1, misaligned buffers, missing
+ * parameter pointer), GRAFX_E_WORKSPACE, GRAFX_E_HIP. NaN/Inf in inputs propagate.
+ */
+grafx_status grafx_render(const grafx_schedule_t* sched, const void* dev_plan, int64_t T,
+                          const float* S, const float* const* P, float* U, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
+/*
+ * grafx_render_backward -- adjoint of grafx_render (the backpropagation through the render that
+ * gradient-descent matching needs, paper Sec. 4). Steps run in reverse order; each node's
+ * output adjoint is gathered from the input adjoints of its successors, each node's input is
+ * re-gathered from U and S, and the processor's adjoint writes the node's input adjoint and
+ * its parameter-gradient partials; partials are reduced in a fixed order (deterministic).
+ * Internal signals are recomputed from U; only the compressor's per-chunk envelope carries are
+ * kept from the forward call (in `ws`).
+ *
+ *   P, S, U, T, dev_plan   exactly as passed to (and produced by) the preceding grafx_render
+ *   ws       the workspace of that grafx_render call (sized with with_backward = 1)
+ *   dY       device float32 [|V_N|][2][T], adjoint of the outputs
+ *   dU       device float32 [|V|][2][T] scratch for the input adjoints (rows of processed
+ *            nodes are written; rows [0, K) and output rows are not used)
+ *   dS       device float32 [K][2][T] or NULL: adjoint of the sources
+ *   dP       host array of GRAFX_NUM_TYPES device pointers or NULL; dP[t] (same layout as P[t])
+ *            receives the parameter gradient (overwritten, not accumulated); a NULL entry skips
+ *            that type. Delay phasors (re z, im z) receive 0: the delay times are not
+ *            differentiated.
+ */
+grafx_status grafx_render_backward(const grafx_schedule_t* sched, const void* dev_plan,
+                                   int64_t T, const float* S, const float* const* P,
+                                   const float* U, const float* dY, float* dU, float* dS,
+                                   float* const* dP, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/*
+ * Multi-resolution STFT loss between two sets of stereo signals (the loss of the paper's
+ * gradient-descent mixing application, Sec. 4): resolutions 512, 1024 and 2048, hop r/4,
+ * periodic Hann window, frames that fit inside [0, T), magnitudes sqrt(|X|^2 + 1e-8);
+ * L = (1/3) sum_r (||S_y - S_t||_F / ||S_t||_F + mean |ln S_y - ln S_t|).
+ *
+ *   rows       number of stereo rows in Y and target (e.g. the output nodes)
+ *   Y, target  device float32 [rows][2][T]
+ *   loss       device float32 scalar (written)
+ *   ws         device workspace of >= grafx_mrstft_workspace_bytes(rows, T) bytes; the
+ *              backward call must see the contents left by the forward call
+ * grafx_mrstft_backward writes dY = dloss * dL/dY (overwritten) where dloss is a device float32
+ * scalar (the upstream gradient).
+ */
+grafx_status grafx_mrstft_workspace_bytes(int32_t rows, int64_t T, size_t* bytes);
+grafx_status grafx_mrstft_loss(int32_t rows, int64_t T, const float* Y, const float* target,
+                               float* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+grafx_status grafx_mrstft_backward(int32_t rows, int64_t T, const float* Y,
+                                   const float* target, const float* dloss, float* dY, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* grafx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAFX_H_ */

@@ -1,0 +1,194 @@
+"""Python surface of the MI355X renderer: schedule, render (autograd Function), MRSTFT loss.
+
+Mirrors the paper's example API (Sec. 4, Fig. 2a): `Schedule(...)` stands in for
+`compute_render_data` (Algorithm 1 preprocessing, on the host in C++), `render(...)` for
+`render_grafx` (the batched render loop, HIP kernels), with the hand-written adjoint behind
+`torch.autograd.Function`. Every step runs in libgrafx; this module only marshals arguments.
+PyTorch supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+TYPE_CODES = {"in": 0, "out": 1, "mix": 2, "gain_pan": 3, "eq": 4, "compressor": 5, "imager": 6,
+              "delay": 7, "tanh": 8}
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1)
+METHODS = {"one_by_one": 0, "greedy": 1, "beam": 2, "optimal": 3}
+
+
+def _iptr(a):
+    return None if a is None else a.ctypes.data_as(_lib.c_i32p)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Schedule:
+    """A scheduled graph: the type string, the node reordering and the read/write index lists,
+    computed on the host by libgrafx (`grafx_schedule`)."""
+
+    def __init__(self, node_type, edges, method: str | int = "beam", beam_width: int = 32,
+                 state_limit: int = 1 << 20, edge_type=None):
+        lib = load()
+        nt = np.ascontiguousarray(np.asarray(node_type), dtype=np.int32)
+        e = np.asarray(edges, dtype=np.int32).reshape(2, -1)
+        src, dst = np.ascontiguousarray(e[0]), np.ascontiguousarray(e[1])
+        et = None if edge_type is None else np.ascontiguousarray(
+            np.asarray(edge_type), dtype=np.int32).reshape(-1)
+        m = METHODS[method] if isinstance(method, str) else int(method)
+        h = ctypes.c_void_p()
+        check(lib.grafx_schedule(nt.shape[0], _iptr(nt), e.shape[1], _iptr(src), _iptr(dst),
+                                 _iptr(et), m, beam_width, state_limit, ctypes.byref(h)))
+        self._h = h
+        s = _lib.ScheduleSizes()
+        check(lib.grafx_schedule_query(h, ctypes.byref(s)))
+        self.num_nodes, self.num_edges, self.num_steps = s.num_nodes, s.num_edges, s.num_steps
+        self.num_inputs, self.num_outputs = s.num_inputs, s.num_outputs
+        self.type_count = list(s.type_count)
+        self.plan_bytes = int(s.plan_bytes)
+        V, E, N = s.num_nodes, s.num_edges, s.num_steps
+        arr = lambda n: np.zeros(max(n, 1), dtype=np.int32)  # noqa: E731
+        self.step_type, self.step_ptr, self.perm = arr(N + 1), arr(N + 2), arr(V)
+        self.in_ptr, self.in_src, self.out_ptr, self.out_dst = arr(V + 1), arr(E), arr(V + 1), arr(E)
+        self.param_row = arr(V)
+        check(lib.grafx_schedule_export(h, *[_iptr(a) for a in (
+            self.step_type, self.step_ptr, self.perm, self.in_ptr, self.in_src, self.out_ptr,
+            self.out_dst, self.param_row)]))
+        self.in_src, self.out_dst = self.in_src[:E], self.out_dst[:E]
+        self.out_begin = int(self.step_ptr[N])
+        self._plans: dict = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().grafx_schedule_free(h)
+            self._h = None
+
+    def type_string(self) -> tuple:
+        return tuple(int(t) for t in self.step_type)
+
+    def plan(self, device) -> torch.Tensor:
+        """Device copy of the index lists (uploaded once per device, on the current stream)."""
+        device = torch.device(device)
+        if device not in self._plans:
+            t = torch.empty(max(self.plan_bytes, 256), dtype=torch.uint8, device=device)
+            check(load().grafx_plan_upload(self._h, t.data_ptr(), t.numel(), _stream(device)))
+            self._plans[device] = t
+        return self._plans[device]
+
+    def workspace_bytes(self, T: int, with_backward: bool) -> int:
+        n = ctypes.c_size_t()
+        check(load().grafx_workspace_bytes(self._h, T, int(with_backward), ctypes.byref(n)))
+        return int(n.value)
+
+
+def _param_list(sched: Schedule, P) -> list:
+    out = [None] * 9
+    for k, v in (P or {}).items():
+        t = TYPE_CODES[k] if isinstance(k, str) else int(k)
+        out[t] = v
+    for t in range(9):
+        if N_PARAMS[t] and sched.type_count[t] > 0:
+            p = out[t]
+            if p is None:
+                raise ValueError(f"missing parameters for node type {t}")
+            if p.dtype != torch.float32 or not p.is_contiguous() or \
+                    tuple(p.shape) != (sched.type_count[t], N_PARAMS[t]):
+                raise ValueError(f"parameters of type {t} must be contiguous float32 "
+                                 f"[{sched.type_count[t]}, {N_PARAMS[t]}]")
+        elif N_PARAMS[t] == 0 or sched.type_count[t] == 0:
+            out[t] = None
+    return out
+
+
+def _ptrs(tensors) -> "_lib.ptr_array":
+    return _lib.ptr_array(*[(t.data_ptr() if t is not None else None) for t in tensors])
+
+
+class _Render(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sched: Schedule, holder: list, S: torch.Tensor, *P):
+        dev = S.device
+        K, T = sched.num_inputs, int(S.shape[-1])
+        if S.dtype != torch.float32 or not S.is_contiguous() or tuple(S.shape) != (K, 2, T):
+            raise ValueError(f"sources must be contiguous float32 [{K}, 2, T]")
+        want_bwd = any(ctx.needs_input_grad[2:])
+        U = torch.empty((sched.num_nodes, 2, T), dtype=torch.float32, device=dev)
+        ws = torch.empty(max(sched.workspace_bytes(T, want_bwd), 256), dtype=torch.uint8,
+                         device=dev)
+        check(load().grafx_render(sched._h, sched.plan(dev).data_ptr(), T, S.data_ptr(),
+                                  _ptrs(P), U.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream(dev)))
+        ctx.sched, ctx.U, ctx.ws = sched, U, ws
+        ctx.save_for_backward(S, *[p if p is not None else torch.empty(0) for p in P])
+        ctx.present = [p is not None for p in P]
+        holder.append(U)
+        return U[sched.out_begin:]
+
+    @staticmethod
+    def backward(ctx, gY):
+        sched, U, ws = ctx.sched, ctx.U, ctx.ws
+        S, *P = ctx.saved_tensors
+        P = [p if ok else None for p, ok in zip(P, ctx.present)]
+        dev, T = U.device, U.shape[-1]
+        dY = gY.contiguous() if gY is not None else torch.zeros_like(U[sched.out_begin:])
+        dU = torch.empty_like(U)
+        dS = torch.empty_like(S) if ctx.needs_input_grad[2] else None
+        dP = [torch.empty_like(p) if (p is not None and ctx.needs_input_grad[3 + t]) else None
+              for t, p in enumerate(P)]
+        check(load().grafx_render_backward(
+            sched._h, sched.plan(dev).data_ptr(), T, S.data_ptr(), _ptrs(P), U.data_ptr(),
+            dY.data_ptr(), dU.data_ptr(), dS.data_ptr() if dS is not None else None, _ptrs(dP),
+            ws.data_ptr(), ws.numel(), _stream(dev)))
+        return (None, None, dS, *dP)
+
+
+def render(sched: Schedule, S: torch.Tensor, P: dict, return_U: bool = False):
+    """Batched render of the scheduled graph (paper Algorithm 1). S: [K, 2, T] float32 on the
+    GPU; P: type (code or name) -> float32 [|V_t|, N_t]. Returns Y [|V_N|, 2, T] (and U
+    [|V|, 2, T] in reordered order, whose input rows [0, K) are not written)."""
+    holder: list = []
+    Y = _Render.apply(sched, holder, S, *_param_list(sched, P))
+    return (Y, holder[0]) if return_U else Y
+
+
+class _MRSTFT(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Y, target):
+        rows, T = int(Y.shape[0]), int(Y.shape[-1])
+        for t in (Y, target):
+            if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (rows, 2, T):
+                raise ValueError("Y and target must be contiguous float32 [rows, 2, T]")
+        n = ctypes.c_size_t()
+        lib = load()
+        check(lib.grafx_mrstft_workspace_bytes(rows, T, ctypes.byref(n)))
+        ws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=Y.device)
+        loss = torch.empty((), dtype=torch.float32, device=Y.device)
+        check(lib.grafx_mrstft_loss(rows, T, Y.data_ptr(), target.data_ptr(), loss.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream(Y.device)))
+        ctx.save_for_backward(Y, target)
+        ctx.ws = ws
+        return loss
+
+    @staticmethod
+    def backward(ctx, gL):
+        Y, target = ctx.saved_tensors
+        rows, T = int(Y.shape[0]), int(Y.shape[-1])
+        g = gL.detach().to(dtype=torch.float32).contiguous()
+        dY = torch.empty_like(Y)
+        check(load().grafx_mrstft_backward(rows, T, Y.data_ptr(), target.data_ptr(),
+                                           g.data_ptr(), dY.data_ptr(), ctx.ws.data_ptr(),
+                                           ctx.ws.numel(), _stream(Y.device)))
+        return dY, None
+
+
+def mrstft_loss(Y: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """Multi-resolution STFT loss (512/1024/2048) between [rows, 2, T] signals."""
+    return _MRSTFT.apply(Y.contiguous(), target.contiguous())

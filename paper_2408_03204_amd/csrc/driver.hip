@@ -1,0 +1,290 @@
+// Render drivers: the host step loops of the batched render (paper Algorithm 1, main loop) and
+// of its adjoint, the plan upload and the workspace layout. Every argument is checked before the
+// first launch; the drivers only enqueue kernels on the caller's stream.
+#include <cstring>
+
+#include "device_common.h"
+#include "grafx_internal.h"
+#include "kernels.h"
+
+namespace grafx {
+namespace {
+
+// Workspace layout (byte offsets, 256-byte aligned sections). The forward part is kept by the
+// render for the adjoint: EQ filters, compressor carries, delay taps.
+struct WsLayout {
+  size_t eq_h, eq_H, comp_agg, comp_carry, delay_taps, delay_offs;
+  size_t fwd_end;
+  size_t part_gp, part_im, part_tanh, comp_ragg, comp_rcarry, comp_part, eq_C, eq_s, delay_part;
+  size_t total;
+};
+
+WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
+  WsLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  const size_t n_eq = h->type_count[GRAFX_EQ], n_comp = h->type_count[GRAFX_COMPRESSOR];
+  const size_t n_del = h->type_count[GRAFX_DELAY];
+  const size_t chunks = comp_chunks(T);
+  L.eq_h = take(n_eq * 1024 * sizeof(double));
+  L.eq_H = take(n_eq * kEqFFT * sizeof(float));
+  L.comp_agg = take(n_comp * chunks * sizeof(double));
+  L.comp_carry = take(n_comp * chunks * sizeof(double));
+  L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
+  L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
+  L.fwd_end = off;
+  if (with_bwd) {
+    const size_t tiles = pointwise_tiles(T);
+    L.part_gp = take(h->type_count[GRAFX_GAIN_PAN] * tiles * 2 * sizeof(double));
+    L.part_im = take(h->type_count[GRAFX_IMAGER] * tiles * sizeof(double));
+    L.part_tanh = take(h->type_count[GRAFX_TANH] * tiles * sizeof(double));
+    L.comp_ragg = take(n_comp * chunks * sizeof(double));
+    L.comp_rcarry = take(n_comp * chunks * sizeof(double));
+    L.comp_part = take(n_comp * chunks * 4 * sizeof(double));
+    L.eq_C = take(n_eq * eq_groups(T) * kEqFFT * sizeof(float2));
+    L.eq_s = take(n_eq * 1024 * sizeof(double));
+    L.delay_part = take(n_del * delay_groups(T) * kDelayCoef * sizeof(float));
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename P>
+P* at(void* ws, size_t off) {
+  return reinterpret_cast<P*>(static_cast<char*>(ws) + off);
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+GraphView make_view(const grafx_schedule_t* h, const void* dev_plan, int64_t T, const float* S,
+                    const float* U) {
+  const int32_t* plan = static_cast<const int32_t*>(dev_plan);
+  GraphView g{};
+  g.in_ptr = plan + h->layout.in_ptr;
+  g.in_src = plan + h->layout.in_src;
+  g.out_ptr = plan + h->layout.out_ptr;
+  g.out_dst = plan + h->layout.out_dst;
+  g.param_row = plan + h->layout.param_row;
+  g.S = S;
+  g.U = U;
+  g.T = T;
+  g.K = h->K;
+  g.out_begin = h->step_ptr[h->N];
+  return g;
+}
+
+grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64_t T,
+                          const float* S, const float* const* P, const float* U, void* ws,
+                          size_t ws_bytes, bool with_bwd) {
+  if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
+  if (!dev_plan) return fail(GRAFX_E_ARG, "plan is NULL");
+  if (T < 1) return fail(GRAFX_E_SHAPE, "T must be >= 1");
+  if ((int64_t)h->V * 2 * T > ((int64_t)1 << 46)) return fail(GRAFX_E_SHAPE, "signal buffer too large");
+  if (!U) return fail(GRAFX_E_ARG, "U is NULL");
+  if (h->K > 0 && !S) return fail(GRAFX_E_ARG, "S is NULL but the graph has input nodes");
+  if (!aligned(dev_plan, 256)) return fail(GRAFX_E_SHAPE, "plan must be 256-byte aligned");
+  if (!aligned(U, 16) || (S && !aligned(S, 16)))
+    return fail(GRAFX_E_SHAPE, "signal buffers must be 16-byte aligned");
+  for (int t = 0; t < kNumTypes; ++t)
+    if (kParamCount[t] > 0 && h->type_count[t] > 0 && (!P || !P[t]))
+      return fail(GRAFX_E_SHAPE, "missing parameter tensor for node type " + std::to_string(t));
+  const WsLayout L = ws_layout(h, T, with_bwd);
+  if (L.total > 0 && (!ws || ws_bytes < L.total))
+    return fail(GRAFX_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
+                                       " bytes, got " + std::to_string(ws_bytes));
+  if (ws && !aligned(ws, 256)) return fail(GRAFX_E_SHAPE, "workspace must be 256-byte aligned");
+  return GRAFX_OK;
+}
+
+grafx_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return GRAFX_OK;
+  return fail(GRAFX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+}  // namespace grafx
+
+using namespace grafx;
+
+extern "C" {
+
+grafx_status grafx_plan_upload(const grafx_schedule_t* h, void* dev_plan, size_t bytes,
+                               hipStream_t stream) {
+  clear_error();
+  if (!h || !dev_plan) return fail(GRAFX_E_ARG, "NULL argument");
+  const size_t need = h->layout.total * sizeof(int32_t);
+  if (bytes < need) return fail(GRAFX_E_WORKSPACE, "plan buffer too small");
+  if (!aligned(dev_plan, 256)) return fail(GRAFX_E_SHAPE, "plan must be 256-byte aligned");
+  if (need == 0) return GRAFX_OK;
+  return hip_status(hipMemcpyAsync(dev_plan, h->plan.data(), need, hipMemcpyHostToDevice, stream),
+                    "plan upload");
+}
+
+grafx_status grafx_workspace_bytes(const grafx_schedule_t* h, int64_t T, int32_t with_backward,
+                                   size_t* bytes) {
+  clear_error();
+  if (!h || !bytes) return fail(GRAFX_E_ARG, "NULL argument");
+  if (T < 1) return fail(GRAFX_E_SHAPE, "T must be >= 1");
+  *bytes = ws_layout(h, T, with_backward != 0).total;
+  return GRAFX_OK;
+}
+
+grafx_status grafx_render(const grafx_schedule_t* h, const void* dev_plan, int64_t T,
+                          const float* S, const float* const* P, float* U, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  grafx_status st = check_common(h, dev_plan, T, S, P, U, ws, ws_bytes, false);
+  if (st != GRAFX_OK) return st;
+  const WsLayout L = ws_layout(h, T, false);
+  const GraphView g = make_view(h, dev_plan, T, S, U);
+  auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
+  hipError_t e = hipSuccess;
+  // per-render parameter preprocessing
+  if (h->type_count[GRAFX_EQ] > 0)
+    e = launch_eq_design(par(GRAFX_EQ), h->type_count[GRAFX_EQ], at<double>(ws, L.eq_h),
+                         at<float>(ws, L.eq_H), stream);
+  if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
+    e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
+                            at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
+  for (int n = 1; n <= h->N && e == hipSuccess; ++n) {
+    const int t = h->step_type[n];
+    const int b = h->step_ptr[n], cnt = h->step_ptr[n + 1] - b;
+    if (cnt == 0) continue;
+    switch (t) {
+      case GRAFX_MIX:
+      case GRAFX_OUT:
+      case GRAFX_GAIN_PAN:
+      case GRAFX_IMAGER:
+      case GRAFX_TANH:
+        e = launch_pointwise_fwd(t, g, U, par(t), b, cnt, stream);
+        break;
+      case GRAFX_EQ:
+        e = launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
+        break;
+      case GRAFX_COMPRESSOR:
+        e = launch_comp_fwd(g, U, par(t), b, cnt, at<double>(ws, L.comp_agg),
+                            at<double>(ws, L.comp_carry), stream);
+        break;
+      case GRAFX_DELAY:
+        e = launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
+                             cnt, stream);
+        break;
+      default:
+        e = hipErrorInvalidValue;
+    }
+  }
+  return hip_status(e, "render launch");
+}
+
+grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_plan, int64_t T,
+                                   const float* S, const float* const* P, const float* U,
+                                   const float* dY, float* dU, float* dS, float* const* dP,
+                                   void* ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  grafx_status st = check_common(h, dev_plan, T, S, P, U, ws, ws_bytes, true);
+  if (st != GRAFX_OK) return st;
+  if (!dY || !dU) return fail(GRAFX_E_ARG, "dY or dU is NULL");
+  if (!aligned(dY, 16) || !aligned(dU, 16) || (dS && !aligned(dS, 16)))
+    return fail(GRAFX_E_SHAPE, "adjoint buffers must be 16-byte aligned");
+  const WsLayout L = ws_layout(h, T, true);
+  GraphView g = make_view(h, dev_plan, T, S, U);
+  g.dY = dY;
+  g.dU = dU;
+  auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
+  auto dpar = [&](int t) -> float* { return dP ? dP[t] : nullptr; };
+  hipError_t e = hipSuccess;
+  for (int n = h->N - 1; n >= 1 && e == hipSuccess; --n) {
+    const int t = h->step_type[n];
+    const int b = h->step_ptr[n], cnt = h->step_ptr[n + 1] - b;
+    if (cnt == 0) continue;
+    switch (t) {
+      case GRAFX_MIX:
+        e = launch_pointwise_bwd(t, g, dU, nullptr, b, cnt, nullptr, stream);
+        break;
+      case GRAFX_GAIN_PAN:
+        e = launch_pointwise_bwd(t, g, dU, par(t), b, cnt, at<double>(ws, L.part_gp), stream);
+        break;
+      case GRAFX_IMAGER:
+        e = launch_pointwise_bwd(t, g, dU, par(t), b, cnt, at<double>(ws, L.part_im), stream);
+        break;
+      case GRAFX_TANH:
+        e = launch_pointwise_bwd(t, g, dU, par(t), b, cnt, at<double>(ws, L.part_tanh), stream);
+        break;
+      case GRAFX_EQ:
+        e = launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float2>(ws, L.eq_C), stream);
+        break;
+      case GRAFX_COMPRESSOR:
+        e = launch_comp_bwd(g, dU, par(t), b, cnt, at<double>(ws, L.comp_carry),
+                            at<double>(ws, L.comp_ragg), at<double>(ws, L.comp_rcarry),
+                            at<double>(ws, L.comp_part), stream);
+        break;
+      case GRAFX_DELAY:
+        e = launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
+                             b, cnt, at<float>(ws, L.delay_part), stream);
+        break;
+      default:
+        e = hipErrorInvalidValue;
+    }
+  }
+  if (e == hipSuccess && dS && h->K > 0)  // adjoint of the input step: sum over output edges
+    e = launch_pointwise_bwd(GRAFX_IN, g, dS, nullptr, 0, h->K, nullptr, stream);
+  const int tiles = pointwise_tiles(T), chunks = comp_chunks(T);
+  if (e == hipSuccess && dpar(GRAFX_GAIN_PAN))
+    e = launch_reduce_partials(at<double>(ws, L.part_gp), h->type_count[GRAFX_GAIN_PAN], tiles, 2,
+                               dpar(GRAFX_GAIN_PAN), stream);
+  if (e == hipSuccess && dpar(GRAFX_IMAGER))
+    e = launch_reduce_partials(at<double>(ws, L.part_im), h->type_count[GRAFX_IMAGER], tiles, 1,
+                               dpar(GRAFX_IMAGER), stream);
+  if (e == hipSuccess && dpar(GRAFX_TANH))
+    e = launch_reduce_partials(at<double>(ws, L.part_tanh), h->type_count[GRAFX_TANH], tiles, 1,
+                               dpar(GRAFX_TANH), stream);
+  if (e == hipSuccess && dpar(GRAFX_COMPRESSOR))
+    e = launch_reduce_partials(at<double>(ws, L.comp_part), h->type_count[GRAFX_COMPRESSOR],
+                               chunks, 4, dpar(GRAFX_COMPRESSOR), stream);
+  if (e == hipSuccess && dpar(GRAFX_EQ))
+    e = launch_eq_grad(par(GRAFX_EQ), at<float2>(ws, L.eq_C), h->type_count[GRAFX_EQ],
+                       eq_groups(T), at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
+  if (e == hipSuccess && dpar(GRAFX_DELAY))
+    e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
+                          h->type_count[GRAFX_DELAY], delay_groups(T), dpar(GRAFX_DELAY), stream);
+  return hip_status(e, "render_backward launch");
+}
+
+grafx_status grafx_mrstft_workspace_bytes(int32_t rows, int64_t T, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(GRAFX_E_ARG, "NULL argument");
+  if (rows < 1 || T < 1) return fail(GRAFX_E_SHAPE, "rows and T must be >= 1");
+  *bytes = mrstft_ws_bytes(rows, T);
+  return GRAFX_OK;
+}
+
+static grafx_status check_mrstft(int32_t rows, int64_t T, const float* Y, const float* tgt,
+                                 void* ws, size_t ws_bytes) {
+  if (rows < 1 || T < 1) return fail(GRAFX_E_SHAPE, "rows and T must be >= 1");
+  if (!Y || !tgt || !ws) return fail(GRAFX_E_ARG, "NULL argument");
+  if (ws_bytes < mrstft_ws_bytes(rows, T)) return fail(GRAFX_E_WORKSPACE, "workspace too small");
+  if (!aligned(ws, 256)) return fail(GRAFX_E_SHAPE, "workspace must be 256-byte aligned");
+  return GRAFX_OK;
+}
+
+grafx_status grafx_mrstft_loss(int32_t rows, int64_t T, const float* Y, const float* target,
+                               float* loss, void* ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  grafx_status st = check_mrstft(rows, T, Y, target, ws, ws_bytes);
+  if (st != GRAFX_OK) return st;
+  if (!loss) return fail(GRAFX_E_ARG, "loss is NULL");
+  return hip_status(launch_mrstft_loss(rows, T, Y, target, loss, ws, stream), "mrstft launch");
+}
+
+grafx_status grafx_mrstft_backward(int32_t rows, int64_t T, const float* Y, const float* target,
+                                   const float* dloss, float* dY, void* ws, size_t ws_bytes,
+                                   hipStream_t stream) {
+  clear_error();
+  grafx_status st = check_mrstft(rows, T, Y, target, ws, ws_bytes);
+  if (st != GRAFX_OK) return st;
+  if (!dloss || !dY) return fail(GRAFX_E_ARG, "dloss or dY is NULL");
+  return hip_status(launch_mrstft_bwd(rows, T, Y, target, dloss, dY, ws, stream),
+                    "mrstft_backward launch");
+}
+
+}  // extern "C"

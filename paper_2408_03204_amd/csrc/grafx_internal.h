@@ -1,0 +1,46 @@
+// Internal definitions shared by the host scheduler, the render drivers and the kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "grafx.h"
+
+namespace grafx {
+
+constexpr int kNumTypes = GRAFX_NUM_TYPES;
+constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1};
+
+// Thread-local error message, set by every failing entry point.
+grafx_status fail(grafx_status code, const std::string& msg);
+void clear_error();
+
+// Round up to a multiple of `a` (a power of two).
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) & ~(a - 1); }
+
+// Device plan layout: int32 sections, each starting on a 64-element (256-byte) boundary.
+struct PlanLayout {
+  size_t in_ptr, in_src, out_ptr, out_dst, param_row;  // element offsets
+  size_t total;                                          // elements
+};
+
+}  // namespace grafx
+
+// The schedule handle (host memory only; immutable after creation).
+struct grafx_schedule_t {
+  int32_t V = 0, E = 0, N = 0, K = 0, n_out = 0;
+  int32_t type_count[grafx::kNumTypes] = {0};
+  std::vector<int32_t> node_type;  // original order
+  std::vector<int32_t> step_type;  // [N+1]
+  std::vector<int32_t> step_ptr;   // [N+2]
+  std::vector<int32_t> perm;       // [V]
+  std::vector<int32_t> in_ptr;     // [V+1]
+  std::vector<int32_t> in_src;     // [E]
+  std::vector<int32_t> out_ptr;    // [V+1]
+  std::vector<int32_t> out_dst;    // [E]
+  std::vector<int32_t> param_row;  // [V]
+  grafx::PlanLayout layout{};
+  std::vector<int32_t> plan;       // packed host image of the device plan
+};

@@ -1,0 +1,250 @@
+// Multitap delay (paper Sec. 3 "Multitap delay", Eq. 14), limited to five 100 ms slots
+// (<= 500 ms) per channel: y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j].
+//
+// Design (once per render): the integer delay of slot m is (m * 4410) plus
+// rint(-arg(z) * 4410 / 2 pi) mod 4410, decided in float32; each slot's 39-tap zero-phase FIR is
+// built from its 20 log-magnitudes like the EQ (N = 39, symmetric Hann), in double.
+// Filtering: one block per 2048 outputs of one node; for each (channel, slot) the 2086-sample
+// input window is staged in LDS and every thread forms 8 consecutive outputs from registers.
+// Adjoint: the input adjoint is the correlation with the same taps (a separate launch), and the
+// tap gradient c-bar_{c,m}[j] = sum_t ybar_c[t] u_c[t - d - j] is accumulated per block over a
+// fixed group of tiles, reduced in a fixed order and mapped back to the log-magnitudes through
+// the design. The delay times themselves are not differentiated (their phasor gradients are 0).
+#include "device_common.h"
+#include "grafx_internal.h"
+#include "kernels.h"
+
+namespace grafx {
+namespace {
+
+constexpr int kHop = 2048;
+constexpr int kHalf = 19;                 // taps j = -19..19
+constexpr int kWin = kHop + 2 * kHalf;    // 2086
+constexpr int kPer = kHop / kBlock;       // 8 outputs per thread
+constexpr int kRow = 2 * kDelayTaps * 22; // 220 parameters per node
+
+__global__ __launch_bounds__(kBlock) void delay_design_kernel(const float* P, float* taps,
+                                                              int32_t* offs) {
+  const int node = blockIdx.x;
+  const float* p = P + (int64_t)node * kRow;
+  for (int i = threadIdx.x; i < kDelayCoef; i += kBlock) {
+    const int cm = i / kDelayFir, j = i % kDelayFir - kHalf;  // cm = c * 5 + m
+    const float* q = p + cm * 22;
+    double acc = exp((double)q[2]);
+    for (int k = 1; k <= kHalf; ++k) acc += 2.0 * exp((double)q[2 + k]) * cospi(2.0 * k * j / 39.0);
+    const double h0 = acc / 39.0;
+    const double win = 0.5 + 0.5 * cospi((double)j / kHalf);
+    taps[(int64_t)node * kDelayCoef + i] = (float)(win * h0);
+  }
+  if (threadIdx.x < 2 * kDelayTaps) {
+    const int cm = threadIdx.x, m = cm % kDelayTaps;
+    const float* q = p + cm * 22;
+    const float kScale = (float)(4410.0 / (2.0 * 3.14159265358979323846));
+    const float ph = atan2f(q[1], q[0]);
+    const int r = (int)rintf(-ph * kScale);
+    const int d = ((r % kDelaySlot) + kDelaySlot) % kDelaySlot;
+    offs[(int64_t)node * 2 * kDelayTaps + cm] = m * kDelaySlot + d;
+  }
+}
+
+// Stage x[base .. base + kWin) of one channel of a node's gather-sum (in: input edges over U/S,
+// adj: output edges over dU/dY) into LDS, zero outside [0, T).
+template <bool ADJ>
+__device__ __forceinline__ void stage_window(const GraphView& g, int node, int c, int64_t base,
+                                             int len, float* w) {
+  const int64_t T = g.T;
+  const int e0 = ADJ ? g.out_ptr[node] : g.in_ptr[node];
+  const int e1 = ADJ ? g.out_ptr[node + 1] : g.in_ptr[node + 1];
+  for (int idx = threadIdx.x; idx < len; idx += kBlock) {
+    const int64_t t = base + idx;
+    float s = 0.f;
+    if (t >= 0 && t < T)
+      for (int e = e0; e < e1; ++e) {
+        const float* row = ADJ ? adj_row(g, g.out_dst[e]) : out_row(g, g.in_src[e]);
+        s += row[(int64_t)c * T + t];
+      }
+    w[idx] = s;
+  }
+}
+
+// out[o] += sum_{j} c[j] w[o + 19 - j] (forward: convolution; window starts at t0 - d - 19) or
+// out[o] += sum_{j} c[j] w[o + 19 + j] (adjoint: correlation; window starts at t0 + d - 19).
+template <bool ADJ>
+__device__ __forceinline__ void apply_taps(const float* w, const float* c, float* acc) {
+  const int o0 = kPer * threadIdx.x;
+  float x[kPer + 2 * kHalf];
+#pragma unroll
+  for (int i = 0; i < kPer + 2 * kHalf; ++i) x[i] = w[o0 + i];
+#pragma unroll
+  for (int jj = 0; jj < kDelayFir; ++jj) {
+    const float cj = c[jj];  // tap j = jj - 19
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) acc[i] += cj * x[ADJ ? i + jj : i + 2 * kHalf - jj];
+  }
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* out,
+                                                            const float* taps,
+                                                            const int32_t* offs, int node_begin,
+                                                            int tiles) {
+  __shared__ float w[kWin];
+  __shared__ float ys[2][kHop];
+  const int tile = blockIdx.x, node = node_begin + blockIdx.y;
+  const int slot = g.param_row[node];
+  const int64_t T = g.T, t0 = (int64_t)tile * kHop;
+  const float* cn = taps + (int64_t)slot * kDelayCoef;
+  for (int c = 0; c < 2; ++c) {
+    float acc[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) acc[i] = 0.f;
+    for (int m = 0; m < kDelayTaps; ++m) {
+      const int d = offs[(int64_t)slot * 2 * kDelayTaps + c * kDelayTaps + m];
+      const int64_t base = ADJ ? t0 + d - kHalf : t0 - d - kHalf;
+      __syncthreads();
+      stage_window<ADJ>(g, node, c, base, kWin, w);
+      __syncthreads();
+      apply_taps<ADJ>(w, cn + (c * kDelayTaps + m) * kDelayFir, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) ys[c][kPer * threadIdx.x + i] = acc[i];
+  }
+  __syncthreads();
+  float* y = out + (int64_t)node * 2 * T;
+  for (int idx = threadIdx.x; idx < kHop; idx += kBlock) {
+    const int64_t t = t0 + idx;
+    if (t < T) {
+      y[t] = ys[0][idx];
+      y[T + t] = ys[1][idx];
+    }
+  }
+  (void)tiles;
+}
+
+// Tap gradients: part[slot][group][c*5+m][j] = sum over the group's tiles of
+// sum_t ybar_c[t] u_c[t - d - j].
+__global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, const int32_t* offs,
+                                                               int node_begin, int tiles,
+                                                               int groups, int tpg,
+                                                               float* part) {
+  __shared__ float w[kWin];
+  __shared__ float yb[kHop];
+  __shared__ float red[4][kDelayFir];
+  const int group = blockIdx.x, node = node_begin + blockIdx.y;
+  const int slot = g.param_row[node];
+  const int tile_end = min(tiles, (group + 1) * tpg);
+  for (int cm = 0; cm < 2 * kDelayTaps; ++cm) {
+    const int c = cm / kDelayTaps;
+    const int d = offs[(int64_t)slot * 2 * kDelayTaps + cm];
+    float acc[kDelayFir];
+#pragma unroll
+    for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] = 0.f;
+    for (int tile = group * tpg; tile < tile_end; ++tile) {
+      const int64_t t0 = (int64_t)tile * kHop;
+      __syncthreads();
+      stage_window<false>(g, node, c, t0 - d - kHalf, kWin, w);
+      stage_window<true>(g, node, c, t0, kHop, yb);
+      __syncthreads();
+      const int o0 = kPer * threadIdx.x;
+      float x[kPer + 2 * kHalf];
+#pragma unroll
+      for (int i = 0; i < kPer + 2 * kHalf; ++i) x[i] = w[o0 + i];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const float yv = yb[o0 + i];
+#pragma unroll
+        for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] += yv * x[i + 2 * kHalf - jj];
+      }
+    }
+    // block reduction of the 39 partial sums (fixed order)
+#pragma unroll
+    for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] = wave_sum(acc[jj]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+      for (int jj = 0; jj < kDelayFir; ++jj) red[threadIdx.x >> 6][jj] = acc[jj];
+    __syncthreads();
+    if (threadIdx.x < kDelayFir) {
+      const int jj = threadIdx.x;
+      part[(((int64_t)slot * groups + group) * 2 * kDelayTaps + cm) * kDelayFir + jj] =
+          red[0][jj] + red[1][jj] + red[2][jj] + red[3][jj];
+    }
+  }
+}
+
+// Sum tap-gradient partials over groups and map them to the log-magnitudes:
+// dL/dlogmag_k = A_k (kappa_k / 39) sum_j cbar[j] v[j] cos(2 pi k j / 39).
+__global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, const float* part,
+                                                            int groups, float* dP) {
+  __shared__ double cb[kDelayCoef];
+  const int slot = blockIdx.x;
+  for (int i = threadIdx.x; i < kDelayCoef; i += kBlock) {
+    double s = 0.0;
+    for (int gi = 0; gi < groups; ++gi) s += part[((int64_t)slot * groups + gi) * kDelayCoef + i];
+    const int j = i % kDelayFir - kHalf;
+    cb[i] = s * (0.5 + 0.5 * cospi((double)j / kHalf));
+  }
+  __syncthreads();
+  const float* p = P + (int64_t)slot * kRow;
+  float* d = dP + (int64_t)slot * kRow;
+  for (int i = threadIdx.x; i < kRow; i += kBlock) {
+    const int cm = i / 22, q = i % 22;
+    if (q < 2) {
+      d[i] = 0.f;
+      continue;
+    }
+    const int k = q - 2;
+    double acc = 0.0;
+    for (int jj = 0; jj < kDelayFir; ++jj) acc += cb[cm * kDelayFir + jj] * cospi(2.0 * k * (jj - kHalf) / 39.0);
+    const double kappa = k == 0 ? 1.0 : 2.0;
+    d[i] = (float)(exp((double)p[i]) * kappa / 39.0 * acc);
+  }
+}
+
+}  // namespace
+
+int delay_tiles(int64_t T) { return (int)((T + kHop - 1) / kHop); }
+
+static int delay_tpg(int64_t T) {
+  int tpg = delay_tiles(T) / 32;
+  return tpg < 1 ? 1 : (tpg > 8 ? 8 : tpg);
+}
+
+int delay_groups(int64_t T) {
+  const int tpg = delay_tpg(T);
+  return (delay_tiles(T) + tpg - 1) / tpg;
+}
+
+hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  delay_design_kernel<<<n, kBlock, 0, s>>>(P, taps, offs);
+  return hipGetLastError();
+}
+
+hipError_t launch_delay_fwd(const GraphView& g, float* U, const float* taps, const int32_t* offs,
+                            int node_begin, int n_nodes, hipStream_t s) {
+  const int tiles = delay_tiles(g.T);
+  delay_conv_kernel<false><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, U, taps, offs, node_begin,
+                                                                   tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
+                            const int32_t* offs, int node_begin, int n_nodes, float* part,
+                            hipStream_t s) {
+  const int tiles = delay_tiles(g.T);
+  delay_conv_kernel<true><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, dU, taps, offs, node_begin,
+                                                                  tiles);
+  const int groups = delay_groups(g.T), tpg = delay_tpg(g.T);
+  delay_tapgrad_kernel<<<dim3(groups, n_nodes), kBlock, 0, s>>>(g, offs, node_begin, tiles,
+                                                                groups, tpg, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_delay_grad(const float* P, const float* part, int n, int groups, float* dP,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  delay_grad_kernel<<<n, kBlock, 0, s>>>(P, part, groups, dP);
+  return hipGetLastError();
+}
+
+}  // namespace grafx

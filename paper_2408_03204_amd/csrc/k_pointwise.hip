@@ -1,0 +1,281 @@
+// Fused gather-sum -> pointwise processor -> store, for one schedule step (paper Algorithm 1:
+// Gather, Aggregate, Process, Store of one iteration), and the matching adjoint step.
+//
+// Types: mix / out (identity, Eq. 1b only), gain_pan (Eq. 2), imager (Eq. 3), tanh distortion.
+// One block of 256 threads covers 1024 samples of one node (both channels); blockIdx.y picks the
+// node inside the step. With T % 4 == 0 every row is 16-byte aligned and each thread moves one
+// float4 per channel and input; otherwise each thread moves 4 scalars at a 256-sample stride.
+// Inputs are summed in original edge order, so a node's arithmetic does not depend on the step
+// it was batched into.
+#include "device_common.h"
+#include "grafx_internal.h"
+#include "kernels.h"
+
+namespace grafx {
+namespace {
+
+constexpr int kTile = 1024;
+
+struct Gains {
+  float e0, e1;
+};
+
+template <int TYPE>
+__device__ __forceinline__ Gains load_gains(const float* P, int row) {
+  Gains g{1.f, 1.f};
+  if constexpr (TYPE == GRAFX_GAIN_PAN) {
+    g.e0 = expf(P[2 * row]);
+    g.e1 = expf(P[2 * row + 1]);
+  } else if constexpr (TYPE == GRAFX_IMAGER || TYPE == GRAFX_TANH) {
+    g.e0 = expf(P[row]);
+  }
+  return g;
+}
+
+template <int TYPE>
+__device__ __forceinline__ void fwd_op(float& l, float& r, Gains k) {
+  if constexpr (TYPE == GRAFX_GAIN_PAN) {
+    l *= k.e0;
+    r *= k.e1;
+  } else if constexpr (TYPE == GRAFX_IMAGER) {
+    const float m = l + r, s = k.e0 * (l - r);
+    l = 0.5f * (m + s);
+    r = 0.5f * (m - s);
+  } else if constexpr (TYPE == GRAFX_TANH) {
+    l = tanhf(k.e0 * l);
+    r = tanhf(k.e0 * r);
+  }
+}
+
+template <int TYPE, bool V4>
+__global__ __launch_bounds__(kBlock) void pointwise_fwd_kernel(GraphView g, float* U,
+                                                               const float* P, int node_begin) {
+  const int node = node_begin + blockIdx.y;
+  const int64_t T = g.T;
+  const Gains k = load_gains<TYPE>(P, g.param_row[node]);
+  const int e0 = g.in_ptr[node], e1 = g.in_ptr[node + 1];
+  float* y = U + (int64_t)node * 2 * T;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  if constexpr (V4) {
+    const int64_t t = base + 4 * threadIdx.x;
+    if (t >= T) return;
+    float4 l = make_float4(0.f, 0.f, 0.f, 0.f), r = l;
+    for (int e = e0; e < e1; ++e) {
+      const float* row = out_row(g, g.in_src[e]);
+      const float4 a = *reinterpret_cast<const float4*>(row + t);
+      const float4 b = *reinterpret_cast<const float4*>(row + T + t);
+      l.x += a.x; l.y += a.y; l.z += a.z; l.w += a.w;
+      r.x += b.x; r.y += b.y; r.z += b.z; r.w += b.w;
+    }
+    fwd_op<TYPE>(l.x, r.x, k);
+    fwd_op<TYPE>(l.y, r.y, k);
+    fwd_op<TYPE>(l.z, r.z, k);
+    fwd_op<TYPE>(l.w, r.w, k);
+    *reinterpret_cast<float4*>(y + t) = l;
+    *reinterpret_cast<float4*>(y + T + t) = r;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t t = base + threadIdx.x + q * kBlock;
+      if (t >= T) break;
+      float l = 0.f, r = 0.f;
+      for (int e = e0; e < e1; ++e) {
+        const float* row = out_row(g, g.in_src[e]);
+        l += row[t];
+        r += row[T + t];
+      }
+      fwd_op<TYPE>(l, r, k);
+      y[t] = l;
+      y[T + t] = r;
+    }
+  }
+}
+
+// Adjoint of one pointwise step. `dst` receives the input adjoint (dU, or dS for the input step,
+// whose rows are indexed the same way). Parameter-gradient partials (one per block and
+// parameter, double) go to part[(slot * tiles + tile) * NP + j].
+template <bool V4>
+__device__ __forceinline__ void load_n(const float* p, float* out) {
+  if constexpr (V4) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  } else {
+    out[0] = *p;
+  }
+}
+
+template <bool V4>
+__device__ __forceinline__ void store_n(float* p, const float* v) {
+  if constexpr (V4) *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  else *p = v[0];
+}
+
+template <int TYPE>
+struct AdjOp {
+  static constexpr int NP = TYPE == GRAFX_GAIN_PAN ? 2 : (TYPE == GRAFX_IMAGER || TYPE == GRAFX_TANH ? 1 : 0);
+};
+
+template <int TYPE>
+__device__ __forceinline__ void adj_op(float yl, float yr, float ul_in, float ur_in, float& gl,
+                                       float& gr, Gains k, float* acc) {
+  // yl, yr: node output (gain_pan, imager); ul_in, ur_in: node input (tanh); gl, gr: output
+  // adjoint in, input adjoint out
+  if constexpr (TYPE == GRAFX_GAIN_PAN) {
+    acc[0] += gl * yl;
+    acc[1] += gr * yr;
+    gl *= k.e0;
+    gr *= k.e1;
+  } else if constexpr (TYPE == GRAFX_IMAGER) {
+    const float mb = 0.5f * (gl + gr), sb = 0.5f * (gl - gr);
+    acc[0] += sb * (yl - yr);
+    gl = mb + k.e0 * sb;
+    gr = mb - k.e0 * sb;
+  } else if constexpr (TYPE == GRAFX_TANH) {
+    const float al = tanhf(k.e0 * ul_in), ar = tanhf(k.e0 * ur_in);
+    gl = gl * k.e0 * (1.f - al * al);
+    gr = gr * k.e0 * (1.f - ar * ar);
+    acc[0] += gl * ul_in + gr * ur_in;
+  }
+}
+
+template <int TYPE, bool V4>
+__global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, float* dst,
+                                                               const float* P, int node_begin,
+                                                               double* part, int tiles) {
+  constexpr int NP = AdjOp<TYPE>::NP;
+  const int node = node_begin + blockIdx.y;
+  const int64_t T = g.T;
+  const int slot = g.param_row[node];
+  const Gains k = load_gains<TYPE>(P, slot);
+  const int o0 = g.out_ptr[node], o1 = g.out_ptr[node + 1];
+  const int i0 = g.in_ptr[node], i1 = g.in_ptr[node + 1];
+  const float* yrow = g.U + (int64_t)node * 2 * T;  // used by gain_pan / imager only
+  float* d = dst + (int64_t)node * 2 * T;
+  float acc[NP > 0 ? NP : 1] = {0.f};
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  constexpr int NV = V4 ? 4 : 1;
+  const int64_t t_first = V4 ? base + 4 * threadIdx.x : base + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < (V4 ? 1 : 4); ++q) {
+    const int64_t t = V4 ? t_first : t_first + q * kBlock;
+    if (t >= T) break;
+    float gl[NV], gr[NV], yl[NV], yr[NV], ul[NV], ur[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gl[v] = gr[v] = yl[v] = yr[v] = ul[v] = ur[v] = 0.f;
+    for (int e = o0; e < o1; ++e) {
+      const float* row = adj_row(g, g.out_dst[e]);
+      float a[NV], b[NV];
+      load_n<V4>(row + t, a);
+      load_n<V4>(row + T + t, b);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        gl[v] += a[v];
+        gr[v] += b[v];
+      }
+    }
+    if constexpr (TYPE == GRAFX_GAIN_PAN || TYPE == GRAFX_IMAGER) {
+      load_n<V4>(yrow + t, yl);
+      load_n<V4>(yrow + T + t, yr);
+    }
+    if constexpr (TYPE == GRAFX_TANH) {
+      for (int e = i0; e < i1; ++e) {
+        const float* row = out_row(g, g.in_src[e]);
+        float a[NV], b[NV];
+        load_n<V4>(row + t, a);
+        load_n<V4>(row + T + t, b);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          ul[v] += a[v];
+          ur[v] += b[v];
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) adj_op<TYPE>(yl[v], yr[v], ul[v], ur[v], gl[v], gr[v], k, acc);
+    store_n<V4>(d + t, gl);
+    store_n<V4>(d + T + t, gr);
+  }
+  (void)i0;
+  (void)i1;
+  if constexpr (NP > 0) {
+    __shared__ double red[4];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const double s = block_sum<double>((double)acc[j], red);
+      if (threadIdx.x == 0) part[((int64_t)slot * tiles + blockIdx.x) * NP + j] = s;
+    }
+  }
+}
+
+// dP[slot][j] = sum over tiles of part[slot][tile][j], fixed order.
+__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const double* part, int tiles,
+                                                                 int np, float* dP) {
+  __shared__ double red[4];
+  const int slot = blockIdx.x;
+  for (int j = 0; j < np; ++j) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < tiles; i += kBlock) s += part[((int64_t)slot * tiles + i) * np + j];
+    s = block_sum<double>(s, red);
+    if (threadIdx.x == 0) dP[(int64_t)slot * np + j] = (float)s;
+  }
+}
+
+template <int TYPE>
+hipError_t launch_fwd_t(const GraphView& g, float* U, const float* P, int node_begin,
+                        int n_nodes, hipStream_t s) {
+  dim3 grid((unsigned)((g.T + kTile - 1) / kTile), (unsigned)n_nodes);
+  if (g.T % 4 == 0)
+    pointwise_fwd_kernel<TYPE, true><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
+  else
+    pointwise_fwd_kernel<TYPE, false><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
+  return hipGetLastError();
+}
+
+template <int TYPE>
+hipError_t launch_bwd_t(const GraphView& g, float* dst, const float* P, int node_begin,
+                        int n_nodes, double* part, hipStream_t s) {
+  const int tiles = (int)((g.T + kTile - 1) / kTile);
+  dim3 grid((unsigned)tiles, (unsigned)n_nodes);
+  if (g.T % 4 == 0)
+    pointwise_bwd_kernel<TYPE, true><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part, tiles);
+  else
+    pointwise_bwd_kernel<TYPE, false><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part, tiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int pointwise_tiles(int64_t T) { return (int)((T + kTile - 1) / kTile); }
+
+hipError_t launch_pointwise_fwd(int type, const GraphView& g, float* U, const float* P,
+                                int node_begin, int n_nodes, hipStream_t s) {
+  switch (type) {
+    case GRAFX_MIX:
+    case GRAFX_OUT: return launch_fwd_t<GRAFX_MIX>(g, U, P, node_begin, n_nodes, s);
+    case GRAFX_GAIN_PAN: return launch_fwd_t<GRAFX_GAIN_PAN>(g, U, P, node_begin, n_nodes, s);
+    case GRAFX_IMAGER: return launch_fwd_t<GRAFX_IMAGER>(g, U, P, node_begin, n_nodes, s);
+    case GRAFX_TANH: return launch_fwd_t<GRAFX_TANH>(g, U, P, node_begin, n_nodes, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pointwise_bwd(int type, const GraphView& g, float* dst, const float* P,
+                                int node_begin, int n_nodes, double* part, hipStream_t s) {
+  switch (type) {
+    case GRAFX_IN:
+    case GRAFX_MIX: return launch_bwd_t<GRAFX_MIX>(g, dst, P, node_begin, n_nodes, part, s);
+    case GRAFX_GAIN_PAN: return launch_bwd_t<GRAFX_GAIN_PAN>(g, dst, P, node_begin, n_nodes, part, s);
+    case GRAFX_IMAGER: return launch_bwd_t<GRAFX_IMAGER>(g, dst, P, node_begin, n_nodes, part, s);
+    case GRAFX_TANH: return launch_bwd_t<GRAFX_TANH>(g, dst, P, node_begin, n_nodes, part, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reduce_partials(const double* part, int n_slots, int tiles, int np, float* dP,
+                                  hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  reduce_partials_kernel<<<n_slots, kBlock, 0, s>>>(part, tiles, np, dP);
+  return hipGetLastError();
+}
+
+}  // namespace grafx

@@ -1,0 +1,72 @@
+// Host-side launchers of the device kernels (one translation unit per processor family).
+// Every launcher only enqueues work on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace grafx {
+
+struct GraphView;
+
+// ---- pointwise family: mix / out / gain_pan / imager / tanh (k_pointwise.hip) --------------
+int pointwise_tiles(int64_t T);  // blocks per node along time (partials per node)
+hipError_t launch_pointwise_fwd(int type, const GraphView& g, float* U, const float* P,
+                                int node_begin, int n_nodes, hipStream_t s);
+// dst: dU (or dS for the input step); part: double [slots][tiles][NP] (NP = 2, 1, 1, 0)
+hipError_t launch_pointwise_bwd(int type, const GraphView& g, float* dst, const float* P,
+                                int node_begin, int n_nodes, double* part, hipStream_t s);
+hipError_t launch_reduce_partials(const double* part, int n_slots, int tiles, int np, float* dP,
+                                  hipStream_t s);
+
+// ---- EQ (k_eq.hip) ---------------------------------------------------------------------------
+constexpr int kEqFFT = 4096;  // overlap-save FFT size
+constexpr int kEqHop = 2048;  // outputs per tile
+int eq_tiles(int64_t T);
+int eq_groups(int64_t T);      // tile groups per node in the adjoint (partial spectra per node)
+// h: double [n_eq][1024] (windowed FIR, taps n = 0..1023; even), H: float [n_eq][4096]
+hipError_t launch_eq_design(const float* P, int n_eq, double* h, float* H, hipStream_t s);
+hipError_t launch_eq_fwd(const GraphView& g, float* U, const float* H, int node_begin,
+                         int n_nodes, hipStream_t s);
+// Cpart: float2 [n_eq][groups][4096]
+hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node_begin,
+                         int n_nodes, float2* Cpart, hipStream_t s);
+// sbuf: double [n_eq][1024] scratch; dP: float [n_eq][1024]
+hipError_t launch_eq_grad(const float* P, const float2* Cpart, int n_eq, int groups,
+                          double* sbuf, float* dP, hipStream_t s);
+
+// ---- compressor (k_comp.hip) ---------------------------------------------------------------
+constexpr int kCompChunk = 2048;
+int comp_chunks(int64_t T);
+// agg, carry: double [n_comp][chunks]; part: double [n_comp][chunks][4]
+hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int node_begin,
+                           int n_nodes, double* agg, double* carry, hipStream_t s);
+hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
+                           int n_nodes, const double* carry, double* ragg, double* rcarry,
+                           double* part, hipStream_t s);
+
+// ---- delay (k_delay.hip) -------------------------------------------------------------------
+constexpr int kDelayTaps = 5, kDelayFir = 39, kDelaySlot = 4410;
+constexpr int kDelayCoef = 2 * kDelayTaps * kDelayFir;  // 390 per node
+int delay_tiles(int64_t T);
+int delay_groups(int64_t T);  // tile groups per node in the tap-gradient pass
+// taps: float [n][390]; offs: int32 [n][10]
+hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s);
+hipError_t launch_delay_fwd(const GraphView& g, float* U, const float* taps, const int32_t* offs,
+                            int node_begin, int n_nodes, hipStream_t s);
+// part: float [n][groups][390]
+hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
+                            const int32_t* offs, int node_begin, int n_nodes, float* part,
+                            hipStream_t s);
+hipError_t launch_delay_grad(const float* P, const float* part, int n, int groups, float* dP,
+                             hipStream_t s);
+
+// ---- MRSTFT loss (k_mrstft.hip) -------------------------------------------------------------
+size_t mrstft_ws_bytes(int rows, int64_t T);
+hipError_t launch_mrstft_loss(int rows, int64_t T, const float* Y, const float* tgt, float* loss,
+                              void* ws, hipStream_t s);
+hipError_t launch_mrstft_bwd(int rows, int64_t T, const float* Y, const float* tgt,
+                             const float* dloss, float* dY, void* ws, hipStream_t s);
+
+}  // namespace grafx

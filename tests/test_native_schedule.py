@@ -1,0 +1,108 @@
+"""The host C++ scheduler behind the C ABI against the oracle scheduler: every schedule array is
+bit-equal for all four methods (paper Sec. 2 "Type scheduling"; Algorithm 1 preprocessing), the
+error codes match, and the library exports every symbol its header declares. CPU only: these
+calls never touch a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import schedule as osch
+from paper_2408_03204_amd import EXPORTS, GrafxError, Schedule, load
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+METHODS = [(osch.ONE_BY_ONE, "one_by_one"), (osch.GREEDY, "greedy"), (osch.BEAM, "beam"),
+           (osch.OPTIMAL, "optimal")]
+
+
+def assert_same(g, method_code, name, beam=32, limit=1 << 20):
+    ref = osch.schedule(g.node_type, g.edges, method_code, beam_width=beam, state_limit=limit)
+    got = Schedule(g.node_type, g.edges, name, beam_width=beam, state_limit=limit)
+    for field in ("step_type", "step_ptr", "perm", "in_ptr", "in_src", "out_ptr", "out_dst",
+                  "param_row"):
+        a, b = getattr(ref, field), getattr(got, field)
+        assert np.array_equal(a, b[:a.shape[0]]) and a.shape[0] == b.shape[0] or \
+            (a.shape[0] == 0 and b.shape[0] == 0), (field, a, b)
+    assert got.num_steps == ref.num_steps
+
+
+def test_header_symbols_exported():
+    header = open(os.path.join(ROOT, "include", "grafx.h")).read()
+    declared = set(re.findall(r"^(?:grafx_status|void|const char\*)\s+(grafx_\w+)\(", header, re.M))
+    assert declared == set(EXPORTS)
+    lib = load()
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_bit_exact_random_dags(seed):
+    rng = synth.rng_for(1000 + seed, 0)
+    g = synth.random_dag(rng, int(rng.integers(3, 16)), types=(2, 3, 4, 5, 6), edge_p=0.3,
+                         n_out=int(rng.integers(1, 3)))
+    for code, name in METHODS:
+        assert_same(g, code, name, beam=int(rng.integers(1, 6)))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_bit_exact_larger_dags(seed):
+    rng = synth.rng_for(2000 + seed, 0)
+    g = synth.random_dag(rng, int(rng.integers(30, 80)), types=(2, 3, 4, 5, 6, 7, 8),
+                         edge_p=0.08)
+    for code, name in METHODS[:3]:
+        assert_same(g, code, name, beam=32)
+
+
+def test_bit_exact_consoles():
+    for w in (synth.tiny_console(T=8), synth.mixing_console(T=8), synth.large_console(T=8)):
+        for code, name in METHODS[:3]:
+            assert_same(w.graph, code, name)
+    assert_same(synth.tiny_console(T=8).graph, osch.OPTIMAL, "optimal")
+
+
+def _err(node_type, edges, **kw):
+    with pytest.raises(GrafxError) as e:
+        Schedule(np.asarray(node_type), np.asarray(edges), **kw)
+    return e.value.status
+
+
+def test_error_codes_match_oracle():
+    assert _err([0, 3, 1, 3], [[0, 1, 3, 1], [1, 3, 1, 2]]) == "GRAFX_E_CYCLE"
+    assert _err([0, 3, 1], [[0, 1, 1], [1, 2, 0]]) == "GRAFX_E_GRAPH"
+    assert _err([0, 3, 1, 3], [[0, 1, 2], [1, 2, 3]]) == "GRAFX_E_GRAPH"
+    assert _err([0, 3], [[0], [1]]) == "GRAFX_E_GRAPH"
+    assert _err([0, 12, 1], [[0, 1], [1, 2]]) == "GRAFX_E_TYPE"
+    assert _err([0, 3, 1], [[0, 1], [1, 2]], edge_type=np.ones((2, 2))) == "GRAFX_E_TYPE"
+    assert _err([0, 3, 1], [[0, 1], [1, 7]]) == "GRAFX_E_GRAPH"
+    assert _err([0, 3, 1], [[0, 1], [1, 2]], method="beam", beam_width=0) == "GRAFX_E_ARG"
+    rng = synth.rng_for(7, 0)
+    g = synth.random_dag(rng, 40, types=(2, 3, 4, 5, 6, 7, 8), edge_p=0.05)
+    assert _err(g.node_type, g.edges, method="optimal", state_limit=3) == "GRAFX_E_LIMIT"
+    with pytest.raises(osch.ScheduleError):
+        osch.schedule(g.node_type, g.edges, osch.OPTIMAL, state_limit=3)
+
+
+def test_no_processing_nodes_and_orphans():
+    # inputs straight to outputs; a processing node without inputs; an unused input
+    nt = np.array([0, 1, 3, 1, 0], dtype=np.int32)
+    e = np.array([[0, 2], [1, 3]], dtype=np.int32)
+    for code, name in METHODS:
+        assert_same(synth.Graph(nt, e), code, name)
+    s = Schedule(nt, e)
+    assert s.type_string() == (0, 3, 1)
+    s = Schedule(np.array([0, 1], dtype=np.int32), np.array([[0], [1]], dtype=np.int32))
+    assert s.type_string() == (0, 1) and s.num_steps == 1
+
+
+def test_workspace_bytes_grow_with_T():
+    w = synth.mixing_console(T=8)
+    s = Schedule(w.graph.node_type, w.graph.edges)
+    a, b = s.workspace_bytes(2 ** 10, False), s.workspace_bytes(2 ** 18, False)
+    assert 0 < a < b < s.workspace_bytes(2 ** 18, True)
+    assert s.plan_bytes >= 4 * (2 * (w.graph.num_nodes + 1) + 2 * w.graph.num_edges)
+    lib = load()
+    n = ctypes.c_size_t()
+    assert lib.grafx_workspace_bytes(s._h, 0, 0, ctypes.byref(n)) == 5  # T < 1: E_SHAPE
