@@ -1,0 +1,239 @@
+"""Benchmark: node-samples/s of one gradient step of the mixing-console graph on one MI355X.
+
+A step is the whole hot path on one batch: the batched forward render of the graph (64 stereo
+tracks, T = 2^18, ~220 nodes), the 3-resolution STFT loss against a target mix rendered with
+hidden parameters, the loss adjoint and the render adjoint down to every processor parameter.
+Throughput = processed (non-input) nodes x T / step time, with every input already resident in
+HBM. All inputs are seeded synthetic stand-ins for the paper's consoles.
+
+Prints one JSON line with, besides the metric, the HBM roofline of the dominant step kernel
+(algorithmic bytes / its event-timed duration, measured here) and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload console|tiny|large] [--method beam]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console"}
+TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh")
+# kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
+KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
+              "imager": "k_pointwise.hip", "tanh": "k_pointwise.hip", "eq": "k_eq.hip",
+              "compressor": "k_comp.hip", "delay": "k_delay.hip"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="console", choices=sorted(WORKLOADS))
+    ap.add_argument("--method", default="beam")
+    ap.add_argument("--T", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--breakdown-json", default=None, help="write the per-step timing table here")
+    return ap.parse_args()
+
+
+def step_bytes(sched, n: int, T: int, backward: bool) -> int:
+    """Algorithmic HBM bytes of one step (stereo float32 = 8 B per node-sample): forward reads
+    every input edge and writes the output, 8 (d_in + 1) T per node; the adjoint reads every
+    output-edge adjoint, writes the input adjoint, and reads either the node output (gain_pan,
+    imager: 1 row) or its inputs (eq, compressor, delay, tanh: d_in rows); mix reads neither."""
+    t = int(sched.step_type[n])
+    total = 0
+    for i in range(int(sched.step_ptr[n]), int(sched.step_ptr[n + 1])):
+        d_in = int(sched.in_ptr[i + 1] - sched.in_ptr[i])
+        d_out = int(sched.out_ptr[i + 1] - sched.out_ptr[i])
+        if not backward:
+            rows = d_in + 1
+        elif t == 2:
+            rows = d_out + 1
+        elif t in (3, 6):
+            rows = d_out + 2
+        else:
+            rows = d_out + d_in + 1
+        total += 8 * rows * T
+    return total
+
+
+def stored_traffic(kernel_type: str, direction: str, workload: str):
+    """HBM traffic of the dominant kernel from committed rocprofv3 PMC summaries, only if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2408_03204_amd", "csrc",
+                                KERNEL_SRC[kernel_type]), "rb").read()
+        key = f"{direction}:{kernel_type}:{workload}"
+        ent = rec.get(key)
+        if ent and ent.get("src_sha256") == hashlib.sha256(src).hexdigest():
+            return ent.get("bytes_per_step")
+    except Exception:  # noqa: BLE001
+        return None
+    return None
+
+
+def cpu_baseline(maker, T_full: int, seed_T: int):
+    """The FP64 oracle (forward render, MRSTFT loss, autograd backward) on the same graph with a
+    shorter signal: a bounded sample of the workload."""
+    import torch
+
+    from oracle import mrstft as OM
+    from oracle import render as OR
+    # one untimed pass on a short signal first (thread pool and FFT plan set-up)
+    wu = maker(T=4096)
+    Pu = OR.as_params64(wu.params, requires_grad=True)
+    Lu = OM.mrstft(OR.render(wu.graph.node_type, wu.graph.edges, wu.sources, Pu),
+                   torch.as_tensor(wu.sources[:1], dtype=torch.float64))
+    torch.autograd.grad(Lu, [Pu[t] for t in Pu if Pu[t].shape[0] > 0])
+    w = maker(T=seed_T)
+    g = w.graph
+    cores = torch.get_num_threads()
+    P = OR.as_params64(w.params, requires_grad=True)
+    with torch.no_grad():
+        tgt = OR.render(g.node_type, g.edges, w.sources, OR.as_params64(w.target_params))
+    t0 = time.perf_counter()
+    Y = OR.render(g.node_type, g.edges, w.sources, P)
+    L = OM.mrstft(Y, tgt)
+    keys = [t for t in P if P[t].shape[0] > 0]
+    torch.autograd.grad(L, [P[t] for t in keys])
+    dt = time.perf_counter() - t0
+    ns = w.processed_nodes * seed_T
+    return {"value": ns / dt, "unit": "node-samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{w.name} graph at T={seed_T} (1/{T_full // seed_T} of the benchmark "
+                      f"length), forward+MRSTFT+backward, float64, {dt:.1f} s"}
+
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2408_03204_amd import RenderBuffers, Schedule, mrstft_loss, render
+
+    maker = getattr(synth, WORKLOADS[args.workload])
+    w = maker(T=args.T) if args.T else maker()
+    T = w.T
+    g = w.graph
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sched = Schedule(g.node_type, g.edges, args.method)
+    S = torch.as_tensor(w.sources, device=dev)
+    P = {t: torch.as_tensor(p, device=dev).requires_grad_(True)
+         for t, p in w.params.items() if p.shape[0] > 0}
+    with torch.no_grad():
+        Ptgt = {t: torch.as_tensor(p, device=dev) for t, p in w.target_params.items()
+                if p.shape[0] > 0}
+        target = render(sched, S, Ptgt).clone()
+    plist = list(P.values())
+
+    def step():
+        Y = render(sched, S, P)
+        L = mrstft_loss(Y, target)
+        return torch.autograd.grad(L, plist)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    node_samples = w.processed_nodes * T
+    value = node_samples / (ms * 1e-3)
+
+    # ---- per-step breakdown: every render / adjoint step timed with events on its stream ------
+    roofline, table = None, []
+    if not args.no_breakdown:
+        rb = RenderBuffers(sched, T, dev, with_backward=True)
+        Pd = {t: p.detach() for t, p in P.items()}
+        dY = torch.randn((sched.num_outputs, 2, T), device=dev)
+        dPd = {t: torch.empty_like(p) for t, p in Pd.items()}
+        rb.forward(S, Pd)
+        rb.backward(S, Pd, dY, dPd)
+        reps = 5
+        evs = []
+        for direction in ("fwd", "bwd"):
+            steps = range(1, sched.num_steps + 1) if direction == "fwd" else \
+                range(sched.num_steps - 1, 0, -1)
+            for n in steps:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    if direction == "fwd":
+                        rb.step(S, Pd, n)
+                    else:
+                        rb.backward_step(S, Pd, dY, n)
+                b.record()
+                evs.append((direction, n, a, b))
+        torch.cuda.synchronize()
+        agg: dict = {}
+        for direction, n, a, b in evs:
+            t_ms = a.elapsed_time(b) / reps
+            tname = TYPE_NAMES[int(sched.step_type[n])]
+            nbytes = step_bytes(sched, n, T, direction == "bwd")
+            nodes = int(sched.step_ptr[n + 1] - sched.step_ptr[n])
+            table.append({"dir": direction, "step": n, "type": tname, "nodes": nodes,
+                          "ms": round(t_ms, 5), "GB/s": round(nbytes / (t_ms * 1e6), 1)})
+            k = (direction, tname)
+            tb = agg.setdefault(k, [0.0, 0, 0])
+            tb[0] += t_ms
+            tb[1] += nbytes
+            tb[2] += 1
+        (d, tname), (t_tot, b_tot, cnt) = max(agg.items(), key=lambda kv: kv[1][0])
+        achieved = b_tot / (t_tot * 1e6)
+        traffic = stored_traffic(tname, d, args.workload)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "kernel": f"{tname} {d}",
+                    "launches": cnt, "algorithmic_bytes": b_tot,
+                    "ms_total": round(t_tot, 4)}
+        if args.breakdown_json:
+            with open(args.breakdown_json, "w") as f:
+                json.dump({"step_ms": ms, "table": table,
+                           "by_type": {f"{k[0]}:{k[1]}": v for k, v in agg.items()}}, f,
+                          indent=1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(maker, T, max(T // 4, 4096) if args.workload != "tiny" else T)
+
+    out = {"metric": "node-samples/s fwd+bwd", "value": round(value, 1),
+           "unit": "node-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "nodes": g.num_nodes,
+                      "processed_nodes": w.processed_nodes, "edges": g.num_edges, "T": T,
+                      "schedule": args.method, "steps_in_schedule": sched.num_steps,
+                      "loss": "mrstft 512/1024/2048", "step": "render+loss+adjoint"},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,25 @@ grafx_status grafx_render_backward(const grafx_schedule_t* sched, const void* de
                                    hipStream_t stream);
 
 /*
+ * Single steps of the two loops above, for callers that drive or time the loop themselves:
+ * grafx_render_step runs the batched processor call of step `step` (1..N) only;
+ * grafx_render_backward_step runs the adjoint of step `step` (1..N-1) only, leaving its
+ * parameter-gradient partials in `ws` (the final reduction into dP happens in
+ * grafx_render_backward). Preconditions: a complete grafx_render with the same parameters has
+ * already run on `ws` (filter designs and envelope carries are there), and the rows the step
+ * reads are current (earlier steps' outputs in U; later steps' input adjoints in dU).
+ * Arguments and errors are those of grafx_render / grafx_render_backward, plus GRAFX_E_ARG for a
+ * step out of range.
+ */
+grafx_status grafx_render_step(const grafx_schedule_t* sched, const void* dev_plan, int64_t T,
+                               const float* S, const float* const* P, float* U, void* ws,
+                               size_t ws_bytes, int32_t step, hipStream_t stream);
+grafx_status grafx_render_backward_step(const grafx_schedule_t* sched, const void* dev_plan,
+                                        int64_t T, const float* S, const float* const* P,
+                                        const float* U, const float* dY, float* dU, void* ws,
+                                        size_t ws_bytes, int32_t step, hipStream_t stream);
+
+/*
  * Multi-resolution STFT loss between two sets of stereo signals (the loss of the paper's
  * gradient-descent mixing application, Sec. 4): resolutions 512, 1024 and 2048, hop r/4,
  * periodic Hann window, frames that fit inside [0, T), magnitudes sqrt(|X|^2 + 1e-8);

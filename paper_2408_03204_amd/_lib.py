@@ -19,7 +19,7 @@ STATUS = {0: "GRAFX_OK", 1: "GRAFX_E_ARG", 2: "GRAFX_E_GRAPH", 3: "GRAFX_E_CYCLE
 # Symbols declared in include/grafx.h (checked by the CPU test suite).
 EXPORTS = ("grafx_schedule", "grafx_schedule_free", "grafx_schedule_query",
            "grafx_schedule_export", "grafx_plan_upload", "grafx_workspace_bytes", "grafx_render",
-           "grafx_render_backward", "grafx_mrstft_workspace_bytes", "grafx_mrstft_loss",
+           "grafx_render_backward", "grafx_render_step", "grafx_render_backward_step", "grafx_mrstft_workspace_bytes", "grafx_mrstft_loss",
            "grafx_mrstft_backward", "grafx_last_error")
 
 
@@ -64,6 +64,9 @@ def load() -> ctypes.CDLL:
         "grafx_render": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, sz, vp]),
         "grafx_render_backward": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, vp, vp, ptr_array,
                                         vp, sz, vp]),
+        "grafx_render_step": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, sz, i32, vp]),
+        "grafx_render_backward_step": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, vp, vp, sz,
+                                             i32, vp]),
         "grafx_mrstft_workspace_bytes": (i32, [i32, i64, ctypes.POINTER(sz)]),
         "grafx_mrstft_loss": (i32, [i32, i64, vp, vp, vp, vp, sz, vp]),
         "grafx_mrstft_backward": (i32, [i32, i64, vp, vp, vp, vp, vp, sz, vp]),

@@ -192,3 +192,50 @@ class _MRSTFT(torch.autograd.Function):
 def mrstft_loss(Y: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
     """Multi-resolution STFT loss (512/1024/2048) between [rows, 2, T] signals."""
     return _MRSTFT.apply(Y.contiguous(), target.contiguous())
+
+
+class RenderBuffers:
+    """Explicit-buffer interface to the C ABI without autograd: owns U, the workspace and the
+    adjoint buffer for one schedule, signal length and device. `forward`, `backward`, and the
+    single-step calls enqueue on the current stream (used for live per-step timing)."""
+
+    def __init__(self, sched: Schedule, T: int, device="cuda", with_backward: bool = True):
+        self.sched, self.T, self.device = sched, int(T), torch.device(device)
+        self.U = torch.empty((sched.num_nodes, 2, T), dtype=torch.float32, device=device)
+        self.dU = torch.empty_like(self.U) if with_backward else None
+        self.ws = torch.empty(max(sched.workspace_bytes(T, with_backward), 256),
+                              dtype=torch.uint8, device=device)
+        self.plan = sched.plan(device)
+
+    @property
+    def Y(self) -> torch.Tensor:
+        return self.U[self.sched.out_begin:]
+
+    def forward(self, S, P):
+        Pl = _param_list(self.sched, P)
+        check(load().grafx_render(self.sched._h, self.plan.data_ptr(), self.T, S.data_ptr(),
+                                  _ptrs(Pl), self.U.data_ptr(), self.ws.data_ptr(),
+                                  self.ws.numel(), _stream(self.device)))
+
+    def backward(self, S, P, dY, dP: dict | None = None, dS=None):
+        Pl = _param_list(self.sched, P)
+        dPl = [None] * 9
+        for k, v in (dP or {}).items():
+            dPl[TYPE_CODES[k] if isinstance(k, str) else int(k)] = v
+        check(load().grafx_render_backward(
+            self.sched._h, self.plan.data_ptr(), self.T, S.data_ptr(), _ptrs(Pl),
+            self.U.data_ptr(), dY.data_ptr(), self.dU.data_ptr(),
+            dS.data_ptr() if dS is not None else None, _ptrs(dPl), self.ws.data_ptr(),
+            self.ws.numel(), _stream(self.device)))
+
+    def step(self, S, P, n: int):
+        check(load().grafx_render_step(self.sched._h, self.plan.data_ptr(), self.T, S.data_ptr(),
+                                       _ptrs(_param_list(self.sched, P)), self.U.data_ptr(),
+                                       self.ws.data_ptr(), self.ws.numel(), n,
+                                       _stream(self.device)))
+
+    def backward_step(self, S, P, dY, n: int):
+        check(load().grafx_render_backward_step(
+            self.sched._h, self.plan.data_ptr(), self.T, S.data_ptr(),
+            _ptrs(_param_list(self.sched, P)), self.U.data_ptr(), dY.data_ptr(),
+            self.dU.data_ptr(), self.ws.data_ptr(), self.ws.numel(), n, _stream(self.device)))

@@ -96,6 +96,61 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
   return GRAFX_OK;
 }
 
+hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
+                            float* U, void* ws, const WsLayout& L, int n, hipStream_t stream) {
+  const int t = h->step_type[n];
+  const int b = h->step_ptr[n], cnt = h->step_ptr[n + 1] - b;
+  if (cnt == 0) return hipSuccess;
+  const float* p = P ? P[t] : nullptr;
+  switch (t) {
+    case GRAFX_MIX:
+    case GRAFX_OUT:
+    case GRAFX_GAIN_PAN:
+    case GRAFX_IMAGER:
+    case GRAFX_TANH:
+      return launch_pointwise_fwd(t, g, U, p, b, cnt, stream);
+    case GRAFX_EQ:
+      return launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
+    case GRAFX_COMPRESSOR:
+      return launch_comp_fwd(g, U, p, b, cnt, at<double>(ws, L.comp_agg),
+                             at<double>(ws, L.comp_carry), stream);
+    case GRAFX_DELAY:
+      return launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
+                              cnt, stream);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
+                            float* dU, void* ws, const WsLayout& L, int n, hipStream_t stream) {
+  const int t = h->step_type[n];
+  const int b = h->step_ptr[n], cnt = h->step_ptr[n + 1] - b;
+  if (cnt == 0) return hipSuccess;
+  const float* p = P ? P[t] : nullptr;
+  switch (t) {
+    case GRAFX_MIX:
+      return launch_pointwise_bwd(t, g, dU, nullptr, b, cnt, nullptr, stream);
+    case GRAFX_GAIN_PAN:
+      return launch_pointwise_bwd(t, g, dU, p, b, cnt, at<double>(ws, L.part_gp), stream);
+    case GRAFX_IMAGER:
+      return launch_pointwise_bwd(t, g, dU, p, b, cnt, at<double>(ws, L.part_im), stream);
+    case GRAFX_TANH:
+      return launch_pointwise_bwd(t, g, dU, p, b, cnt, at<double>(ws, L.part_tanh), stream);
+    case GRAFX_EQ:
+      return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float2>(ws, L.eq_C), stream);
+    case GRAFX_COMPRESSOR:
+      return launch_comp_bwd(g, dU, p, b, cnt, at<double>(ws, L.comp_carry),
+                             at<double>(ws, L.comp_ragg), at<double>(ws, L.comp_rcarry),
+                             at<double>(ws, L.comp_part), stream);
+    case GRAFX_DELAY:
+      return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
+                              b, cnt, at<float>(ws, L.delay_part), stream);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 grafx_status hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return GRAFX_OK;
   return fail(GRAFX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -146,33 +201,8 @@ grafx_status grafx_render(const grafx_schedule_t* h, const void* dev_plan, int64
   if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
     e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
                             at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
-  for (int n = 1; n <= h->N && e == hipSuccess; ++n) {
-    const int t = h->step_type[n];
-    const int b = h->step_ptr[n], cnt = h->step_ptr[n + 1] - b;
-    if (cnt == 0) continue;
-    switch (t) {
-      case GRAFX_MIX:
-      case GRAFX_OUT:
-      case GRAFX_GAIN_PAN:
-      case GRAFX_IMAGER:
-      case GRAFX_TANH:
-        e = launch_pointwise_fwd(t, g, U, par(t), b, cnt, stream);
-        break;
-      case GRAFX_EQ:
-        e = launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
-        break;
-      case GRAFX_COMPRESSOR:
-        e = launch_comp_fwd(g, U, par(t), b, cnt, at<double>(ws, L.comp_agg),
-                            at<double>(ws, L.comp_carry), stream);
-        break;
-      case GRAFX_DELAY:
-        e = launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
-                             cnt, stream);
-        break;
-      default:
-        e = hipErrorInvalidValue;
-    }
-  }
+  for (int n = 1; n <= h->N && e == hipSuccess; ++n)
+    e = enqueue_fwd_step(h, g, P, U, ws, L, n, stream);
   return hip_status(e, "render launch");
 }
 
@@ -193,39 +223,8 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
   auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
   auto dpar = [&](int t) -> float* { return dP ? dP[t] : nullptr; };
   hipError_t e = hipSuccess;
-  for (int n = h->N - 1; n >= 1 && e == hipSuccess; --n) {
-    const int t = h->step_type[n];
-    const int b = h->step_ptr[n], cnt = h->step_ptr[n + 1] - b;
-    if (cnt == 0) continue;
-    switch (t) {
-      case GRAFX_MIX:
-        e = launch_pointwise_bwd(t, g, dU, nullptr, b, cnt, nullptr, stream);
-        break;
-      case GRAFX_GAIN_PAN:
-        e = launch_pointwise_bwd(t, g, dU, par(t), b, cnt, at<double>(ws, L.part_gp), stream);
-        break;
-      case GRAFX_IMAGER:
-        e = launch_pointwise_bwd(t, g, dU, par(t), b, cnt, at<double>(ws, L.part_im), stream);
-        break;
-      case GRAFX_TANH:
-        e = launch_pointwise_bwd(t, g, dU, par(t), b, cnt, at<double>(ws, L.part_tanh), stream);
-        break;
-      case GRAFX_EQ:
-        e = launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float2>(ws, L.eq_C), stream);
-        break;
-      case GRAFX_COMPRESSOR:
-        e = launch_comp_bwd(g, dU, par(t), b, cnt, at<double>(ws, L.comp_carry),
-                            at<double>(ws, L.comp_ragg), at<double>(ws, L.comp_rcarry),
-                            at<double>(ws, L.comp_part), stream);
-        break;
-      case GRAFX_DELAY:
-        e = launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
-                             b, cnt, at<float>(ws, L.delay_part), stream);
-        break;
-      default:
-        e = hipErrorInvalidValue;
-    }
-  }
+  for (int n = h->N - 1; n >= 1 && e == hipSuccess; --n)
+    e = enqueue_bwd_step(h, g, P, dU, ws, L, n, stream);
   if (e == hipSuccess && dS && h->K > 0)  // adjoint of the input step: sum over output edges
     e = launch_pointwise_bwd(GRAFX_IN, g, dS, nullptr, 0, h->K, nullptr, stream);
   const int tiles = pointwise_tiles(T), chunks = comp_chunks(T);
@@ -248,6 +247,35 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
                           h->type_count[GRAFX_DELAY], delay_groups(T), dpar(GRAFX_DELAY), stream);
   return hip_status(e, "render_backward launch");
+}
+
+grafx_status grafx_render_step(const grafx_schedule_t* h, const void* dev_plan, int64_t T,
+                               const float* S, const float* const* P, float* U, void* ws,
+                               size_t ws_bytes, int32_t step, hipStream_t stream) {
+  clear_error();
+  grafx_status st = check_common(h, dev_plan, T, S, P, U, ws, ws_bytes, false);
+  if (st != GRAFX_OK) return st;
+  if (step < 1 || step > h->N) return fail(GRAFX_E_ARG, "step out of range");
+  const WsLayout L = ws_layout(h, T, false);
+  const GraphView g = make_view(h, dev_plan, T, S, U);
+  return hip_status(enqueue_fwd_step(h, g, P, U, ws, L, step, stream), "render_step launch");
+}
+
+grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* dev_plan,
+                                        int64_t T, const float* S, const float* const* P,
+                                        const float* U, const float* dY, float* dU, void* ws,
+                                        size_t ws_bytes, int32_t step, hipStream_t stream) {
+  clear_error();
+  grafx_status st = check_common(h, dev_plan, T, S, P, U, ws, ws_bytes, true);
+  if (st != GRAFX_OK) return st;
+  if (!dY || !dU) return fail(GRAFX_E_ARG, "dY or dU is NULL");
+  if (step < 1 || step >= h->N) return fail(GRAFX_E_ARG, "step out of range");
+  const WsLayout L = ws_layout(h, T, true);
+  GraphView g = make_view(h, dev_plan, T, S, U);
+  g.dY = dY;
+  g.dU = dU;
+  return hip_status(enqueue_bwd_step(h, g, P, dU, ws, L, step, stream),
+                    "render_backward_step launch");
 }
 
 grafx_status grafx_mrstft_workspace_bytes(int32_t rows, int64_t T, size_t* bytes) {
