@@ -37,6 +37,18 @@ __device__ __forceinline__ const float* adj_row(const GraphView& g, int d) {
                           : g.dU + (int64_t)d * 2 * g.T;
 }
 
+// Raw buffer resource over n floats starting at p: loads through it take a 32-bit element
+// offset and return 0 outside [0, n) (the hardware range check), which implements the zero
+// padding of signal windows without branches. Requires n < 2^29.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* p, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)(n * 4),
+                                           0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; remap the hardware block id so
 // that every XCD works through one contiguous range of logical blocks (neighbouring time tiles
 // of a node then share an L2, which serves their overlapping halos).

@@ -13,9 +13,9 @@ namespace {
 // Workspace layout (byte offsets, 256-byte aligned sections). The forward part is kept by the
 // render for the adjoint: EQ filters, compressor carries, delay taps.
 struct WsLayout {
-  size_t eq_h, eq_H, comp_agg, comp_carry, delay_taps, delay_offs;
+  size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps, delay_offs;
   size_t fwd_end;
-  size_t part_gp, part_im, part_tanh, comp_ragg, comp_rcarry, comp_part, eq_C, eq_s, delay_part;
+  size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part;
   size_t total;
 };
 
@@ -28,8 +28,10 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   const size_t chunks = comp_chunks(T);
   L.eq_h = take(n_eq * 1024 * sizeof(double));
   L.eq_H = take(n_eq * kEqFFT * sizeof(float));
-  L.comp_agg = take(n_comp * chunks * sizeof(double));
+  L.comp_agg = take(n_comp * chunks * sizeof(uint64_t));
   L.comp_carry = take(n_comp * chunks * sizeof(double));
+  // one ticket counter per step (forward), one per step (adjoint), then the error word
+  L.comp_tickets = take((2 * (size_t)(h->N + 1) + 1) * sizeof(unsigned));
   L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
   L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
   L.fwd_end = off;
@@ -38,10 +40,10 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.part_gp = take(h->type_count[GRAFX_GAIN_PAN] * tiles * 2 * sizeof(double));
     L.part_im = take(h->type_count[GRAFX_IMAGER] * tiles * sizeof(double));
     L.part_tanh = take(h->type_count[GRAFX_TANH] * tiles * sizeof(double));
-    L.comp_ragg = take(n_comp * chunks * sizeof(double));
-    L.comp_rcarry = take(n_comp * chunks * sizeof(double));
+    L.comp_ragg = take(n_comp * chunks * sizeof(uint64_t));
     L.comp_part = take(n_comp * chunks * 4 * sizeof(double));
     L.eq_C = take(n_eq * eq_groups(T) * kEqFFT * sizeof(float2));
+    L.eq_spec = take(n_eq * kEqFFT * sizeof(float2));
     L.eq_s = take(n_eq * 1024 * sizeof(double));
     L.delay_part = take(n_del * delay_groups(T) * kDelayCoef * sizeof(float));
   }
@@ -79,7 +81,7 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
   if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
   if (!dev_plan) return fail(GRAFX_E_ARG, "plan is NULL");
   if (T < 1) return fail(GRAFX_E_SHAPE, "T must be >= 1");
-  if ((int64_t)h->V * 2 * T > ((int64_t)1 << 46)) return fail(GRAFX_E_SHAPE, "signal buffer too large");
+  if (T >= ((int64_t)1 << 29)) return fail(GRAFX_E_SHAPE, "T must be < 2^29");
   if (!U) return fail(GRAFX_E_ARG, "U is NULL");
   if (h->K > 0 && !S) return fail(GRAFX_E_ARG, "S is NULL but the graph has input nodes");
   if (!aligned(dev_plan, 256)) return fail(GRAFX_E_SHAPE, "plan must be 256-byte aligned");
@@ -94,6 +96,24 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
                                        " bytes, got " + std::to_string(ws_bytes));
   if (ws && !aligned(ws, 256)) return fail(GRAFX_E_SHAPE, "workspace must be 256-byte aligned");
   return GRAFX_OK;
+}
+
+unsigned* tickets(void* ws, const WsLayout& L, const grafx_schedule_t* h, bool bwd) {
+  return at<unsigned>(ws, L.comp_tickets) + (bwd ? h->N + 1 : 0);
+}
+
+unsigned* error_word(void* ws, const WsLayout& L, const grafx_schedule_t* h) {
+  return at<unsigned>(ws, L.comp_tickets) + 2 * (h->N + 1);
+}
+
+// Reset the compressor chaining state of one pass (all compressor nodes, all steps).
+hipError_t reset_comp(const grafx_schedule_t* h, void* ws, const WsLayout& L, bool bwd,
+                      int64_t T, hipStream_t stream) {
+  const int n_comp = h->type_count[GRAFX_COMPRESSOR];
+  if (n_comp == 0) return hipSuccess;
+  uint64_t* tot = at<uint64_t>(ws, bwd ? L.comp_ragg : L.comp_agg);
+  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd),
+                           h->N + 1, stream);
 }
 
 hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
@@ -112,8 +132,9 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_EQ:
       return launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
     case GRAFX_COMPRESSOR:
-      return launch_comp_fwd(g, U, p, b, cnt, at<double>(ws, L.comp_agg),
-                             at<double>(ws, L.comp_carry), stream);
+      return launch_comp_fwd(g, U, p, b, cnt, at<uint64_t>(ws, L.comp_agg),
+                             at<double>(ws, L.comp_carry), tickets(ws, L, h, false) + n,
+                             error_word(ws, L, h), stream);
     case GRAFX_DELAY:
       return launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
                               cnt, stream);
@@ -141,8 +162,8 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float2>(ws, L.eq_C), stream);
     case GRAFX_COMPRESSOR:
       return launch_comp_bwd(g, dU, p, b, cnt, at<double>(ws, L.comp_carry),
-                             at<double>(ws, L.comp_ragg), at<double>(ws, L.comp_rcarry),
-                             at<double>(ws, L.comp_part), stream);
+                             at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
+                             tickets(ws, L, h, true) + n, error_word(ws, L, h), stream);
     case GRAFX_DELAY:
       return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
                               b, cnt, at<float>(ws, L.delay_part), stream);
@@ -201,6 +222,7 @@ grafx_status grafx_render(const grafx_schedule_t* h, const void* dev_plan, int64
   if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
     e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
                             at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
+  if (e == hipSuccess) e = reset_comp(h, ws, L, false, T, stream);
   for (int n = 1; n <= h->N && e == hipSuccess; ++n)
     e = enqueue_fwd_step(h, g, P, U, ws, L, n, stream);
   return hip_status(e, "render launch");
@@ -222,7 +244,7 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
   g.dU = dU;
   auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
   auto dpar = [&](int t) -> float* { return dP ? dP[t] : nullptr; };
-  hipError_t e = hipSuccess;
+  hipError_t e = reset_comp(h, ws, L, true, T, stream);
   for (int n = h->N - 1; n >= 1 && e == hipSuccess; --n)
     e = enqueue_bwd_step(h, g, P, dU, ws, L, n, stream);
   if (e == hipSuccess && dS && h->K > 0)  // adjoint of the input step: sum over output edges
@@ -242,7 +264,8 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
                                chunks, 4, dpar(GRAFX_COMPRESSOR), stream);
   if (e == hipSuccess && dpar(GRAFX_EQ))
     e = launch_eq_grad(par(GRAFX_EQ), at<float2>(ws, L.eq_C), h->type_count[GRAFX_EQ],
-                       eq_groups(T), at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
+                       eq_groups(T), at<float2>(ws, L.eq_spec), at<double>(ws, L.eq_s),
+                       dpar(GRAFX_EQ), stream);
   if (e == hipSuccess && dpar(GRAFX_DELAY))
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
                           h->type_count[GRAFX_DELAY], delay_groups(T), dpar(GRAFX_DELAY), stream);
@@ -258,7 +281,10 @@ grafx_status grafx_render_step(const grafx_schedule_t* h, const void* dev_plan, 
   if (step < 1 || step > h->N) return fail(GRAFX_E_ARG, "step out of range");
   const WsLayout L = ws_layout(h, T, false);
   const GraphView g = make_view(h, dev_plan, T, S, U);
-  return hip_status(enqueue_fwd_step(h, g, P, U, ws, L, step, stream), "render_step launch");
+  hipError_t e = hipSuccess;
+  if (h->step_type[step] == GRAFX_COMPRESSOR) e = reset_comp(h, ws, L, false, T, stream);
+  if (e == hipSuccess) e = enqueue_fwd_step(h, g, P, U, ws, L, step, stream);
+  return hip_status(e, "render_step launch");
 }
 
 grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* dev_plan,
@@ -274,8 +300,10 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* d
   GraphView g = make_view(h, dev_plan, T, S, U);
   g.dY = dY;
   g.dU = dU;
-  return hip_status(enqueue_bwd_step(h, g, P, dU, ws, L, step, stream),
-                    "render_backward_step launch");
+  hipError_t e = hipSuccess;
+  if (h->step_type[step] == GRAFX_COMPRESSOR) e = reset_comp(h, ws, L, true, T, stream);
+  if (e == hipSuccess) e = enqueue_bwd_step(h, g, P, dU, ws, L, step, stream);
+  return hip_status(e, "render_backward_step launch");
 }
 
 grafx_status grafx_mrstft_workspace_bytes(int32_t rows, int64_t T, size_t* bytes) {

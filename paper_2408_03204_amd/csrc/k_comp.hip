@@ -1,22 +1,33 @@
 // Feed-forward compressor (paper Sec. 3 "Compressor", Eqs. 8-12), parallel across nodes and
-// time chunks.
+// time chunks, one pass over the signal per direction.
 //
 // With equal attack and release the energy envelope g[t] = a g[t-1] + (1-a) x[t],
 // x = (u_l + u_r)^2, is a linear one-pole recursion (the untruncated FIR of Eq. 9). It is computed
-// exactly, in double, as a chunked scan: each block owns 2048 samples (256 threads x 8 consecutive
+// in double as a chunked scan: a block owns a chunk of 2048 samples (256 threads x 8 consecutive
 // samples); a thread folds its 8 samples, a Kogge-Stone scan across the wave and a fold across
-// the 4 waves give every thread its incoming state. Chunks are chained in three launches: local
-// chunk totals, a fixed-order carry fold per node (c_{k+1} = a^2048 c_k + total_k), then the
-// final pass that rebuilds g from its carry, applies the quadratic-knee curve
-// (G_u = ln(g + 1e-8); gain exp(G_y - G_u)) and writes y. Every fold has a fixed order, so the
-// result does not depend on block scheduling.
+// the 4 waves give every thread its state relative to the chunk start. The chunk then publishes
+// its total (the state it would leave from a zero start) and folds the totals of all earlier
+// chunks of its node, c_k = sum_{j<k} total_j A^(k-1-j), A = a^2048, as one block-wide sum in a
+// fixed order. Folding totals (never partially folded prefixes) keeps the arithmetic independent
+// of timing, so results are deterministic and do not depend on the schedule.
+//
+// Chunk ids come from an atomic ticket taken when a block starts, so every chunk a block waits
+// for belongs to a block that started earlier and publishes without waiting: the waits always
+// end. A total is published as one 64-bit atomic store at device scope over a "not ready"
+// sentinel and read back by 64-bit atomic loads at device scope (the XCDs do not share an L2;
+// device-scope atomics bypass the non-coherent caches). The reader consumes only that word, so
+// no ordering with other data is needed: the accesses are relaxed, which avoids L2 write-back and
+// invalidation. Every wait is bounded; a wait that runs out records an error word and poisons
+// its result instead of spinning forever.
+//
+// The gain curve G_u = ln(g + 1e-8), quadratic knee, gain exp(G_y - G_u) is evaluated in float.
 //
 // Adjoint (rho = sum_c ybar_c y_c, e = G_y - G_u):
 //   gbar = rho de/dG_u / (g + 1e-8);  lambda[t] = gbar[t] + a lambda[t+1]  (reverse scan);
 //   ubar_c = gamma ybar_c + 2 (u_l + u_r)(1 - a) lambda;
 //   dL/da = sum lambda[t] (g[t-1] - x[t]);  dL/d(T, W, R) = sum rho de/d(T, W, R).
-// The reverse recursion uses the same chunked scan run on reversed thread order. The forward
-// carries saved by the render are the only state kept between the two calls.
+// The adjoint takes chunks from the end of each node backwards and runs the same scan on
+// reversed thread order; the envelope entering each chunk is kept from the forward call.
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
@@ -27,11 +38,17 @@ namespace {
 constexpr int kPer = 8;
 constexpr int kChunk = kCompChunk;  // 256 x 8
 constexpr double kEps = 1e-8;
+constexpr uint64_t kNotReady = ~0ull;
+constexpr int kMaxSpin = 1 << 24;
 
 struct Coef {
-  double a, b;             // alpha, 1 - alpha
-  double thr, knee, c, R;  // T, W, 1/R - 1, R
-  double pw[9];            // pw[d] = (a^8)^(2^d); pw[8] = a^2048
+  double a, b;        // alpha, 1 - alpha
+  float thr, knee;    // T, W
+  float c;            // 1/R - 1
+  float inv2w, inv4w; // 1/(2W), 1/(4W)
+  float invR2;        // 1/R^2
+  double pw[9];       // pw[d] = (a^8)^(2^d); pw[8] = a^2048
+  double logA;        // ln(a^2048)
 };
 
 __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
@@ -39,10 +56,14 @@ __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
   const float* p = P + (int64_t)slot * 4;
   k.a = (double)p[0];
   k.b = 1.0 - k.a;
-  k.thr = (double)p[1];
-  k.knee = (double)p[2];
-  k.R = (double)p[3];
-  k.c = 1.0 / k.R - 1.0;
+  k.thr = p[1];
+  k.knee = p[2];
+  const float R = p[3];
+  k.c = 1.0f / R - 1.0f;
+  k.inv2w = k.knee > 0.f ? 1.0f / (2.f * k.knee) : 0.f;
+  k.inv4w = k.knee > 0.f ? 1.0f / (4.f * k.knee) : 0.f;
+  k.invR2 = 1.0f / (R * R);
+  k.logA = 2048.0 * log(k.a);
   double q = k.a * k.a;
   q = q * q;
   k.pw[0] = q * q;
@@ -61,25 +82,24 @@ __device__ __forceinline__ double pow_a8(const Coef& k, int n) {
 }
 
 struct Curve {
-  double e, dG, dT, dW, dR;
+  float e, dG, dT, dW, dR;
 };
 
 // e = G_y - G_u of the quadratic-knee curve (Eqs. 10-11) and its partial derivatives.
 template <bool GRAD>
-__device__ __forceinline__ Curve curve(double Gu, const Coef& k) {
-  Curve o{0.0, 0.0, 0.0, 0.0, 0.0};
-  const double d = Gu - k.thr;
-  const bool soft = k.knee > 0.0;
+__device__ __forceinline__ Curve curve(float Gu, const Coef& k) {
+  Curve o{0.f, 0.f, 0.f, 0.f, 0.f};
+  const float d = Gu - k.thr;
+  const bool soft = k.knee > 0.f;
   if (soft ? (Gu < k.thr - k.knee) : (Gu < k.thr)) return o;
   if (soft && Gu < k.thr + k.knee) {
-    const double q = d + k.knee;
-    const double w4 = 4.0 * k.knee;
-    o.e = k.c * q * q / w4;
+    const float q = d + k.knee;
+    o.e = k.c * q * q * k.inv4w;
     if (GRAD) {
-      o.dG = k.c * q / (2.0 * k.knee);
+      o.dG = k.c * q * k.inv2w;
       o.dT = -o.dG;
-      o.dW = k.c * (q / (2.0 * k.knee) - q * q / (w4 * k.knee));
-      o.dR = -q * q / (w4 * k.R * k.R);
+      o.dW = k.c * (q * k.inv2w - q * q * k.inv4w * (2.f * k.inv2w));
+      o.dR = -q * q * k.inv4w * k.invR2;
     }
     return o;
   }
@@ -87,18 +107,17 @@ __device__ __forceinline__ Curve curve(double Gu, const Coef& k) {
   if (GRAD) {
     o.dG = k.c;
     o.dT = -k.c;
-    o.dR = -d / (k.R * k.R);
+    o.dR = -d * k.invR2;
   }
   return o;
 }
 
 // Chunk scan of s_out = a^8 s_in + B over the block's 256 threads (reversed thread order when
-// REV). `B` is this thread's fold of its own 8 samples from a zero state; `cin` is the state
-// entering the chunk. Returns the state entering this thread's samples; `chunk_out` receives the
-// state leaving the chunk (every thread).
+// REV), from a zero state entering the chunk. Returns the state entering this thread's samples;
+// `total` receives the state leaving the chunk (every thread). Thread J's state for a non-zero
+// entering state c is the returned value plus (a^8)^J' c, J' = J (forward) or 255 - J (REV).
 template <bool REV>
-__device__ __forceinline__ double chunk_scan(double B, double cin, const Coef& k, double* wtot,
-                                             double& chunk_out) {
+__device__ __forceinline__ double chunk_scan(double B, const Coef& k, double* wtot, double& total) {
   const int lane0 = threadIdx.x & 63, w0 = threadIdx.x >> 6;
   const int lane = REV ? 63 - lane0 : lane0;
   const int w = REV ? 3 - w0 : w0;
@@ -113,54 +132,95 @@ __device__ __forceinline__ double chunk_scan(double B, double cin, const Coef& k
   __syncthreads();
   if (lane == 63) wtot[w] = S;
   __syncthreads();
-  double P = cin, end = cin;
+  double P = 0.0, end = 0.0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     if (v < w) P = fma(k.pw[6], P, wtot[v]);
     end = fma(k.pw[6], end, wtot[v]);
   }
-  chunk_out = end;
+  total = end;
   return fma(pow_a8(k, lane), P, ex);
 }
 
-// Stage the gather-sum of a chunk (both channels) into LDS.
-__device__ __forceinline__ void stage_input(const GraphView& g, int node, int64_t t0, float* sl,
-                                            float* sr) {
-  const int64_t T = g.T;
-  const int e0 = g.in_ptr[node], e1 = g.in_ptr[node + 1];
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int idx = threadIdx.x + kBlock * q;
-    const int64_t t = t0 + idx;
-    float l = 0.f, r = 0.f;
-    if (t < T)
-      for (int e = e0; e < e1; ++e) {
-        const float* row = out_row(g, g.in_src[e]);
-        l += row[t];
-        r += row[T + t];
-      }
-    sl[idx] = l;
-    sr[idx] = r;
+__device__ __forceinline__ int scan_index(bool rev) {
+  return rev ? kBlock - 1 - (int)threadIdx.x : (int)threadIdx.x;
+}
+
+// ---- chunk chaining ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int take_ticket(unsigned* counter, int* sh) {
+  __syncthreads();
+  if (threadIdx.x == 0)
+    *sh = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return *sh;
+}
+
+__device__ __forceinline__ void publish(uint64_t* slot, double v) {
+  __hip_atomic_store(slot, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double await_total(uint64_t* slot, unsigned* err) {
+  for (int spin = 0;; ++spin) {
+    const uint64_t x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (x != kNotReady) return __longlong_as_double((long long)x);
+    if (spin >= kMaxSpin) {  // never expected: poison the result instead of spinning on
+      atomicOr(err, 1u);
+      return __longlong_as_double(0x7FF8000000000001ll);
+    }
+    __builtin_amdgcn_s_sleep(1);
   }
 }
 
-__device__ __forceinline__ void stage_adjoint(const GraphView& g, int node, int64_t t0, float* sl,
-                                              float* sr) {
+// Entering state of chunk k: fixed-order block-wide sum over the published totals of the
+// chunks before it (REV: after it), weighted by A^(distance - 1).
+template <bool REV>
+__device__ __forceinline__ double chunk_carry(uint64_t* tot, int k, int chunks, const Coef& c,
+                                              unsigned* err, double* red) {
+  double s = 0.0;
+  if (!REV) {
+    for (int j = threadIdx.x; j < k; j += kBlock)
+      s += await_total(tot + j, err) * exp((double)(k - 1 - j) * c.logA);
+  } else {
+    for (int j = k + 1 + threadIdx.x; j < chunks; j += kBlock)
+      s += await_total(tot + j, err) * exp((double)(j - k - 1) * c.logA);
+  }
+  return block_sum<double>(s, red);
+}
+
+// ---- staging -----------------------------------------------------------------------------------
+
+// Gather-sum of a chunk (both channels) into LDS: ADJ = false sums the input edges over U/S,
+// ADJ = true the output edges over dU/dY. Zero beyond T.
+template <bool ADJ>
+__device__ __forceinline__ void stage(const GraphView& g, int node, int t0, float* sl, float* sr) {
   const int64_t T = g.T;
-  const int o0 = g.out_ptr[node], o1 = g.out_ptr[node + 1];
+  const int e0 = ADJ ? g.out_ptr[node] : g.in_ptr[node];
+  const int e1 = ADJ ? g.out_ptr[node + 1] : g.in_ptr[node + 1];
+  float l[kPer], r[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) l[q] = r[q] = 0.f;
+  for (int e = e0; e < e1; ++e) {  // all loads of a row issued before any is consumed
+    const float* row = ADJ ? adj_row(g, g.out_dst[e]) : out_row(g, g.in_src[e]);
+    const auto rl = row_rsrc(row, T), rr = row_rsrc(row + T, T);
+    float xl[kPer], xr[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = t0 + (int)threadIdx.x + kBlock * q;
+      xl[q] = bload(rl, t);
+      xr[q] = bload(rr, t);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      l[q] += xl[q];
+      r[q] += xr[q];
+    }
+  }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int idx = threadIdx.x + kBlock * q;
-    const int64_t t = t0 + idx;
-    float l = 0.f, r = 0.f;
-    if (t < T)
-      for (int e = o0; e < o1; ++e) {
-        const float* row = adj_row(g, g.out_dst[e]);
-        l += row[t];
-        r += row[T + t];
-      }
-    sl[idx] = l;
-    sr[idx] = r;
+    sl[threadIdx.x + kBlock * q] = l[q];
+    sr[threadIdx.x + kBlock * q] = r[q];
   }
 }
 
@@ -169,12 +229,12 @@ __device__ __forceinline__ double energy(const float* sl, const float* sr, int i
   return m * m;
 }
 
-__device__ __forceinline__ void store_chunk(float* row, int64_t T, int64_t t0, const float* sl,
+__device__ __forceinline__ void store_chunk(float* row, int64_t T, int t0, const float* sl,
                                             const float* sr) {
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int idx = threadIdx.x + kBlock * q;
-    const int64_t t = t0 + idx;
+    const int t = t0 + idx;
     if (t < T) {
       row[t] = sl[idx];
       row[T + t] = sr[idx];
@@ -184,66 +244,42 @@ __device__ __forceinline__ void store_chunk(float* row, int64_t T, int64_t t0, c
 
 // ---- forward ----------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void comp_fwd_total_kernel(GraphView g, const float* P,
-                                                                int node_begin, int chunks,
-                                                                double* agg) {
+__global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U, const float* P,
+                                                          int node_begin, int n_nodes, int chunks,
+                                                          uint64_t* agg, double* carry,
+                                                          unsigned* ticket, unsigned* err) {
   __shared__ float sl[kChunk], sr[kChunk];
-  __shared__ double wtot[4];
-  const int chunk = blockIdx.x, node = node_begin + blockIdx.y;
-  const int slot = g.param_row[node];
-  const Coef k = load_coef(P, slot);
-  stage_input(g, node, (int64_t)chunk * kChunk, sl, sr);
-  __syncthreads();
-  double B = 0.0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) B = fma(k.a, B, k.b * energy(sl, sr, kPer * threadIdx.x + i));
-  double end;
-  chunk_scan<false>(B, 0.0, k, wtot, end);
-  if (threadIdx.x == 0) agg[(int64_t)slot * chunks + chunk] = end;
-}
-
-// carry[k] = state entering chunk k; carry[0] = 0 (g[-1] = 0), carry[k+1] = a^2048 carry[k] +
-// agg[k]. One thread per node walks its chunks in order.
-__global__ __launch_bounds__(64) void comp_carry_kernel(const int32_t* param_row, const float* P,
-                                                        int node_begin, int chunks,
-                                                        const double* agg, double* carry) {
-  if (threadIdx.x != 0) return;
-  const int slot = param_row[node_begin + blockIdx.x];
-  const Coef k = load_coef(P, slot);
-  const double A = k.pw[8];
-  const double* a = agg + (int64_t)slot * chunks;
-  double* c = carry + (int64_t)slot * chunks;
-  double s = 0.0;
-  for (int i = 0; i < chunks; ++i) {
-    c[i] = s;
-    s = fma(A, s, a[i]);
+  __shared__ double wtot[4], red[4];
+  __shared__ int sh_ticket;
+  const int tk = take_ticket(ticket, &sh_ticket);
+  if (tk >= n_nodes * chunks) {  // tickets not reset before the launch: do nothing
+    if (threadIdx.x == 0) atomicOr(err, 2u);
+    return;
   }
-}
-
-__global__ __launch_bounds__(kBlock) void comp_fwd_apply_kernel(GraphView g, float* U,
-                                                                const float* P, int node_begin,
-                                                                int chunks, const double* carry) {
-  __shared__ float sl[kChunk], sr[kChunk];
-  __shared__ double wtot[4];
-  const int chunk = blockIdx.x, node = node_begin + blockIdx.y;
+  const int chunk = tk % chunks, node = node_begin + tk / chunks;
   const int slot = g.param_row[node];
   const Coef k = load_coef(P, slot);
-  const int64_t t0 = (int64_t)chunk * kChunk;
-  stage_input(g, node, t0, sl, sr);
+  const int t0 = chunk * kChunk;
+  stage<false>(g, node, t0, sl, sr);
   __syncthreads();
   const int i0 = kPer * threadIdx.x;
   double B = 0.0;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) B = fma(k.a, B, k.b * energy(sl, sr, i0 + i));
-  double end;
-  double s = chunk_scan<false>(B, carry[(int64_t)slot * chunks + chunk], k, wtot, end);
+  double total;
+  const double E0 = chunk_scan<false>(B, k, wtot, total);
+  uint64_t* tots = agg + (int64_t)slot * chunks;
+  if (threadIdx.x == 0) publish(tots + chunk, total);
+  const double cin = chunk_carry<false>(tots, chunk, chunks, k, err, red);
+  if (threadIdx.x == 0) carry[(int64_t)slot * chunks + chunk] = cin;
+  double s = fma(pow_a8(k, scan_index(false)), cin, E0);
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     s = fma(k.a, s, k.b * energy(sl, sr, i0 + i));
-    const Curve cv = curve<false>(log(s + kEps), k);
-    const double gam = exp(cv.e);
-    sl[i0 + i] = (float)(gam * (double)sl[i0 + i]);
-    sr[i0 + i] = (float)(gam * (double)sr[i0 + i]);
+    const Curve cv = curve<false>(logf((float)(s + kEps)), k);
+    const float gam = expf(cv.e);
+    sl[i0 + i] = gam * sl[i0 + i];
+    sr[i0 + i] = gam * sr[i0 + i];
   }
   __syncthreads();
   store_chunk(U + (int64_t)node * 2 * g.T, g.T, t0, sl, sr);
@@ -251,121 +287,78 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_apply_kernel(GraphView g, flo
 
 // ---- adjoint ----------------------------------------------------------------------------------
 
-// Per-sample adjoint quantities of one thread's 8 samples.
-struct Local {
-  double gv[kPer];    // envelope g
-  double gbar[kPer];  // dL/dg (direct part, before the recursion)
-  float gam[kPer];    // gain
-  double E;           // envelope entering the thread's first sample
-  double accT, accW, accR;
-};
-
-__device__ __forceinline__ void adjoint_local(const float* ul, const float* ur, const float* yl,
-                                              const float* yr, const Coef& k, double cin,
-                                              double* wtot, Local& L) {
+__global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU, const float* P,
+                                                          int node_begin, int n_nodes, int chunks,
+                                                          const double* carry, uint64_t* ragg,
+                                                          double* part, unsigned* ticket,
+                                                          unsigned* err) {
+  __shared__ float ul[kChunk], ur[kChunk], yl[kChunk], yr[kChunk];
+  __shared__ double wtot[4], red[4];
+  __shared__ int sh_ticket;
+  const int tk = take_ticket(ticket, &sh_ticket);
+  if (tk >= n_nodes * chunks) {  // tickets not reset before the launch: do nothing
+    if (threadIdx.x == 0) atomicOr(err, 2u);
+    return;
+  }
+  const int chunk = chunks - 1 - tk % chunks, node = node_begin + tk / chunks;
+  const int slot = g.param_row[node];
+  const Coef k = load_coef(P, slot);
+  const int t0 = chunk * kChunk;
+  stage<false>(g, node, t0, ul, ur);
+  stage<true>(g, node, t0, yl, yr);
+  __syncthreads();
   const int i0 = kPer * threadIdx.x;
+  // envelope rebuilt from the forward carry
   double B = 0.0;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) B = fma(k.a, B, k.b * energy(ul, ur, i0 + i));
-  double end;
-  L.E = chunk_scan<false>(B, cin, k, wtot, end);
-  double s = L.E;
-  L.accT = L.accW = L.accR = 0.0;
+  double total;
+  const double E0 = chunk_scan<false>(B, k, wtot, total);
+  const double E = fma(pow_a8(k, scan_index(false)), carry[(int64_t)slot * chunks + chunk], E0);
+  double gv[kPer];
+  float gbar[kPer], gam[kPer];
+  double accT = 0.0, accW = 0.0, accR = 0.0;
+  {
+    double s = E;
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    s = fma(k.a, s, k.b * energy(ul, ur, i0 + i));
-    L.gv[i] = s;
-    const Curve cv = curve<true>(log(s + kEps), k);
-    const double gam = exp(cv.e);
-    const double rho = gam * ((double)yl[i0 + i] * (double)ul[i0 + i] +
-                              (double)yr[i0 + i] * (double)ur[i0 + i]);
-    L.gam[i] = (float)gam;
-    L.gbar[i] = rho * cv.dG / (s + kEps);
-    L.accT += rho * cv.dT;
-    L.accW += rho * cv.dW;
-    L.accR += rho * cv.dR;
+    for (int i = 0; i < kPer; ++i) {
+      s = fma(k.a, s, k.b * energy(ul, ur, i0 + i));
+      gv[i] = s;
+      const float gs = (float)(s + kEps);
+      const Curve cv = curve<true>(logf(gs), k);
+      gam[i] = expf(cv.e);
+      const float rho = gam[i] * (yl[i0 + i] * ul[i0 + i] + yr[i0 + i] * ur[i0 + i]);
+      gbar[i] = rho * cv.dG / gs;
+      accT += (double)(rho * cv.dT);
+      accW += (double)(rho * cv.dW);
+      accR += (double)(rho * cv.dR);
+    }
   }
-}
-
-__global__ __launch_bounds__(kBlock) void comp_bwd_total_kernel(GraphView g, const float* P,
-                                                                int node_begin, int chunks,
-                                                                const double* carry,
-                                                                double* ragg) {
-  __shared__ float ul[kChunk], ur[kChunk], yl[kChunk], yr[kChunk];
-  __shared__ double wtot[4];
-  const int chunk = blockIdx.x, node = node_begin + blockIdx.y;
-  const int slot = g.param_row[node];
-  const Coef k = load_coef(P, slot);
-  const int64_t t0 = (int64_t)chunk * kChunk;
-  stage_input(g, node, t0, ul, ur);
-  stage_adjoint(g, node, t0, yl, yr);
-  __syncthreads();
-  Local L;
-  adjoint_local(ul, ur, yl, yr, k, carry[(int64_t)slot * chunks + chunk], wtot, L);
+  // reverse recursion lambda[t] = gbar[t] + a lambda[t+1]
   double R = 0.0;
 #pragma unroll
-  for (int i = kPer - 1; i >= 0; --i) R = fma(k.a, R, L.gbar[i]);
-  double end;
-  chunk_scan<true>(R, 0.0, k, wtot, end);
-  if (threadIdx.x == 0) ragg[(int64_t)slot * chunks + chunk] = end;
-}
-
-// rcarry[k] = lambda entering chunk k from the right (lambda at the first sample after it):
-// rcarry[last] = 0, rcarry[k-1] = ragg[k] + a^2048 rcarry[k].
-__global__ __launch_bounds__(64) void comp_rcarry_kernel(const int32_t* param_row, const float* P,
-                                                         int node_begin, int chunks,
-                                                         const double* ragg, double* rcarry) {
-  if (threadIdx.x != 0) return;
-  const int slot = param_row[node_begin + blockIdx.x];
-  const Coef k = load_coef(P, slot);
-  const double A = k.pw[8];
-  const double* a = ragg + (int64_t)slot * chunks;
-  double* c = rcarry + (int64_t)slot * chunks;
-  double s = 0.0;
-  for (int i = chunks - 1; i >= 0; --i) {
-    c[i] = s;
-    s = fma(A, s, a[i]);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void comp_bwd_apply_kernel(GraphView g, float* dU,
-                                                                const float* P, int node_begin,
-                                                                int chunks, const double* carry,
-                                                                const double* rcarry,
-                                                                double* part) {
-  __shared__ float ul[kChunk], ur[kChunk], yl[kChunk], yr[kChunk];
-  __shared__ double wtot[4];
-  __shared__ double red[4];
-  const int chunk = blockIdx.x, node = node_begin + blockIdx.y;
-  const int slot = g.param_row[node];
-  const Coef k = load_coef(P, slot);
-  const int64_t t0 = (int64_t)chunk * kChunk;
-  stage_input(g, node, t0, ul, ur);
-  stage_adjoint(g, node, t0, yl, yr);
-  __syncthreads();
-  Local L;
-  adjoint_local(ul, ur, yl, yr, k, carry[(int64_t)slot * chunks + chunk], wtot, L);
-  double R = 0.0;
-#pragma unroll
-  for (int i = kPer - 1; i >= 0; --i) R = fma(k.a, R, L.gbar[i]);
-  double end;
-  double lam = chunk_scan<true>(R, rcarry[(int64_t)slot * chunks + chunk], k, wtot, end);
-  const int i0 = kPer * threadIdx.x;
+  for (int i = kPer - 1; i >= 0; --i) R = fma(k.a, R, (double)gbar[i]);
+  double rtotal;
+  const double L0 = chunk_scan<true>(R, k, wtot, rtotal);
+  uint64_t* rtots = ragg + (int64_t)slot * chunks;
+  if (threadIdx.x == 0) publish(rtots + chunk, rtotal);
+  const double rin = chunk_carry<true>(rtots, chunk, chunks, k, err, red);
+  double lam = fma(pow_a8(k, scan_index(true)), rin, L0);
   double accA = 0.0;
 #pragma unroll
   for (int i = kPer - 1; i >= 0; --i) {
-    lam = fma(k.a, lam, L.gbar[i]);
+    lam = fma(k.a, lam, (double)gbar[i]);
     const double x = energy(ul, ur, i0 + i);
-    const double gprev = i > 0 ? L.gv[i - 1] : L.E;
+    const double gprev = i > 0 ? gv[i - 1] : E;
     accA += lam * (gprev - x);
     const double mid = 2.0 * ((double)ul[i0 + i] + (double)ur[i0 + i]) * k.b * lam;
-    yl[i0 + i] = (float)((double)L.gam[i] * (double)yl[i0 + i] + mid);
-    yr[i0 + i] = (float)((double)L.gam[i] * (double)yr[i0 + i] + mid);
+    yl[i0 + i] = (float)((double)(gam[i] * yl[i0 + i]) + mid);
+    yr[i0 + i] = (float)((double)(gam[i] * yr[i0 + i]) + mid);
   }
   const double sA = block_sum<double>(accA, red);
-  const double sT = block_sum<double>(L.accT, red);
-  const double sW = block_sum<double>(L.accW, red);
-  const double sR = block_sum<double>(L.accR, red);
+  const double sT = block_sum<double>(accT, red);
+  const double sW = block_sum<double>(accW, red);
+  const double sR = block_sum<double>(accR, red);
   if (threadIdx.x == 0) {
     double* p = part + ((int64_t)slot * chunks + chunk) * 4;
     p[0] = sA;
@@ -376,29 +369,43 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_apply_kernel(GraphView g, flo
   store_chunk(dU + (int64_t)node * 2 * g.T, g.T, t0, yl, yr);
 }
 
+// Reset the published totals to "not ready" and the tickets to 0 before a pass.
+__global__ __launch_bounds__(kBlock) void comp_reset_kernel(uint64_t* tot, int64_t n,
+                                                            unsigned* tickets, int n_tickets) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) tot[i] = kNotReady;
+  if (i < n_tickets) tickets[i] = 0u;
+}
+
 }  // namespace
 
 int comp_chunks(int64_t T) { return (int)((T + kChunk - 1) / kChunk); }
 
+hipError_t launch_comp_reset(uint64_t* tot, int64_t n, unsigned* tickets, int n_tickets,
+                             hipStream_t s) {
+  const int64_t m = n > n_tickets ? n : n_tickets;
+  if (m <= 0) return hipSuccess;
+  comp_reset_kernel<<<(unsigned)((m + kBlock - 1) / kBlock), kBlock, 0, s>>>(tot, n, tickets,
+                                                                              n_tickets);
+  return hipGetLastError();
+}
+
 hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int node_begin,
-                           int n_nodes, double* agg, double* carry, hipStream_t s) {
+                           int n_nodes, uint64_t* agg, double* carry, unsigned* ticket,
+                           unsigned* err, hipStream_t s) {
   const int chunks = comp_chunks(g.T);
-  const dim3 grid((unsigned)chunks, (unsigned)n_nodes);
-  comp_fwd_total_kernel<<<grid, kBlock, 0, s>>>(g, P, node_begin, chunks, agg);
-  comp_carry_kernel<<<n_nodes, 64, 0, s>>>(g.param_row, P, node_begin, chunks, agg, carry);
-  comp_fwd_apply_kernel<<<grid, kBlock, 0, s>>>(g, U, P, node_begin, chunks, carry);
+  comp_fwd_kernel<<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(g, U, P, node_begin, n_nodes,
+                                                                  chunks, agg, carry, ticket, err);
   return hipGetLastError();
 }
 
 hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
-                           int n_nodes, const double* carry, double* ragg, double* rcarry,
-                           double* part, hipStream_t s) {
+                           int n_nodes, const double* carry, uint64_t* ragg, double* part,
+                           unsigned* ticket, unsigned* err, hipStream_t s) {
   const int chunks = comp_chunks(g.T);
-  const dim3 grid((unsigned)chunks, (unsigned)n_nodes);
-  comp_bwd_total_kernel<<<grid, kBlock, 0, s>>>(g, P, node_begin, chunks, carry, ragg);
-  comp_rcarry_kernel<<<n_nodes, 64, 0, s>>>(g.param_row, P, node_begin, chunks, ragg, rcarry);
-  comp_bwd_apply_kernel<<<grid, kBlock, 0, s>>>(g, dU, P, node_begin, chunks, carry, rcarry,
-                                                part);
+  comp_bwd_kernel<<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(g, dU, P, node_begin, n_nodes,
+                                                                  chunks, carry, ragg, part, ticket,
+                                                                  err);
   return hipGetLastError();
 }
 

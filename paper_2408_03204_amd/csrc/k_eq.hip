@@ -12,8 +12,9 @@
 // samples before its first output, so the 2047-tap kernel never wraps. The FFT is a radix-16
 // Stockham transform with 256 threads x 16 points held in registers: the forward transform ends
 // and the inverse begins in the same register layout, so only the two inner passes of each
-// transform touch LDS. Tiles of one node are mapped onto one XCD (neighbouring tiles share the
-// halo through its L2).
+// transform touch LDS; each thread keeps its 30 twiddles in registers for all transforms of the
+// block. Window gathers use raw buffer loads whose range check supplies the zero padding. Tiles
+// of one node are mapped onto one XCD (neighbouring tiles share the halo through its L2).
 //
 // Adjoint: the input adjoint is the same filter applied to the output adjoint (h is even). The
 // FIR gradient hbar[n] = sum_{c,t} ybar_c[t] u_c[t - n] is the real part of a complex
@@ -35,16 +36,26 @@ constexpr int kLds = kN + kN / 16;  // one pad slot per 16 entries
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-template <bool INV>
-__device__ __forceinline__ float2 twiddle(int m) {
-  const float2 w = kTw4096[m];
-  return INV ? make_float2(w.x, -w.y) : w;
+// Twiddles of the two twiddled passes for thread j, loaded once per block and reused by every
+// transform of the block (the inverse uses their conjugates):
+// w1[r] = exp(-2 pi i r (j mod 16) / 256), w2[r] = exp(-2 pi i r j / 4096).
+struct Twiddles {
+  float2 w1[16], w2[16];
+};
+
+__device__ __forceinline__ void load_twiddles(Twiddles& tw) {
+  const int j = threadIdx.x;
+#pragma unroll
+  for (int r = 1; r < 16; ++r) {
+    tw.w1[r] = kTw4096[r * (j & 15) * 16];
+    tw.w2[r] = kTw4096[r * j];
+  }
 }
 
 // In-place 4096-point DFT (forward: exp(-2 pi i nk/N); inverse: exp(+...), unnormalised).
 // On entry v[r] holds x[j + 256 r] for thread j; on exit v[r] holds X[j + 256 r].
 template <bool INV>
-__device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds) {
+__device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds, const Twiddles& tw) {
   const int j = threadIdx.x;
   // pass 0 (sub-transform size 1): no twiddles
   dft16<INV>(v);
@@ -54,11 +65,8 @@ __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds) {
   // pass 1 (sub-transform size 16)
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[pad(j + 256 * r)];
-  {
-    const int k = j & 15;
 #pragma unroll
-    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<INV>(r * k * 16));
-  }
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], INV ? cconj(tw.w1[r]) : tw.w1[r]);
   dft16<INV>(v);
   __syncthreads();
   {
@@ -71,49 +79,79 @@ __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[pad(j + 256 * r)];
 #pragma unroll
-  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<INV>(r * j));
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], INV ? cconj(tw.w2[r]) : tw.w2[r]);
   dft16<INV>(v);
   __syncthreads();
 }
 
-// ---- design ---------------------------------------------------------------------------------
+// v[r] = sum over the node's rows of x[w0 + j + 256 r] for r in [r_lo, r_hi) (both channels as
+// re/im), zero elsewhere and outside [0, T). All loads of one row are issued before they are
+// consumed, so a tile waits for memory once per row, not once per load.
+template <bool ADJ>
+__device__ __forceinline__ void gather_window(const GraphView& g, int node, int w0, float2 (&v)[16],
+                                              int r_lo, int r_hi) {
+  const int64_t T = g.T;
+  const int e0 = ADJ ? g.out_ptr[node] : g.in_ptr[node];
+  const int e1 = ADJ ? g.out_ptr[node + 1] : g.in_ptr[node + 1];
+  const int j = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+  for (int e = e0; e < e1; ++e) {
+    const float* row = ADJ ? adj_row(g, g.out_dst[e]) : out_row(g, g.in_src[e]);
+    const auto rl = row_rsrc(row, T), rr = row_rsrc(row + T, T);
+    float2 x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int t = w0 + j + 256 * r;
+      x[r] = (r < r_lo || r >= r_hi) ? make_float2(0.f, 0.f)
+                                     : make_float2(bload(rl, t), bload(rr, t));
+    }
+    if (e == e0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = x[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = cadd(v[r], x[r]);
+    }
+  }
+}
+
+// ---- design ----------------------------------------------------------------------------------
+// Cosine sums in double, one output per thread; cos(m theta) follows the Chebyshev recurrence
+// c_{m+1} = 2 cos(theta) c_m - c_{m-1}, so the inner loop is two FMAs and one LDS broadcast.
+
+__device__ __forceinline__ double cos_sum(const double* w, double theta_over_pi) {
+  // sum_{m=1}^{1023} w[m] cos(m theta)
+  const double c1 = cospi(theta_over_pi), two_c1 = 2.0 * c1;
+  double cm = 1.0, c = c1, acc = 0.0;
+  for (int m = 1; m < 1024; ++m) {
+    acc = fma(w[m], c, acc);
+    const double cn = fma(two_c1, c, -cm);
+    cm = c;
+    c = cn;
+  }
+  return acc;
+}
 
 __global__ __launch_bounds__(kBlock) void eq_design_h_kernel(const float* P, double* h) {
   __shared__ double A[1024];
-  __shared__ double cs[2047];
   const int slot = blockIdx.x;
   for (int i = threadIdx.x; i < 1024; i += kBlock) A[i] = exp((double)P[(int64_t)slot * 1024 + i]);
-  for (int i = threadIdx.x; i < 2047; i += kBlock) cs[i] = kCos2047[i];
   __syncthreads();
   const int n = blockIdx.y * kBlock + threadIdx.x;  // 0..1023
-  double acc = 0.0;
-  int m = 0;
-  for (int k = 1; k < 1024; ++k) {
-    m += n;
-    if (m >= 2047) m -= 2047;
-    acc += A[k] * cs[m];
-  }
-  const double h0 = (A[0] + 2.0 * acc) / 2047.0;
+  const double h0 = (A[0] + 2.0 * cos_sum(A, 2.0 * n / 2047.0)) / 2047.0;
   const double win = 0.5 + 0.5 * cospi((double)n / 1023.0);
   h[(int64_t)slot * 1024 + n] = win * h0;
 }
 
 __global__ __launch_bounds__(kBlock) void eq_design_H_kernel(const double* h, float* H) {
   __shared__ double hs[1024];
-  __shared__ double cs[kN];
   const int slot = blockIdx.x;
   for (int i = threadIdx.x; i < 1024; i += kBlock) hs[i] = h[(int64_t)slot * 1024 + i];
-  for (int i = threadIdx.x; i < kN; i += kBlock) cs[i] = kCos4096[i];
   __syncthreads();
   const int k = blockIdx.y * kBlock + threadIdx.x;
   if (k > kN / 2) return;
-  double acc = 0.0;
-  int m = 0;
-  for (int n = 1; n < 1024; ++n) {
-    m = (m + k) & (kN - 1);
-    acc += hs[n] * cs[m];
-  }
-  const float Hk = (float)((hs[0] + 2.0 * acc) / (double)kN);
+  const float Hk = (float)((hs[0] + 2.0 * cos_sum(hs, k / (double)(kN / 2))) / (double)kN);
   float* Hn = H + (int64_t)slot * kN;
   Hn[k] = Hk;
   if (k > 0 && k < kN / 2) Hn[kN - k] = Hk;
@@ -128,24 +166,12 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
   const int tile = lb % tiles, node = node_begin + lb / tiles;
   const int j = threadIdx.x;
   const int64_t T = g.T;
-  const int64_t t0 = (int64_t)tile * kEqHop;
-  const int64_t w0 = t0 - kN / 4;  // window start: 1024 samples of history
+  const int t0 = tile * kEqHop;
+  Twiddles tw;
+  load_twiddles(tw);
   float2 v[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-  const int e0 = g.in_ptr[node], e1 = g.in_ptr[node + 1];
-  for (int e = e0; e < e1; ++e) {
-    const float* row = out_row(g, g.in_src[e]);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t t = w0 + j + 256 * r;
-      if (t >= 0 && t < T) {
-        v[r].x += row[t];
-        v[r].y += row[T + t];
-      }
-    }
-  }
-  fft4096<false>(v, lds);
+  gather_window<false>(g, node, t0 - kN / 4, v, 0, 16);  // window: 1024 samples of history
+  fft4096<false>(v, lds, tw);
   const float* Hn = H + (int64_t)g.param_row[node] * kN;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -153,11 +179,11 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
     v[r].x *= hk;
     v[r].y *= hk;
   }
-  fft4096<true>(v, lds);
+  fft4096<true>(v, lds, tw);
   float* y = U + (int64_t)node * 2 * T;
 #pragma unroll
   for (int r = 4; r < 12; ++r) {
-    const int64_t t = t0 + j + 256 * (r - 4);
+    const int t = t0 + j + 256 * (r - 4);
     if (t < T) {
       y[t] = v[r].x;
       y[T + t] = v[r].y;
@@ -166,11 +192,15 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
 }
 
 // ---- adjoint ----------------------------------------------------------------------------------
+// Per tile: FFT of the output-adjoint window (kept in LDS), times H and inverse FFT for the input
+// adjoint, FFT of the zero-padded input tile, cross-spectrum accumulated in registers over the
+// block's group of tiles.
 
 __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, const float* H,
                                                         int node_begin, int tiles, int groups,
                                                         int tiles_per_group, float2* Cpart) {
   __shared__ float2 lds[kLds];
+  __shared__ float2 keep[kN];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int group = lb % groups, node = node_begin + lb / groups;
   const int j = threadIdx.x;
@@ -178,90 +208,70 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   const int slot = g.param_row[node];
   const float* Hn = H + (int64_t)slot * kN;
   float* d = dU + (int64_t)node * 2 * T;
-  const int o0 = g.out_ptr[node], o1 = g.out_ptr[node + 1];
-  const int i0 = g.in_ptr[node], i1 = g.in_ptr[node + 1];
+  Twiddles tw;
+  load_twiddles(tw);
   float2 C[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) C[r] = make_float2(0.f, 0.f);
   const int tile_end = min(tiles, (group + 1) * tiles_per_group);
   for (int tile = group * tiles_per_group; tile < tile_end; ++tile) {
-    const int64_t t0 = (int64_t)tile * kEqHop;
-    const int64_t w0 = t0 - kN / 4;
-    float2 v[16], c[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-    for (int e = o0; e < o1; ++e) {  // output adjoint over the window
-      const float* row = adj_row(g, g.out_dst[e]);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t t = w0 + j + 256 * r;
-        if (t >= 0 && t < T) {
-          v[r].x += row[t];
-          v[r].y += row[T + t];
-        }
-      }
-    }
-    fft4096<false>(v, lds);
+    const int t0 = tile * kEqHop;
+    float2 v[16];
+    gather_window<true>(g, node, t0 - kN / 4, v, 0, 16);
+    fft4096<false>(v, lds, tw);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      c[r] = v[r];
+      keep[j + 256 * r] = v[r];
       const float hk = Hn[j + 256 * r];
       v[r].x *= hk;
       v[r].y *= hk;
     }
-    fft4096<true>(v, lds);
+    fft4096<true>(v, lds, tw);
 #pragma unroll
     for (int r = 4; r < 12; ++r) {
-      const int64_t t = t0 + j + 256 * (r - 4);
+      const int t = t0 + j + 256 * (r - 4);
       if (t < T) {
         d[t] = v[r].x;
         d[T + t] = v[r].y;
       }
     }
-    // input tile, zero-padded to the window (positions 1024..3071)
+    gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded
+    fft4096<false>(v, lds, tw);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-    for (int e = i0; e < i1; ++e) {
-      const float* row = out_row(g, g.in_src[e]);
-#pragma unroll
-      for (int r = 4; r < 12; ++r) {
-        const int64_t t = t0 + j + 256 * (r - 4);
-        if (t < T) {
-          v[r].x += row[t];
-          v[r].y += row[T + t];
-        }
-      }
-    }
-    fft4096<false>(v, lds);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) C[r] = cadd(C[r], cmulc(c[r], v[r]));
+    for (int r = 0; r < 16; ++r) C[r] = cadd(C[r], cmulc(keep[j + 256 * r], v[r]));
   }
   float2* out = Cpart + ((int64_t)slot * groups + group) * kN;
 #pragma unroll
   for (int r = 0; r < 16; ++r) out[j + 256 * r] = C[r];
 }
 
-// Sum the groups' cross-spectra (fixed order), inverse FFT, fold +-n with the window:
+// Sum the groups' cross-spectra per bin (fixed order, double).
+__global__ __launch_bounds__(kBlock) void eq_spec_reduce_kernel(const float2* Cpart, int groups,
+                                                                float2* spec) {
+  const int slot = blockIdx.x, k = blockIdx.y * kBlock + threadIdx.x;
+  const float2* p = Cpart + (int64_t)slot * groups * kN + k;
+  double sx = 0.0, sy = 0.0;
+  for (int gi = 0; gi < groups; ++gi) {
+    const float2 c = p[(int64_t)gi * kN];
+    sx += c.x;
+    sy += c.y;
+  }
+  spec[(int64_t)slot * kN + k] = make_float2((float)sx, (float)sy);
+}
+
+// Inverse FFT of the summed cross-spectrum gives hbar; fold +-n with the window:
 // s[0] = hbar[0], s[n] = v[n] (hbar[n] + hbar[-n]).
-__global__ __launch_bounds__(kBlock) void eq_grad_reduce_kernel(const float2* Cpart, int groups,
-                                                                double* sbuf) {
+__global__ __launch_bounds__(kBlock) void eq_grad_ifft_kernel(const float2* spec, double* sbuf) {
   __shared__ float2 lds[kLds];
   __shared__ float hb[kN];
   const int slot = blockIdx.x;
   const int j = threadIdx.x;
+  Twiddles tw;
+  load_twiddles(tw);
   float2 v[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    double sx = 0.0, sy = 0.0;
-    const float2* p = Cpart + (int64_t)slot * groups * kN + j + 256 * r;
-    for (int gi = 0; gi < groups; ++gi) {
-      const float2 c = p[(int64_t)gi * kN];
-      sx += c.x;
-      sy += c.y;
-    }
-    v[r] = make_float2((float)sx, (float)sy);
-  }
-  fft4096<true>(v, lds);
+  for (int r = 0; r < 16; ++r) v[r] = spec[(int64_t)slot * kN + j + 256 * r];
+  fft4096<true>(v, lds, tw);
 #pragma unroll
   for (int r = 0; r < 16; ++r) hb[j + 256 * r] = v[r].x * (1.0f / kN);
   __syncthreads();
@@ -277,22 +287,15 @@ __global__ __launch_bounds__(kBlock) void eq_grad_reduce_kernel(const float2* Cp
   }
 }
 
+// dL/dp_k = (kappa_k / 2047) A_k (s[0] + sum_{n>=1} s[n] cos(2 pi k n / 2047)).
 __global__ __launch_bounds__(kBlock) void eq_grad_p_kernel(const float* P, const double* sbuf,
                                                            float* dP) {
   __shared__ double s[1024];
-  __shared__ double cs[2047];
   const int slot = blockIdx.x;
   for (int i = threadIdx.x; i < 1024; i += kBlock) s[i] = sbuf[(int64_t)slot * 1024 + i];
-  for (int i = threadIdx.x; i < 2047; i += kBlock) cs[i] = kCos2047[i];
   __syncthreads();
   const int k = blockIdx.y * kBlock + threadIdx.x;  // 0..1023
-  double acc = 0.0;
-  int m = 0;
-  for (int n = 1; n < 1024; ++n) {
-    m += k;
-    if (m >= 2047) m -= 2047;
-    acc += s[n] * cs[m];
-  }
+  const double acc = cos_sum(s, 2.0 * k / 2047.0);
   const double A = exp((double)P[(int64_t)slot * 1024 + k]);
   const double kappa = k == 0 ? 1.0 : 2.0;
   dP[(int64_t)slot * 1024 + k] = (float)(kappa / 2047.0 * A * (s[0] + acc));
@@ -336,9 +339,10 @@ hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node
 }
 
 hipError_t launch_eq_grad(const float* P, const float2* Cpart, int n_eq, int groups,
-                          double* sbuf, float* dP, hipStream_t s) {
+                          float2* spec, double* sbuf, float* dP, hipStream_t s) {
   if (n_eq <= 0) return hipSuccess;
-  eq_grad_reduce_kernel<<<n_eq, kBlock, 0, s>>>(Cpart, groups, sbuf);
+  eq_spec_reduce_kernel<<<dim3(n_eq, kN / kBlock), kBlock, 0, s>>>(Cpart, groups, spec);
+  eq_grad_ifft_kernel<<<n_eq, kBlock, 0, s>>>(spec, sbuf);
   eq_grad_p_kernel<<<dim3(n_eq, 1024 / kBlock), kBlock, 0, s>>>(P, sbuf, dP);
   return hipGetLastError();
 }

@@ -32,19 +32,25 @@ hipError_t launch_eq_fwd(const GraphView& g, float* U, const float* H, int node_
 // Cpart: float2 [n_eq][groups][4096]
 hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node_begin,
                          int n_nodes, float2* Cpart, hipStream_t s);
-// sbuf: double [n_eq][1024] scratch; dP: float [n_eq][1024]
+// spec: float2 [n_eq][4096] and sbuf: double [n_eq][1024] scratch; dP: float [n_eq][1024]
 hipError_t launch_eq_grad(const float* P, const float2* Cpart, int n_eq, int groups,
-                          double* sbuf, float* dP, hipStream_t s);
+                          float2* spec, double* sbuf, float* dP, hipStream_t s);
 
 // ---- compressor (k_comp.hip) ---------------------------------------------------------------
 constexpr int kCompChunk = 2048;
 int comp_chunks(int64_t T);
-// agg, carry: double [n_comp][chunks]; part: double [n_comp][chunks][4]
+// agg, ragg: uint64 [n_comp][chunks] published chunk totals (reset to "not ready" before each
+// pass); carry: double [n_comp][chunks] envelope entering each chunk (forward, kept for the
+// adjoint); part: double [n_comp][chunks][4]; ticket: one counter per launch (reset to 0);
+// err: error word (bit 0: a wait ran out, bit 1: tickets were not reset)
+hipError_t launch_comp_reset(uint64_t* tot, int64_t n, unsigned* tickets, int n_tickets,
+                             hipStream_t s);
 hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int node_begin,
-                           int n_nodes, double* agg, double* carry, hipStream_t s);
+                           int n_nodes, uint64_t* agg, double* carry, unsigned* ticket,
+                           unsigned* err, hipStream_t s);
 hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
-                           int n_nodes, const double* carry, double* ragg, double* rcarry,
-                           double* part, hipStream_t s);
+                           int n_nodes, const double* carry, uint64_t* ragg, double* part,
+                           unsigned* ticket, unsigned* err, hipStream_t s);
 
 // ---- delay (k_delay.hip) -------------------------------------------------------------------
 constexpr int kDelayTaps = 5, kDelayFir = 39, kDelaySlot = 4410;
