@@ -100,7 +100,7 @@ def stored_traffic(kernel_type: str, direction: str, workload: str):
         key = f"{direction}:{kernel_type}:{workload}"
         ent = rec.get(key)
         if ent and ent.get("src_sha256") == hashlib.sha256(src).hexdigest():
-            return ent.get("bytes_per_step")
+            return ent.get("bytes_per_launch")
     except Exception:  # noqa: BLE001
         return None
     return None

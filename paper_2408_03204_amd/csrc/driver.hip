@@ -30,8 +30,8 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   L.eq_H = take(n_eq * kEqFFT * sizeof(float));
   L.comp_agg = take(n_comp * chunks * sizeof(uint64_t));
   L.comp_carry = take(n_comp * chunks * sizeof(double));
-  // one ticket counter per step (forward), one per step (adjoint), then the error word
-  L.comp_tickets = take((2 * (size_t)(h->N + 1) + 1) * sizeof(unsigned));
+  // one ticket counter per compressor node (forward), one per node (adjoint), the error word
+  L.comp_tickets = take((2 * n_comp + 1) * sizeof(unsigned));
   L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
   L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
   L.fwd_end = off;
@@ -99,11 +99,11 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
 }
 
 unsigned* tickets(void* ws, const WsLayout& L, const grafx_schedule_t* h, bool bwd) {
-  return at<unsigned>(ws, L.comp_tickets) + (bwd ? h->N + 1 : 0);
+  return at<unsigned>(ws, L.comp_tickets) + (bwd ? h->type_count[GRAFX_COMPRESSOR] : 0);
 }
 
 unsigned* error_word(void* ws, const WsLayout& L, const grafx_schedule_t* h) {
-  return at<unsigned>(ws, L.comp_tickets) + 2 * (h->N + 1);
+  return at<unsigned>(ws, L.comp_tickets) + 2 * h->type_count[GRAFX_COMPRESSOR];
 }
 
 // Reset the compressor chaining state of one pass (all compressor nodes, all steps).
@@ -112,8 +112,8 @@ hipError_t reset_comp(const grafx_schedule_t* h, void* ws, const WsLayout& L, bo
   const int n_comp = h->type_count[GRAFX_COMPRESSOR];
   if (n_comp == 0) return hipSuccess;
   uint64_t* tot = at<uint64_t>(ws, bwd ? L.comp_ragg : L.comp_agg);
-  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd),
-                           h->N + 1, stream);
+  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd), n_comp,
+                           stream);
 }
 
 hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
@@ -133,7 +133,7 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
     case GRAFX_COMPRESSOR:
       return launch_comp_fwd(g, U, p, b, cnt, at<uint64_t>(ws, L.comp_agg),
-                             at<double>(ws, L.comp_carry), tickets(ws, L, h, false) + n,
+                             at<double>(ws, L.comp_carry), tickets(ws, L, h, false),
                              error_word(ws, L, h), stream);
     case GRAFX_DELAY:
       return launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
@@ -163,7 +163,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_COMPRESSOR:
       return launch_comp_bwd(g, dU, p, b, cnt, at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
-                             tickets(ws, L, h, true) + n, error_word(ws, L, h), stream);
+                             tickets(ws, L, h, true), error_word(ws, L, h), stream);
     case GRAFX_DELAY:
       return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
                               b, cnt, at<float>(ws, L.delay_part), stream);

@@ -11,9 +11,9 @@
 // fixed order. Folding totals (never partially folded prefixes) keeps the arithmetic independent
 // of timing, so results are deterministic and do not depend on the schedule.
 //
-// Chunk ids come from an atomic ticket taken when a block starts, so every chunk a block waits
-// for belongs to a block that started earlier and publishes without waiting: the waits always
-// end. A total is published as one 64-bit atomic store at device scope over a "not ready"
+// A block's node comes from its block id; its chunk within the node comes from an atomic ticket
+// on that node's counter, taken when the block starts, so every chunk a block waits for belongs
+// to a block that started earlier and publishes without waiting: the waits always end. A total is published as one 64-bit atomic store at device scope over a "not ready"
 // sentinel and read back by 64-bit atomic loads at device scope (the XCDs do not share an L2;
 // device-scope atomics bypass the non-coherent caches). The reader consumes only that word, so
 // no ordering with other data is needed: the accesses are relaxed, which avoids L2 write-back and
@@ -251,13 +251,13 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
   __shared__ float sl[kChunk], sr[kChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
-  const int tk = take_ticket(ticket, &sh_ticket);
-  if (tk >= n_nodes * chunks) {  // tickets not reset before the launch: do nothing
+  const int node = node_begin + (int)blockIdx.x / chunks;
+  const int slot = g.param_row[node];
+  const int chunk = take_ticket(ticket + slot, &sh_ticket);
+  if (chunk >= chunks) {  // tickets not reset before the launch: do nothing
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
   }
-  const int chunk = tk % chunks, node = node_begin + tk / chunks;
-  const int slot = g.param_row[node];
   const Coef k = load_coef(P, slot);
   const int t0 = chunk * kChunk;
   stage<false>(g, node, t0, sl, sr);
@@ -295,13 +295,14 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   __shared__ float ul[kChunk], ur[kChunk], yl[kChunk], yr[kChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
-  const int tk = take_ticket(ticket, &sh_ticket);
-  if (tk >= n_nodes * chunks) {  // tickets not reset before the launch: do nothing
+  const int node = node_begin + (int)blockIdx.x / chunks;
+  const int slot = g.param_row[node];
+  const int tk = take_ticket(ticket + slot, &sh_ticket);
+  if (tk >= chunks) {  // tickets not reset before the launch: do nothing
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
   }
-  const int chunk = chunks - 1 - tk % chunks, node = node_begin + tk / chunks;
-  const int slot = g.param_row[node];
+  const int chunk = chunks - 1 - tk;
   const Coef k = load_coef(P, slot);
   const int t0 = chunk * kChunk;
   stage<false>(g, node, t0, ul, ur);
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   store_chunk(dU + (int64_t)node * 2 * g.T, g.T, t0, yl, yr);
 }
 
-// Reset the published totals to "not ready" and the tickets to 0 before a pass.
+// Reset the published totals to "not ready" and the per-node tickets to 0 before a pass.
 __global__ __launch_bounds__(kBlock) void comp_reset_kernel(uint64_t* tot, int64_t n,
                                                             unsigned* tickets, int n_tickets) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;

@@ -41,7 +41,7 @@ constexpr int kCompChunk = 2048;
 int comp_chunks(int64_t T);
 // agg, ragg: uint64 [n_comp][chunks] published chunk totals (reset to "not ready" before each
 // pass); carry: double [n_comp][chunks] envelope entering each chunk (forward, kept for the
-// adjoint); part: double [n_comp][chunks][4]; ticket: one counter per launch (reset to 0);
+// adjoint); part: double [n_comp][chunks][4]; ticket: one counter per compressor node (reset to 0);
 // err: error word (bit 0: a wait ran out, bit 1: tickets were not reset)
 hipError_t launch_comp_reset(uint64_t* tot, int64_t n, unsigned* tickets, int n_tickets,
                              hipStream_t s);

@@ -1,8 +1,24 @@
-"""Summarise a rocprofv3 kernel-trace database (rocpd SQLite) into a short text table:
-per kernel, calls, total and average duration (us), share of GPU time.
+"""Summaries of rocprofv3 output databases (rocpd SQLite) as short text tables.
 
-    python -m paper_2408_03204_amd.rocprof_summary <run_results.db> <command> > profiles/<name>.txt
+Kernel durations (from a `--kernel-trace --stats` run):
+
+    python -m paper_2408_03204_amd.rocprof_summary trace <run_results.db> <command...>
+
+HBM traffic per kernel from two PMC runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`) of a
+program that first copies `copy_mib` MiB device-to-device: each counter is scaled by
+(true bytes of that copy) / (what the counter reads for it). Also writes the traffic of one
+step-kernel type to a JSON file keyed "<dir>:<type>:<workload>", with the SHA-256 of the kernel's
+source so the figure is only used while that source is unchanged:
+
+    python -m paper_2408_03204_amd.rocprof_summary pmc <fetch.db> <write.db> <copy_mib> \\
+        <steps> <kernel substring> <key> <source file> <json out> <command...>
 """
+from __future__ import annotations
+
+import collections
+import hashlib
+import json
+import os
 import re
 import sqlite3
 import sys
@@ -13,7 +29,7 @@ def short(name: str) -> str:
     return name.replace("grafx::", "").replace("void ", "")
 
 
-def main(db: str, cmd: str) -> None:
+def trace(db: str, cmd: str) -> None:
     c = sqlite3.connect(db)
     rows = list(c.execute("select name, count(*), sum(duration), avg(duration) from kernels "
                           "group by name order by sum(duration) desc"))
@@ -26,5 +42,53 @@ def main(db: str, cmd: str) -> None:
     print(f"\n{'all kernels':60s} {sum(r[1] for r in rows):6d} {total / 1e3:10.1f}")
 
 
+def _counter(db: str, name: str):
+    c = sqlite3.connect(db)
+    return list(c.execute("select dispatch_id, kernel_name, value from counters_collection "
+                          "where counter_name=? order by dispatch_id", (name,)))
+
+
+def pmc(fetch_db: str, write_db: str, copy_mib: float, steps: int, kernel: str, key: str,
+        source: str, json_out: str, cmd: str) -> None:
+    f, w = _counter(fetch_db, "FETCH_SIZE"), _counter(write_db, "WRITE_SIZE")
+    copy_f = max(v for _, n, v in f if "copyBuffer" in n)
+    copy_w = max(v for _, n, v in w if "copyBuffer" in n)
+    kib = copy_mib * 1024.0
+    sf, sw = kib / copy_f, kib / copy_w
+    agg = collections.defaultdict(lambda: [0, 0.0, 0.0])
+    for (_, n, v), (_, n2, v2) in zip(f, w):
+        if n != n2:
+            raise SystemExit("the two PMC runs dispatched different kernels")
+        a = agg[short(n)]
+        a[0] += 1
+        a[1] += v * sf
+        a[2] += v2 * sw
+    print(f"# rocprofv3 PMC summary: HBM traffic per kernel launch (scaled)\n# command: {cmd}")
+    print(f"# calibration: a {copy_mib:g} MiB device copy reads FETCH_SIZE {copy_f:.1f} KiB and "
+          f"WRITE_SIZE {copy_w:.1f} KiB -> scale fetch x{sf:.4f}, write x{sw:.4f}\n")
+    print(f"{'kernel':50s} {'calls':>6s} {'fetch_KiB/call':>15s} {'write_KiB/call':>15s}")
+    for k, (n, fe, wr) in sorted(agg.items(), key=lambda kv: -(kv[1][1] + kv[1][2])):
+        print(f"{k[:50]:50s} {n:6d} {fe / n:15.1f} {wr / n:15.1f}")
+    hits = [(k, v) for k, v in agg.items() if kernel in k]
+    if len(hits) != 1:
+        raise SystemExit(f"kernel substring {kernel!r} matches {len(hits)} kernels")
+    name, (n, fe, wr) = hits[0]
+    rec = json.load(open(json_out)) if os.path.exists(json_out) else {}
+    rec[key] = {"kernel": name, "launches_per_step": n / steps,
+                "fetch_bytes_per_launch": fe * 1024 / n, "write_bytes_per_launch": wr * 1024 / n,
+                "bytes_per_launch": (fe + wr) * 1024 / n,
+                "src_sha256": hashlib.sha256(open(source, "rb").read()).hexdigest(),
+                "command": cmd}
+    with open(json_out, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    print(f"\n{name}: {(fe + wr) * 1024 / n / 1e6:.1f} MB per launch -> {json_out} [{key}]")
+
+
 if __name__ == "__main__":
-    main(sys.argv[1], " ".join(sys.argv[2:]))
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2], " ".join(sys.argv[3:]))
+    elif sys.argv[1] == "pmc":
+        pmc(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6],
+            sys.argv[7], sys.argv[8], sys.argv[9], " ".join(sys.argv[10:]))
+    else:
+        raise SystemExit(__doc__)
