@@ -1,6 +1,7 @@
 // Render drivers: the host step loops of the batched render (paper Algorithm 1, main loop) and
 // of its adjoint, the plan upload and the workspace layout. Every argument is checked before the
 // first launch; the drivers only enqueue kernels on the caller's stream.
+#include <algorithm>
 #include <cstring>
 
 #include "device_common.h"
@@ -30,8 +31,9 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   L.eq_H = take(n_eq * kEqFFT * sizeof(float));
   L.comp_agg = take(n_comp * chunks * sizeof(uint64_t));
   L.comp_carry = take(n_comp * chunks * sizeof(double));
-  // one ticket counter per compressor node (forward), one per node (adjoint), the error word
-  L.comp_tickets = take((2 * n_comp + 1) * sizeof(unsigned));
+  // one ticket counter per compressor node (forward), one per node (adjoint), each on its own
+  // cache line, then the error word
+  L.comp_tickets = take((2 * n_comp * kCompTicketStride + 1) * sizeof(unsigned));
   L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
   L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
   L.fwd_end = off;
@@ -42,8 +44,14 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.part_tanh = take(h->type_count[GRAFX_TANH] * tiles * sizeof(double));
     L.comp_ragg = take(n_comp * chunks * sizeof(uint64_t));
     L.comp_part = take(n_comp * chunks * 4 * sizeof(double));
-    L.eq_C = take(n_eq * eq_groups(T) * kEqFFT * sizeof(float2));
-    L.eq_spec = take(n_eq * kEqFFT * sizeof(float2));
+    size_t fold = 0;  // EQ adjoint partials of the largest step (reused step after step)
+    for (int n = 1; n <= h->N; ++n) {
+      if (h->step_type[n] != GRAFX_EQ) continue;
+      const int cnt = h->step_ptr[n + 1] - h->step_ptr[n];
+      fold = std::max(fold, (size_t)cnt * eq_tiles(T));
+    }
+    L.eq_C = take(fold * kEqFoldStride * sizeof(float));
+    L.eq_spec = take(n_eq * kEqFoldStride * sizeof(float));
     L.eq_s = take(n_eq * 1024 * sizeof(double));
     L.delay_part = take(n_del * delay_groups(T) * kDelayCoef * sizeof(float));
   }
@@ -99,11 +107,13 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
 }
 
 unsigned* tickets(void* ws, const WsLayout& L, const grafx_schedule_t* h, bool bwd) {
-  return at<unsigned>(ws, L.comp_tickets) + (bwd ? h->type_count[GRAFX_COMPRESSOR] : 0);
+  return at<unsigned>(ws, L.comp_tickets) +
+         (bwd ? (size_t)h->type_count[GRAFX_COMPRESSOR] * kCompTicketStride : 0);
 }
 
 unsigned* error_word(void* ws, const WsLayout& L, const grafx_schedule_t* h) {
-  return at<unsigned>(ws, L.comp_tickets) + 2 * h->type_count[GRAFX_COMPRESSOR];
+  return at<unsigned>(ws, L.comp_tickets) +
+         (size_t)2 * h->type_count[GRAFX_COMPRESSOR] * kCompTicketStride;
 }
 
 // Reset the compressor chaining state of one pass (all compressor nodes, all steps).
@@ -112,8 +122,8 @@ hipError_t reset_comp(const grafx_schedule_t* h, void* ws, const WsLayout& L, bo
   const int n_comp = h->type_count[GRAFX_COMPRESSOR];
   if (n_comp == 0) return hipSuccess;
   uint64_t* tot = at<uint64_t>(ws, bwd ? L.comp_ragg : L.comp_agg);
-  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd), n_comp,
-                           stream);
+  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd),
+                           n_comp * kCompTicketStride, stream);
 }
 
 hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
@@ -159,7 +169,8 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_TANH:
       return launch_pointwise_bwd(t, g, dU, p, b, cnt, at<double>(ws, L.part_tanh), stream);
     case GRAFX_EQ:
-      return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float2>(ws, L.eq_C), stream);
+      return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float>(ws, L.eq_C),
+                           at<float>(ws, L.eq_spec), stream);
     case GRAFX_COMPRESSOR:
       return launch_comp_bwd(g, dU, p, b, cnt, at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
@@ -263,9 +274,8 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = launch_reduce_partials(at<double>(ws, L.comp_part), h->type_count[GRAFX_COMPRESSOR],
                                chunks, 4, dpar(GRAFX_COMPRESSOR), stream);
   if (e == hipSuccess && dpar(GRAFX_EQ))
-    e = launch_eq_grad(par(GRAFX_EQ), at<float2>(ws, L.eq_C), h->type_count[GRAFX_EQ],
-                       eq_groups(T), at<float2>(ws, L.eq_spec), at<double>(ws, L.eq_s),
-                       dpar(GRAFX_EQ), stream);
+    e = launch_eq_grad(par(GRAFX_EQ), at<float>(ws, L.eq_spec), h->type_count[GRAFX_EQ],
+                       at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
   if (e == hipSuccess && dpar(GRAFX_DELAY))
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
                           h->type_count[GRAFX_DELAY], delay_groups(T), dpar(GRAFX_DELAY), stream);

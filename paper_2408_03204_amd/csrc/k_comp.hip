@@ -12,7 +12,7 @@
 // of timing, so results are deterministic and do not depend on the schedule.
 //
 // A block's node comes from its block id; its chunk within the node comes from an atomic ticket
-// on that node's counter, taken when the block starts, so every chunk a block waits for belongs
+// on that node's counter (one cache line per counter), taken when the block starts, so every chunk a block waits for belongs
 // to a block that started earlier and publishes without waiting: the waits always end. A total is published as one 64-bit atomic store at device scope over a "not ready"
 // sentinel and read back by 64-bit atomic loads at device scope (the XCDs do not share an L2;
 // device-scope atomics bypass the non-coherent caches). The reader consumes only that word, so
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
   __shared__ int sh_ticket;
   const int node = node_begin + (int)blockIdx.x / chunks;
   const int slot = g.param_row[node];
-  const int chunk = take_ticket(ticket + slot, &sh_ticket);
+  const int chunk = take_ticket(ticket + (int64_t)slot * kCompTicketStride, &sh_ticket);
   if (chunk >= chunks) {  // tickets not reset before the launch: do nothing
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   __shared__ int sh_ticket;
   const int node = node_begin + (int)blockIdx.x / chunks;
   const int slot = g.param_row[node];
-  const int tk = take_ticket(ticket + slot, &sh_ticket);
+  const int tk = take_ticket(ticket + (int64_t)slot * kCompTicketStride, &sh_ticket);
   if (tk >= chunks) {  // tickets not reset before the launch: do nothing
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;

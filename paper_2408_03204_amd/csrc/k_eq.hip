@@ -18,10 +18,14 @@
 //
 // Adjoint: the input adjoint is the same filter applied to the output adjoint (h is even). The
 // FIR gradient hbar[n] = sum_{c,t} ybar_c[t] u_c[t - n] is the real part of a complex
-// correlation, accumulated per tile as W'[k] conj(U_tile[k]) (ybar window spectrum times the
-// conjugate spectrum of the zero-padded input tile); each block sums the cross-spectra of a
-// fixed group of tiles, the groups are summed in a fixed order, one inverse FFT gives hbar, and
-// the chain rule through the design gives dL/dp_k = (kappa_k / 2047) A_k sum_n hbar[n] v[n]
+// correlation, accumulated per tile as C[k] = W'[k] conj(U_tile[k]) (ybar window spectrum times
+// the conjugate spectrum of the zero-padded input tile). The design is even in n, so only
+// hbar[n] + hbar[-n] matters: the inverse transform of the real, even sequence
+// F[k] = Re C[k] + Re C[N - k], of which N/2 + 1 values are kept. Each block handles one tile
+// and writes its folded F; right after the step the tiles' F are summed per node in a fixed
+// order, which does not depend on how nodes are grouped into steps, so results do not depend on
+// the schedule. After the last step one inverse FFT per node gives hbar[n] + hbar[-n], and the
+// chain rule through the design gives dL/dp_k = (kappa_k / 2047) A_k sum_n hbar[n] v[n]
 // cos(2 pi k n / 2047).
 #include "device_common.h"
 #include "grafx_internal.h"
@@ -193,16 +197,13 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
 
 // ---- adjoint ----------------------------------------------------------------------------------
 // Per tile: FFT of the output-adjoint window (kept in LDS), times H and inverse FFT for the input
-// adjoint, FFT of the zero-padded input tile, cross-spectrum accumulated in registers over the
-// block's group of tiles.
-
+// adjoint, FFT of the zero-padded input tile, cross-spectrum folded and written per tile.
 __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, const float* H,
-                                                        int node_begin, int tiles, int groups,
-                                                        int tiles_per_group, float2* Cpart) {
+                                                        int node_begin, int tiles, float* Fpart) {
   __shared__ float2 lds[kLds];
   __shared__ float2 keep[kN];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int group = lb % groups, node = node_begin + lb / groups;
+  const int tile = lb % tiles, i_node = lb / tiles, node = node_begin + i_node;
   const int j = threadIdx.x;
   const int64_t T = g.T;
   const int slot = g.param_row[node];
@@ -210,58 +211,65 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   float* d = dU + (int64_t)node * 2 * T;
   Twiddles tw;
   load_twiddles(tw);
-  float2 C[16];
+  const int t0 = tile * kEqHop;
+  float2 v[16];
+  gather_window<true>(g, node, t0 - kN / 4, v, 0, 16);
+  fft4096<false>(v, lds, tw);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) C[r] = make_float2(0.f, 0.f);
-  const int tile_end = min(tiles, (group + 1) * tiles_per_group);
-  for (int tile = group * tiles_per_group; tile < tile_end; ++tile) {
-    const int t0 = tile * kEqHop;
-    float2 v[16];
-    gather_window<true>(g, node, t0 - kN / 4, v, 0, 16);
-    fft4096<false>(v, lds, tw);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      keep[j + 256 * r] = v[r];
-      const float hk = Hn[j + 256 * r];
-      v[r].x *= hk;
-      v[r].y *= hk;
-    }
-    fft4096<true>(v, lds, tw);
-#pragma unroll
-    for (int r = 4; r < 12; ++r) {
-      const int t = t0 + j + 256 * (r - 4);
-      if (t < T) {
-        d[t] = v[r].x;
-        d[T + t] = v[r].y;
-      }
-    }
-    gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded
-    fft4096<false>(v, lds, tw);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) C[r] = cadd(C[r], cmulc(keep[j + 256 * r], v[r]));
+  for (int r = 0; r < 16; ++r) {
+    keep[j + 256 * r] = v[r];
+    const float hk = Hn[j + 256 * r];
+    v[r].x *= hk;
+    v[r].y *= hk;
   }
-  float2* out = Cpart + ((int64_t)slot * groups + group) * kN;
+  fft4096<true>(v, lds, tw);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) out[j + 256 * r] = C[r];
+  for (int r = 4; r < 12; ++r) {
+    const int t = t0 + j + 256 * (r - 4);
+    if (t < T) {
+      d[t] = v[r].x;
+      d[T + t] = v[r].y;
+    }
+  }
+  gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded
+  fft4096<false>(v, lds, tw);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) keep[j + 256 * r] = cmulc(keep[j + 256 * r], v[r]);
+  // fold F[k] = Re C[k] + Re C[N - k], k = 0..N/2 (bins of other threads: through LDS)
+  __syncthreads();
+  float* out = Fpart + ((int64_t)i_node * tiles + tile) * kEqFoldStride;
+  for (int k = j; k <= kN / 2; k += kBlock) out[k] = keep[k].x + keep[(kN - k) & (kN - 1)].x;
 }
 
-// Sum the groups' cross-spectra per bin (fixed order, double).
-__global__ __launch_bounds__(kBlock) void eq_spec_reduce_kernel(const float2* Cpart, int groups,
-                                                                float2* spec) {
-  const int slot = blockIdx.x, k = blockIdx.y * kBlock + threadIdx.x;
-  const float2* p = Cpart + (int64_t)slot * groups * kN + k;
-  double sx = 0.0, sy = 0.0;
-  for (int gi = 0; gi < groups; ++gi) {
-    const float2 c = p[(int64_t)gi * kN];
-    sx += c.x;
-    sy += c.y;
+// Sum the folded cross-spectra of the tiles of one step's nodes per bin, in double and in a fixed
+// order: wave w of a block sums tiles w, w + 4, w + 8, ... of 64 bins, then the four wave sums
+// are added in order.
+__global__ __launch_bounds__(kBlock) void eq_fold_reduce_kernel(const int32_t* param_row,
+                                                                int node_begin, const float* Fpart,
+                                                                int tiles, float* F) {
+  __shared__ double part[4][64];
+  const int i_node = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = blockIdx.y * 64 + lane;
+  const bool live = k <= kN / 2;
+  double s = 0.0;
+  if (live) {
+    const float* p = Fpart + (int64_t)i_node * tiles * kEqFoldStride + k;
+#pragma unroll 8
+    for (int t = w; t < tiles; t += 4) s += p[(int64_t)t * kEqFoldStride];
   }
-  spec[(int64_t)slot * kN + k] = make_float2((float)sx, (float)sy);
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && live) {
+    const int slot = param_row[node_begin + i_node];
+    F[(int64_t)slot * kEqFoldStride + k] =
+        (float)(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+  }
 }
 
-// Inverse FFT of the summed cross-spectrum gives hbar; fold +-n with the window:
-// s[0] = hbar[0], s[n] = v[n] (hbar[n] + hbar[-n]).
-__global__ __launch_bounds__(kBlock) void eq_grad_ifft_kernel(const float2* spec, double* sbuf) {
+// The inverse FFT of the folded cross-spectrum gives hbar[n] + hbar[-n]; with the window,
+// s[0] = hbar[0] and s[n] = v[n] (hbar[n] + hbar[-n]).
+__global__ __launch_bounds__(kBlock) void eq_grad_ifft_kernel(const float* F, double* sbuf) {
   __shared__ float2 lds[kLds];
   __shared__ float hb[kN];
   const int slot = blockIdx.x;
@@ -270,7 +278,10 @@ __global__ __launch_bounds__(kBlock) void eq_grad_ifft_kernel(const float2* spec
   load_twiddles(tw);
   float2 v[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = spec[(int64_t)slot * kN + j + 256 * r];
+  for (int r = 0; r < 16; ++r) {
+    const int k = j + 256 * r;
+    v[r] = make_float2(F[(int64_t)slot * kEqFoldStride + (k <= kN / 2 ? k : kN - k)], 0.f);
+  }
   fft4096<true>(v, lds, tw);
 #pragma unroll
   for (int r = 0; r < 16; ++r) hb[j + 256 * r] = v[r].x * (1.0f / kN);
@@ -278,10 +289,10 @@ __global__ __launch_bounds__(kBlock) void eq_grad_ifft_kernel(const float2* spec
   for (int n = j; n < 1024; n += kBlock) {
     double s;
     if (n == 0) {
-      s = hb[0];
+      s = 0.5 * (double)hb[0];
     } else {
       const double win = 0.5 + 0.5 * cospi((double)n / 1023.0);
-      s = win * ((double)hb[n] + (double)hb[kN - n]);
+      s = win * (double)hb[n];
     }
     sbuf[(int64_t)slot * 1024 + n] = s;
   }
@@ -305,17 +316,6 @@ __global__ __launch_bounds__(kBlock) void eq_grad_p_kernel(const float* P, const
 
 int eq_tiles(int64_t T) { return (int)((T + kEqHop - 1) / kEqHop); }
 
-static int eq_tiles_per_group(int64_t T) {
-  const int tiles = eq_tiles(T);
-  int tpg = tiles / 32;
-  return tpg < 1 ? 1 : (tpg > 8 ? 8 : tpg);
-}
-
-int eq_groups(int64_t T) {
-  const int tpg = eq_tiles_per_group(T);
-  return (eq_tiles(T) + tpg - 1) / tpg;
-}
-
 hipError_t launch_eq_design(const float* P, int n_eq, double* h, float* H, hipStream_t s) {
   if (n_eq <= 0) return hipSuccess;
   eq_design_h_kernel<<<dim3(n_eq, 1024 / kBlock), kBlock, 0, s>>>(P, h);
@@ -331,18 +331,19 @@ hipError_t launch_eq_fwd(const GraphView& g, float* U, const float* H, int node_
 }
 
 hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node_begin,
-                         int n_nodes, float2* Cpart, hipStream_t s) {
-  const int tiles = eq_tiles(g.T), groups = eq_groups(g.T), tpg = eq_tiles_per_group(g.T);
-  eq_bwd_kernel<<<(unsigned)(groups * n_nodes), kBlock, 0, s>>>(g, dU, H, node_begin, tiles,
-                                                                groups, tpg, Cpart);
+                         int n_nodes, float* Fpart, float* F, hipStream_t s) {
+  const int tiles = eq_tiles(g.T);
+  eq_bwd_kernel<<<(unsigned)(tiles * n_nodes), kBlock, 0, s>>>(g, dU, H, node_begin, tiles,
+                                                               Fpart);
+  eq_fold_reduce_kernel<<<dim3(n_nodes, (kN / 2 + 64) / 64), kBlock, 0, s>>>(
+      g.param_row, node_begin, Fpart, tiles, F);
   return hipGetLastError();
 }
 
-hipError_t launch_eq_grad(const float* P, const float2* Cpart, int n_eq, int groups,
-                          float2* spec, double* sbuf, float* dP, hipStream_t s) {
+hipError_t launch_eq_grad(const float* P, const float* F, int n_eq, double* sbuf, float* dP,
+                          hipStream_t s) {
   if (n_eq <= 0) return hipSuccess;
-  eq_spec_reduce_kernel<<<dim3(n_eq, kN / kBlock), kBlock, 0, s>>>(Cpart, groups, spec);
-  eq_grad_ifft_kernel<<<n_eq, kBlock, 0, s>>>(spec, sbuf);
+  eq_grad_ifft_kernel<<<n_eq, kBlock, 0, s>>>(F, sbuf);
   eq_grad_p_kernel<<<dim3(n_eq, 1024 / kBlock), kBlock, 0, s>>>(P, sbuf, dP);
   return hipGetLastError();
 }

@@ -24,25 +24,28 @@ hipError_t launch_reduce_partials(const double* part, int n_slots, int tiles, in
 constexpr int kEqFFT = 4096;  // overlap-save FFT size
 constexpr int kEqHop = 2048;  // outputs per tile
 int eq_tiles(int64_t T);
-int eq_groups(int64_t T);      // tile groups per node in the adjoint (partial spectra per node)
+constexpr int kEqFoldStride = 2112;  // N/2 + 1 = 2049 folded bins, padded to 256 bytes
 // h: double [n_eq][1024] (windowed FIR, taps n = 0..1023; even), H: float [n_eq][4096]
 hipError_t launch_eq_design(const float* P, int n_eq, double* h, float* H, hipStream_t s);
 hipError_t launch_eq_fwd(const GraphView& g, float* U, const float* H, int node_begin,
                          int n_nodes, hipStream_t s);
-// Cpart: float2 [n_eq][groups][4096]
+// Adjoint of one step. Fpart: float [n_nodes][tiles][kEqFoldStride] scratch; F: float
+// [n_eq][kEqFoldStride]: the rows (by parameter slot) of the step's nodes are written.
 hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node_begin,
-                         int n_nodes, float2* Cpart, hipStream_t s);
-// spec: float2 [n_eq][4096] and sbuf: double [n_eq][1024] scratch; dP: float [n_eq][1024]
-hipError_t launch_eq_grad(const float* P, const float2* Cpart, int n_eq, int groups,
-                          float2* spec, double* sbuf, float* dP, hipStream_t s);
+                         int n_nodes, float* Fpart, float* F, hipStream_t s);
+// F as written by the adjoint steps; sbuf: double [n_eq][1024] scratch; dP: float [n_eq][1024]
+hipError_t launch_eq_grad(const float* P, const float* F, int n_eq, double* sbuf, float* dP,
+                          hipStream_t s);
 
 // ---- compressor (k_comp.hip) ---------------------------------------------------------------
 constexpr int kCompChunk = 2048;
 int comp_chunks(int64_t T);
 // agg, ragg: uint64 [n_comp][chunks] published chunk totals (reset to "not ready" before each
 // pass); carry: double [n_comp][chunks] envelope entering each chunk (forward, kept for the
-// adjoint); part: double [n_comp][chunks][4]; ticket: one counter per compressor node (reset to 0);
-// err: error word (bit 0: a wait ran out, bit 1: tickets were not reset)
+// adjoint); part: double [n_comp][chunks][4]; ticket: one counter per compressor node (reset to 0),
+// kCompTicketStride words apart so that no two counters share a cache line (atomics on one line
+// serialise); err: error word (bit 0: a wait ran out, bit 1: tickets were not reset)
+constexpr int kCompTicketStride = 64;
 hipError_t launch_comp_reset(uint64_t* tot, int64_t n, unsigned* tickets, int n_tickets,
                              hipStream_t s);
 hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int node_begin,
