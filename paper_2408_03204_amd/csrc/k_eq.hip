@@ -121,31 +121,48 @@ __device__ __forceinline__ void gather_window(const GraphView& g, int node, int 
 }
 
 // ---- design ----------------------------------------------------------------------------------
-// Cosine sums in double, one output per thread; cos(m theta) follows the Chebyshev recurrence
-// c_{m+1} = 2 cos(theta) c_m - c_{m-1}, so the inner loop is two FMAs and one LDS broadcast.
+// Cosine sums in double, eight lanes per output: lane q sums the terms m = q, q + 8, ... with the
+// stride-8 Chebyshev recurrence c_{m+8} = 2 cos(8 theta) c_m - c_{m-8}, so each lane's dependent
+// chain is 128 FMAs long; the eight partial sums are combined by a fixed xor butterfly (addition
+// is commutative, so all eight lanes end with the same value).
+
+constexpr int kCosLanes = 8;
 
 __device__ __forceinline__ double cos_sum(const double* w, double theta_over_pi) {
   // sum_{m=1}^{1023} w[m] cos(m theta)
-  const double c1 = cospi(theta_over_pi), two_c1 = 2.0 * c1;
-  double cm = 1.0, c = c1, acc = 0.0;
-  for (int m = 1; m < 1024; ++m) {
-    acc = fma(w[m], c, acc);
-    const double cn = fma(two_c1, c, -cm);
+  const int q = (int)threadIdx.x & (kCosLanes - 1);
+  const double two_c8 = 2.0 * cospi(kCosLanes * theta_over_pi);
+  double cm = cospi((q - kCosLanes) * theta_over_pi), c = cospi(q * theta_over_pi);
+  double acc = q > 0 ? w[q] * c : 0.0;  // the m = 0 term is not part of the sum
+  {
+    const double cn = fma(two_c8, c, -cm);
     cm = c;
     c = cn;
   }
+#pragma unroll 8
+  for (int i = 1; i < 1024 / kCosLanes; ++i) {  // the same trip count on every lane
+    acc = fma(w[q + kCosLanes * i], c, acc);
+    const double cn = fma(two_c8, c, -cm);
+    cm = c;
+    c = cn;
+  }
+#pragma unroll
+  for (int d = 1; d < kCosLanes; d <<= 1) acc += __shfl_xor(acc, d, 64);
   return acc;
 }
+
+// Outputs handled by one block of the design kernels (kCosLanes threads per output).
+constexpr int kCosOut = kBlock / kCosLanes;
 
 __global__ __launch_bounds__(kBlock) void eq_design_h_kernel(const float* P, double* h) {
   __shared__ double A[1024];
   const int slot = blockIdx.x;
   for (int i = threadIdx.x; i < 1024; i += kBlock) A[i] = exp((double)P[(int64_t)slot * 1024 + i]);
   __syncthreads();
-  const int n = blockIdx.y * kBlock + threadIdx.x;  // 0..1023
+  const int n = blockIdx.y * kCosOut + (int)threadIdx.x / kCosLanes;  // 0..1023
   const double h0 = (A[0] + 2.0 * cos_sum(A, 2.0 * n / 2047.0)) / 2047.0;
   const double win = 0.5 + 0.5 * cospi((double)n / 1023.0);
-  h[(int64_t)slot * 1024 + n] = win * h0;
+  if ((threadIdx.x & (kCosLanes - 1)) == 0) h[(int64_t)slot * 1024 + n] = win * h0;
 }
 
 __global__ __launch_bounds__(kBlock) void eq_design_H_kernel(const double* h, float* H) {
@@ -153,9 +170,10 @@ __global__ __launch_bounds__(kBlock) void eq_design_H_kernel(const double* h, fl
   const int slot = blockIdx.x;
   for (int i = threadIdx.x; i < 1024; i += kBlock) hs[i] = h[(int64_t)slot * 1024 + i];
   __syncthreads();
-  const int k = blockIdx.y * kBlock + threadIdx.x;
-  if (k > kN / 2) return;
+  const int k = blockIdx.y * kCosOut + (int)threadIdx.x / kCosLanes;
+  if (k > kN / 2) return;  // whole groups of kCosLanes lanes leave together
   const float Hk = (float)((hs[0] + 2.0 * cos_sum(hs, k / (double)(kN / 2))) / (double)kN);
+  if ((threadIdx.x & (kCosLanes - 1)) != 0) return;
   float* Hn = H + (int64_t)slot * kN;
   Hn[k] = Hk;
   if (k > 0 && k < kN / 2) Hn[kN - k] = Hk;
@@ -305,8 +323,9 @@ __global__ __launch_bounds__(kBlock) void eq_grad_p_kernel(const float* P, const
   const int slot = blockIdx.x;
   for (int i = threadIdx.x; i < 1024; i += kBlock) s[i] = sbuf[(int64_t)slot * 1024 + i];
   __syncthreads();
-  const int k = blockIdx.y * kBlock + threadIdx.x;  // 0..1023
+  const int k = blockIdx.y * kCosOut + (int)threadIdx.x / kCosLanes;  // 0..1023
   const double acc = cos_sum(s, 2.0 * k / 2047.0);
+  if ((threadIdx.x & (kCosLanes - 1)) != 0) return;
   const double A = exp((double)P[(int64_t)slot * 1024 + k]);
   const double kappa = k == 0 ? 1.0 : 2.0;
   dP[(int64_t)slot * 1024 + k] = (float)(kappa / 2047.0 * A * (s[0] + acc));
@@ -318,8 +337,8 @@ int eq_tiles(int64_t T) { return (int)((T + kEqHop - 1) / kEqHop); }
 
 hipError_t launch_eq_design(const float* P, int n_eq, double* h, float* H, hipStream_t s) {
   if (n_eq <= 0) return hipSuccess;
-  eq_design_h_kernel<<<dim3(n_eq, 1024 / kBlock), kBlock, 0, s>>>(P, h);
-  eq_design_H_kernel<<<dim3(n_eq, (kN / 2 + kBlock) / kBlock), kBlock, 0, s>>>(h, H);
+  eq_design_h_kernel<<<dim3(n_eq, 1024 / kCosOut), kBlock, 0, s>>>(P, h);
+  eq_design_H_kernel<<<dim3(n_eq, (kN / 2 + kCosOut) / kCosOut), kBlock, 0, s>>>(h, H);
   return hipGetLastError();
 }
 
@@ -344,7 +363,7 @@ hipError_t launch_eq_grad(const float* P, const float* F, int n_eq, double* sbuf
                           hipStream_t s) {
   if (n_eq <= 0) return hipSuccess;
   eq_grad_ifft_kernel<<<n_eq, kBlock, 0, s>>>(F, sbuf);
-  eq_grad_p_kernel<<<dim3(n_eq, 1024 / kBlock), kBlock, 0, s>>>(P, sbuf, dP);
+  eq_grad_p_kernel<<<dim3(n_eq, 1024 / kCosOut), kBlock, 0, s>>>(P, sbuf, dP);
   return hipGetLastError();
 }
 

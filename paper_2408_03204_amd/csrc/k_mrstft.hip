@@ -3,12 +3,17 @@
 // frames inside [0, T), S = sqrt(|X|^2 + 1e-8),
 // L = (1/3) sum_r ( ||S_y - S_t||_F / ||S_t||_F + mean |ln S_y - ln S_t| ).
 //
-// One block per (frame, row, resolution): both channels of a frame ride in one complex FFT
-// (left + i right) and are separated through conjugate symmetry; per-block partial sums (double)
-// are reduced in a fixed order by a single block. The adjoint rebuilds each frame's spectra,
-// forms dL/dX per bin, assembles the Hermitian spectrum whose inverse transform is the windowed
-// frame gradient (again both channels in one complex transform), and an overlap-add pass sums,
-// for every sample, the frames that cover it in a fixed order.
+// A group of G threads per frame (one wave for N = 512 and 1024, two waves for N = 2048), several
+// frames per block. Both channels of a frame ride in one complex FFT (left + i right) held in
+// registers, N/G points per thread: one radix-N/G pass in registers, then two passes whose
+// radices multiply to G, exchanging through the group's own LDS slice; a one-wave group needs no
+// block-wide barrier. The two spectra of a frame (output and target) are kept in LDS, where the
+// channel spectra are separated through conjugate symmetry (bins k and N - k).
+// Per-block partial sums (double) are reduced in a fixed order by a single block. The adjoint
+// rebuilds each frame's spectra, forms dL/dX per bin, assembles the Hermitian spectrum whose
+// inverse transform is the windowed frame gradient (again both channels in one complex
+// transform), and an overlap-add pass sums, for every sample, the frames that cover it in a
+// fixed order.
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
@@ -17,14 +22,19 @@
 namespace grafx {
 namespace {
 
-constexpr double kMagEps = 1e-8;
+constexpr float kMagEps = 1e-8f;
 constexpr int kRes[3] = {512, 1024, 2048};
+constexpr int kWaves = kBlock / 64;
 
 int frames_of(int64_t T, int r) { return T >= r ? (int)((T - r) / (r / 4) + 1) : 0; }
+int frames_per_block(int r) { return r == 2048 ? kBlock / 128 : kBlock / 64; }
+int blocks_of(int64_t T, int r) {
+  return (frames_of(T, r) + frames_per_block(r) - 1) / frames_per_block(r);
+}
 
 struct Layout {
-  size_t consts;     // double [3][2]: (c_sc, c_lm) per resolution; then loss parts
-  size_t part[3];    // double [F_r * rows][3]
+  size_t consts;     // double [3][2]: (c_sc, c_lm) per resolution
+  size_t part[3];    // double [blocks_r * rows][3]
   size_t fb[3];      // float [rows][F_r][2][r] frame gradients
   size_t total;
 };
@@ -34,54 +44,118 @@ Layout layout(int rows, int64_t T) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   L.consts = take(8 * sizeof(double));
-  for (int i = 0; i < 3; ++i) L.part[i] = take((size_t)frames_of(T, kRes[i]) * rows * 3 * sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    L.part[i] = take((size_t)blocks_of(T, kRes[i]) * rows * 3 * sizeof(double));
   for (int i = 0; i < 3; ++i)
     L.fb[i] = take((size_t)rows * frames_of(T, kRes[i]) * 2 * kRes[i] * sizeof(float));
   L.total = off;
   return L;
 }
 
-template <bool INV>
-__device__ __forceinline__ float2 twid(int m) {
-  const float2 w = kTw4096[m];
+// exp(-+2 pi i q / N), q in [0, N)
+template <int N, bool INV>
+__device__ __forceinline__ float2 twid(int q) {
+  const float2 w = kTw4096[q * (4096 / N)];
   return INV ? make_float2(w.x, -w.y) : w;
 }
 
-template <int N, int R, int NS, bool INV>
-__device__ __forceinline__ void stockham_pass(const float2* in, float2* out) {
-  constexpr int L = N / R;
-  for (int j = threadIdx.x; j < L; j += kBlock) {
-    const int k = j % NS;
-    float2 v[R];
+__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> 4); }
+
+// LDS accesses of one wave are executed in order; this keeps the compiler from moving them across
+// a phase boundary of the wave's exchange and waits for the wave's outstanding LDS operations.
+__device__ __forceinline__ void wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <bool INV>
+__device__ __forceinline__ void dft32(float2* v) {
+  // 32 = 2 x 16: n = 2 n1 + n2, k = k1 + 16 k2
+  float2 e[16], o[16];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[j + r * L];
-    if (NS > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid<INV>(r * k * (4096 / (NS * R))));
-    }
-    dft_r<R, INV>(v);
-    const int base = (j / NS) * NS * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[base + r * NS] = v[r];
+  for (int i = 0; i < 16; ++i) {
+    e[i] = v[2 * i];
+    o[i] = v[2 * i + 1];
   }
-  __syncthreads();
+  dft16<INV>(e);
+  dft16<INV>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float2 t = k == 0 ? o[0] : cmul(o[k], twid<32, INV>(k));
+    v[k] = cadd(e[k], t);
+    v[k + 16] = csub(e[k], t);
+  }
 }
 
-// Three-pass Stockham FFT in LDS: input in a, output in b (a is clobbered).
+template <int P, bool INV>
+__device__ __forceinline__ void dft_p(float2* v) {
+  if constexpr (P == 32) dft32<INV>(v);
+  else dft_r<P, INV>(v);
+}
+
+// Threads per frame and the first cross-thread radix for each resolution.
+template <int N> struct Grp { static constexpr int G = 64, R1 = 8; };
+template <> struct Grp<2048> { static constexpr int G = 128, R1 = 16; };
+
+// Exchange boundary of a group: a one-wave group only orders its own LDS accesses; larger groups
+// synchronise the block (all groups of a block run the same code path).
+template <int G>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (G == 64) wave_sync();
+  else __syncthreads();
+}
+
+// In-place N-point DFT over a group of G threads (forward exp(-2 pi i nk/N), inverse exp(+...),
+// unnormalised). On entry v[m] holds x[j + G m] for thread j of the group; on exit X[j + G m].
+// s: the group's LDS slice of lpad(N - 1) + 1 entries. Stockham passes: radix P = N/G
+// (sub-transform size 1), radix R1 (size P), radix R2 = G/R1 (size P R1).
 template <int N, bool INV>
-__device__ __forceinline__ void lds_fft(float2* a, float2* b) {
-  if constexpr (N == 512) {
-    stockham_pass<N, 8, 1, INV>(a, b);
-    stockham_pass<N, 8, 8, INV>(b, a);
-    stockham_pass<N, 8, 64, INV>(a, b);
-  } else if constexpr (N == 1024) {
-    stockham_pass<N, 16, 1, INV>(a, b);
-    stockham_pass<N, 16, 16, INV>(b, a);
-    stockham_pass<N, 4, 256, INV>(a, b);
-  } else {
-    stockham_pass<N, 16, 1, INV>(a, b);
-    stockham_pass<N, 16, 16, INV>(b, a);
-    stockham_pass<N, 8, 256, INV>(a, b);
+__device__ __forceinline__ void group_fft(float2 (&v)[N / Grp<N>::G], float2* s, int j) {
+  constexpr int G = Grp<N>::G, P = N / G, R1 = Grp<N>::R1, R2 = G / R1;
+  static_assert(P % R1 == 0 && P % R2 == 0, "radices must divide the points per thread");
+  dft_p<P, INV>(v);
+#pragma unroll
+  for (int r = 0; r < P; ++r) s[lpad(P * j + r)] = v[r];
+  group_sync<G>();
+  {  // butterflies b = j + G h, inputs b + (N/R1) r, twiddles exp(-+2 pi i r (b mod P) / (R1 P))
+#pragma unroll
+    for (int h = 0; h < P / R1; ++h)
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[R1 * h + r] = s[lpad(j + G * h + (N / R1) * r)];
+    group_sync<G>();
+    const int k = j % P;
+    float2 w[R1];
+#pragma unroll
+    for (int r = 1; r < R1; ++r) w[r] = twid<N, INV>(r * k * (N / (R1 * P)));
+#pragma unroll
+    for (int h = 0; h < P / R1; ++h) {
+      float2* u = v + R1 * h;
+#pragma unroll
+      for (int r = 1; r < R1; ++r) u[r] = cmul(u[r], w[r]);
+      dft_r<R1, INV>(u);
+      const int b = j + G * h;
+      const int base = (b / P) * P * R1 + k;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) s[lpad(base + P * r)] = u[r];
+    }
+    group_sync<G>();
+  }
+  {  // butterflies b = j + G h, inputs b + (N/R2) r, twiddles exp(-+2 pi i r b / N)
+#pragma unroll
+    for (int h = 0; h < P / R2; ++h)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[R2 * h + r] = s[lpad(j + G * h + (N / R2) * r)];
+    group_sync<G>();
+    float2 o[P];
+#pragma unroll
+    for (int h = 0; h < P / R2; ++h) {
+      float2* u = v + R2 * h;
+      const int b = j + G * h;
+#pragma unroll
+      for (int r = 1; r < R2; ++r) u[r] = cmul(u[r], twid<N, INV>(r * b));
+      dft_r<R2, INV>(u);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) o[h + (P / R2) * r] = u[r];  // X[j + G (h + (P/R2) r)]
+    }
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = o[m];
   }
 }
 
@@ -90,13 +164,23 @@ __device__ __forceinline__ float hann(int n) {
   return 0.5f - 0.5f * kTw4096[n * (4096 / N)].x;
 }
 
-// Load one windowed stereo frame as left + i right.
+// Forward transform of one windowed stereo frame (left + i right) by thread j of its group; the
+// spectrum is left in s at lpad(k).
 template <int N>
-__device__ __forceinline__ void load_frame(const float* row, int64_t T, int64_t s0, float2* a) {
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+__device__ __forceinline__ void frame_spectrum(const float* row, int64_t T, int64_t s0, float2* s,
+                                               int j) {
+  constexpr int G = Grp<N>::G, P = N / G;
+  float2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int n = j + G * m;
     const float w = hann<N>(n);
-    a[n] = make_float2(w * row[s0 + n], w * row[T + s0 + n]);
+    v[m] = make_float2(w * row[s0 + n], w * row[T + s0 + n]);
   }
+  group_fft<N, false>(v, s, j);
+  group_sync<G>();
+#pragma unroll
+  for (int m = 0; m < P; ++m) s[lpad(j + G * m)] = v[m];
 }
 
 // Separate the spectra of the two real channels from Z = FFT(l + i r).
@@ -105,121 +189,180 @@ __device__ __forceinline__ void split(float2 zk, float2 znk, float2& xl, float2&
   xr = make_float2(0.5f * (zk.y + znk.y), -0.5f * (zk.x - znk.x));
 }
 
-__device__ __forceinline__ double mag(float2 x) {
-  return sqrt((double)x.x * x.x + (double)x.y * x.y + kMagEps);
+// Per-bin arithmetic is in float (the spectra themselves are float); sums are kept in double.
+__device__ __forceinline__ float mag(float2 x) {
+  return sqrtf(fmaf(x.x, x.x, fmaf(x.y, x.y, kMagEps)));
+}
+
+// Bins k = j + G i of thread j (i < N/(2G)), and bin N/2 on thread 0: every bin of [0, N/2] once.
+template <int N, typename F>
+__device__ __forceinline__ void for_half_bins(int j, F&& fn) {
+  constexpr int G = Grp<N>::G;
+#pragma unroll 2
+  for (int i = 0; i < N / (2 * G); ++i) fn(j + G * i);
+  if (j == 0) fn(N / 2);
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void stats_kernel(int rows, int64_t T, const float* Y,
-                                                       const float* tgt, double* part) {
-  __shared__ float2 a[N], b[N], c[N], d[N];
-  __shared__ double red[4];
-  const int f = blockIdx.x, row = blockIdx.y;
-  const int64_t s0 = (int64_t)f * (N / 4);
-  load_frame<N>(Y + (int64_t)row * 2 * T, T, s0, a);
-  load_frame<N>(tgt + (int64_t)row * 2 * T, T, s0, c);
-  __syncthreads();
-  lds_fft<N, false>(a, b);
-  lds_fft<N, false>(c, d);
-  double sd = 0.0, st = 0.0, sl = 0.0;
-  for (int k = threadIdx.x; k <= N / 2; k += kBlock) {
-    float2 yl, yr, tl, tr;
-    split(b[k], b[(N - k) & (N - 1)], yl, yr);
-    split(d[k], d[(N - k) & (N - 1)], tl, tr);
-    const double my[2] = {mag(yl), mag(yr)}, mt[2] = {mag(tl), mag(tr)};
+__global__ __launch_bounds__(kBlock) void stats_kernel(int rows, int64_t T, int frames,
+                                                       const float* Y, const float* tgt,
+                                                       double* part) {
+  constexpr int G = Grp<N>::G, FPB = kBlock / G, S = lpad(N - 1) + 1;
+  __shared__ float2 lds[FPB * 2 * S];
+  __shared__ double red[kWaves][3];
+  const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
+  const int f = blockIdx.x * FPB + grp, row = blockIdx.y;
+  const bool live = f < frames;  // uniform over the group
+  double acc[3] = {0.0, 0.0, 0.0};  // sum (S_y - S_t)^2, sum S_t^2, sum |ln S_y - ln S_t|
+  if (G == 64 ? live : true) {  // multi-wave groups keep every barrier convergent
+    float2* sy = lds + grp * 2 * S;
+    float2* st = sy + S;
+    const int64_t s0 = (int64_t)(live ? f : frames - 1) * (N / 4);
+    frame_spectrum<N>(Y + (int64_t)row * 2 * T, T, s0, sy, j);
+    frame_spectrum<N>(tgt + (int64_t)row * 2 * T, T, s0, st, j);
+    group_sync<G>();
+    if (live)
+      for_half_bins<N>(j, [&](int k) {
+        const int nk = (N - k) & (N - 1);
+        float2 yl, yr, tl, tr;
+        split(sy[lpad(k)], sy[lpad(nk)], yl, yr);
+        split(st[lpad(k)], st[lpad(nk)], tl, tr);
+        const float my[2] = {mag(yl), mag(yr)}, mt[2] = {mag(tl), mag(tr)};
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-    for (int ch = 0; ch < 2; ++ch) {
-      sd += (my[ch] - mt[ch]) * (my[ch] - mt[ch]);
-      st += mt[ch] * mt[ch];
-      sl += fabs(log(my[ch]) - log(mt[ch]));
-    }
+        for (int ch = 0; ch < 2; ++ch) {
+          const float d = my[ch] - mt[ch];
+          a0 = fmaf(d, d, a0);
+          a1 = fmaf(mt[ch], mt[ch], a1);
+          a2 += fabsf(logf(my[ch]) - logf(mt[ch]));
+        }
+        acc[0] += (double)a0;
+        acc[1] += (double)a1;
+        acc[2] += (double)a2;
+      });
   }
-  sd = block_sum<double>(sd, red);
-  st = block_sum<double>(st, red);
-  sl = block_sum<double>(sl, red);
-  if (threadIdx.x == 0) {
-    double* p = part + ((int64_t)f * rows + row) * 3;
-    p[0] = sd;
-    p[1] = st;
-    p[2] = sl;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) acc[q] = wave_sum<double>(acc[q]);
+  if (l == 0)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) red[w][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) v += red[q][threadIdx.x];
+    part[((int64_t)blockIdx.x * rows + row) * 3 + threadIdx.x] = v;
   }
 }
 
 struct Frames {
-  int F[3];
+  int F[3], B[3];
   double* part[3];
 };
 
+// Fixed-order reduction of the per-block partial sums of all three resolutions.
 __global__ __launch_bounds__(kBlock) void reduce_kernel(int rows, Frames fr, double* consts,
                                                         float* loss) {
-  __shared__ double red[4];
+  __shared__ double red[kWaves][9];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  double s[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    const int n = fr.B[i] * rows;
+    for (int q = threadIdx.x; q < n; q += kBlock) {
+      a0 += fr.part[i][(int64_t)q * 3];
+      a1 += fr.part[i][(int64_t)q * 3 + 1];
+      a2 += fr.part[i][(int64_t)q * 3 + 2];
+    }
+    s[3 * i] = wave_sum<double>(a0);
+    s[3 * i + 1] = wave_sum<double>(a1);
+    s[3 * i + 2] = wave_sum<double>(a2);
+  }
+  if (l == 0)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) red[w][j] = s[j];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   double L = 0.0;
   for (int i = 0; i < 3; ++i) {
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < kWaves; ++q)
+      for (int j = 0; j < 3; ++j) t[j] += red[q][3 * i + j];
     const int n = fr.F[i] * rows;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int q = threadIdx.x; q < n; q += kBlock)
-      for (int j = 0; j < 3; ++j) s[j] += fr.part[i][(int64_t)q * 3 + j];
-    for (int j = 0; j < 3; ++j) s[j] = block_sum<double>(s[j], red);
     if (n > 0) {
-      const double nd = sqrt(s[0]), nt = sqrt(s[1]);
+      const double nd = sqrt(t[0]), nt = sqrt(t[1]);
       const double M = (double)n * 2.0 * (kRes[i] / 2 + 1);
-      L += nd / nt + s[2] / M;
-      if (threadIdx.x == 0) {
-        consts[2 * i] = nd > 0.0 ? 1.0 / (3.0 * nd * nt) : 0.0;
-        consts[2 * i + 1] = 1.0 / (3.0 * M);
-      }
-    } else if (threadIdx.x == 0) {
+      L += nd / nt + t[2] / M;
+      consts[2 * i] = nd > 0.0 ? 1.0 / (3.0 * nd * nt) : 0.0;
+      consts[2 * i + 1] = 1.0 / (3.0 * M);
+    } else {
       consts[2 * i] = consts[2 * i + 1] = 0.0;
     }
   }
-  if (threadIdx.x == 0) *loss = (float)(L / 3.0);
+  *loss = (float)(L / 3.0);
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void grad_kernel(int rows, int64_t T, const float* Y,
-                                                      const float* tgt, const double* consts,
-                                                      int res, const float* dloss, int frames,
-                                                      float* fb) {
-  __shared__ float2 a[N], b[N], c[N], d[N];
-  const int f = blockIdx.x, row = blockIdx.y;
-  const int64_t s0 = (int64_t)f * (N / 4);
-  load_frame<N>(Y + (int64_t)row * 2 * T, T, s0, a);
-  load_frame<N>(tgt + (int64_t)row * 2 * T, T, s0, c);
-  __syncthreads();
-  lds_fft<N, false>(a, b);
-  lds_fft<N, false>(c, d);
+__global__ __launch_bounds__(kBlock) void grad_kernel(int rows, int64_t T, int frames,
+                                                      const float* Y, const float* tgt,
+                                                      const double* consts, int res,
+                                                      const float* dloss, float* fb) {
+  constexpr int G = Grp<N>::G, FPB = kBlock / G, P = N / G, S = lpad(N - 1) + 1;
+  __shared__ float2 lds[FPB * 2 * S];
+  const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
+  const int f = blockIdx.x * FPB + grp, row = blockIdx.y;
+  const bool live = f < frames;  // uniform over the group
+  if (G == 64 && !live) return;  // one-wave groups need no block-wide barrier
+  float2* sy = lds + grp * 2 * S;
+  float2* st = sy + S;
+  const int64_t s0 = (int64_t)(live ? f : frames - 1) * (N / 4);
+  frame_spectrum<N>(Y + (int64_t)row * 2 * T, T, s0, sy, j);
+  frame_spectrum<N>(tgt + (int64_t)row * 2 * T, T, s0, st, j);
+  group_sync<G>();
   const double up = (double)*dloss;
-  const double c_sc = consts[2 * res] * up, c_lm = consts[2 * res + 1] * up;
-  // Hermitian spectrum of the frame gradient, both channels packed: F = F_l + i F_r (into a)
-  for (int k = threadIdx.x; k <= N / 2; k += kBlock) {
-    float2 x[2], t[2];
-    split(b[k], b[(N - k) & (N - 1)], x[0], x[1]);
-    split(d[k], d[(N - k) & (N - 1)], t[0], t[1]);
-    float2 G[2];
+  const float c_sc = (float)(consts[2 * res] * up), c_lm = (float)(consts[2 * res + 1] * up);
+  // Hermitian spectrum of the frame gradient, both channels packed (F = F_l + i F_r), written
+  // over sy: the pair {k, N - k} is read and written by one thread only.
+  for_half_bins<N>(j, [&](int k) {
+    const int nk = (N - k) & (N - 1);
+    float2 x[2], tt[2];
+    split(sy[lpad(k)], sy[lpad(nk)], x[0], x[1]);
+    split(st[lpad(k)], st[lpad(nk)], tt[0], tt[1]);
+    float2 Gc[2];
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch) {
-      const double my = mag(x[ch]), mt = mag(t[ch]);
-      const double dl = log(my) - log(mt);
-      const double sgn = dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0);
-      const double gS = c_sc * (my - mt) + c_lm * sgn / my;
-      G[ch] = make_float2((float)(gS * x[ch].x / my), (float)(gS * x[ch].y / my));
+      const float my = mag(x[ch]), mt = mag(tt[ch]);
+      const float dl = logf(my) - logf(mt);
+      const float sgn = dl > 0.f ? 1.f : (dl < 0.f ? -1.f : 0.f);
+      const float inv = 1.f / my;
+      const float gS = fmaf(c_sc, my - mt, c_lm * sgn * inv) * inv;
+      Gc[ch] = make_float2(gS * x[ch].x, gS * x[ch].y);
     }
     if (k == 0 || k == N / 2) {
-      a[k] = make_float2(G[0].x, G[1].x);
+      sy[lpad(k)] = make_float2(Gc[0].x, Gc[1].x);
     } else {
-      const float2 gl = make_float2(0.5f * G[0].x, 0.5f * G[0].y);
-      const float2 gr = make_float2(0.5f * G[1].x, 0.5f * G[1].y);
-      a[k] = make_float2(gl.x - gr.y, gl.y + gr.x);
-      a[N - k] = make_float2(gl.x + gr.y, -gl.y + gr.x);  // conj(gl) + i conj(gr)
+      const float2 gl = make_float2(0.5f * Gc[0].x, 0.5f * Gc[0].y);
+      const float2 gr = make_float2(0.5f * Gc[1].x, 0.5f * Gc[1].y);
+      sy[lpad(k)] = make_float2(gl.x - gr.y, gl.y + gr.x);
+      sy[lpad(nk)] = make_float2(gl.x + gr.y, -gl.y + gr.x);  // conj(gl) + i conj(gr)
     }
-  }
-  __syncthreads();
-  lds_fft<N, true>(a, b);
+  });
+  group_sync<G>();
+  float2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = sy[lpad(j + G * m)];
+  group_sync<G>();
+  group_fft<N, true>(v, st, j);
+  if (!live) return;
   float* out = fb + ((int64_t)row * frames + f) * 2 * N;
-  for (int n = threadIdx.x; n < N; n += kBlock) {
-    const float w = hann<N>(n);
-    out[n] = w * b[n].x;
-    out[N + n] = w * b[n].y;
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int n = j + G * m;
+    const float wn = hann<N>(n);
+    out[n] = wn * v[m].x;
+    out[N + n] = wn * v[m].y;
   }
 }
 
@@ -259,14 +402,15 @@ hipError_t launch_mrstft_loss(int rows, int64_t T, const float* Y, const float* 
   Frames fr;
   for (int i = 0; i < 3; ++i) {
     fr.F[i] = frames_of(T, kRes[i]);
+    fr.B[i] = blocks_of(T, kRes[i]);
     fr.part[i] = reinterpret_cast<double*>(base + L.part[i]);
   }
   if (fr.F[0] > 0)
-    stats_kernel<512><<<dim3(fr.F[0], rows), kBlock, 0, s>>>(rows, T, Y, tgt, fr.part[0]);
+    stats_kernel<512><<<dim3(fr.B[0], rows), kBlock, 0, s>>>(rows, T, fr.F[0], Y, tgt, fr.part[0]);
   if (fr.F[1] > 0)
-    stats_kernel<1024><<<dim3(fr.F[1], rows), kBlock, 0, s>>>(rows, T, Y, tgt, fr.part[1]);
+    stats_kernel<1024><<<dim3(fr.B[1], rows), kBlock, 0, s>>>(rows, T, fr.F[1], Y, tgt, fr.part[1]);
   if (fr.F[2] > 0)
-    stats_kernel<2048><<<dim3(fr.F[2], rows), kBlock, 0, s>>>(rows, T, Y, tgt, fr.part[2]);
+    stats_kernel<2048><<<dim3(fr.B[2], rows), kBlock, 0, s>>>(rows, T, fr.F[2], Y, tgt, fr.part[2]);
   reduce_kernel<<<1, kBlock, 0, s>>>(rows, fr, reinterpret_cast<double*>(base + L.consts), loss);
   return hipGetLastError();
 }
@@ -284,15 +428,16 @@ hipError_t launch_mrstft_bwd(int rows, int64_t T, const float* Y, const float* t
   float* fb0 = reinterpret_cast<float*>(base + L.fb[0]);
   float* fb1 = reinterpret_cast<float*>(base + L.fb[1]);
   float* fb2 = reinterpret_cast<float*>(base + L.fb[2]);
+  const int B[3] = {blocks_of(T, 512), blocks_of(T, 1024), blocks_of(T, 2048)};
   if (fbs.F[0] > 0)
-    grad_kernel<512><<<dim3(fbs.F[0], rows), kBlock, 0, s>>>(rows, T, Y, tgt, consts, 0, dloss,
-                                                             fbs.F[0], fb0);
+    grad_kernel<512><<<dim3(B[0], rows), kBlock, 0, s>>>(rows, T, fbs.F[0], Y, tgt, consts, 0,
+                                                         dloss, fb0);
   if (fbs.F[1] > 0)
-    grad_kernel<1024><<<dim3(fbs.F[1], rows), kBlock, 0, s>>>(rows, T, Y, tgt, consts, 1, dloss,
-                                                              fbs.F[1], fb1);
+    grad_kernel<1024><<<dim3(B[1], rows), kBlock, 0, s>>>(rows, T, fbs.F[1], Y, tgt, consts, 1,
+                                                          dloss, fb1);
   if (fbs.F[2] > 0)
-    grad_kernel<2048><<<dim3(fbs.F[2], rows), kBlock, 0, s>>>(rows, T, Y, tgt, consts, 2, dloss,
-                                                              fbs.F[2], fb2);
+    grad_kernel<2048><<<dim3(B[2], rows), kBlock, 0, s>>>(rows, T, fbs.F[2], Y, tgt, consts, 2,
+                                                          dloss, fb2);
   const int64_t n = (int64_t)rows * 2 * T;
   ola_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(rows, T, fbs, dY);
   return hipGetLastError();
