@@ -10,7 +10,13 @@ Prints one JSON line with, besides the metric, the HBM roofline of the dominant 
 (algorithmic bytes / its event-timed duration, measured here) and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
 
+The timed step is issued as one HIP-graph replay of the whole step (default: `--mode graph`,
+captured once from the same C-ABI calls); `--mode eager` issues those calls one by one and
+`--mode autograd` goes through torch.autograd. All three are timed and listed in
+`ms_per_step_by_issue`; the reported value is the selected one.
+
     python bench.py [--steps K] [--warmup W] [--workload console|tiny|large] [--method beam]
+                    [--mode graph|eager|autograd]
 """
 from __future__ import annotations
 
@@ -44,6 +50,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="console", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="beam")
+    ap.add_argument("--mode", default="graph", choices=("graph", "eager", "autograd"),
+                    help="how the timed step is issued: one HIP-graph replay of the whole step "
+                         "(default), the same C-ABI calls issued eagerly, or through autograd")
     ap.add_argument("--T", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
@@ -150,7 +159,7 @@ def main():
     import torch
 
     import synth
-    from paper_2408_03204_amd import RenderBuffers, Schedule, mrstft_loss, render
+    from paper_2408_03204_amd import GradStep, RenderBuffers, Schedule, mrstft_loss, render
 
     maker = getattr(synth, WORKLOADS[args.workload])
     w = maker(T=args.T) if args.T else maker()
@@ -175,21 +184,31 @@ def main():
         target = render(sched, S, Ptgt).clone()
     plist = list(P.values())
 
-    def step():
+    def autograd_step():
         Y = render(sched, S, P)
         L = mrstft_loss(Y, target)
         return torch.autograd.grad(L, plist)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    gs = GradStep(sched, S, {t: p.detach() for t, p in P.items()}, target)
+    gs.run()
+    gs.capture()
+    steps = {"graph": gs.replay, "eager": gs.run, "autograd": autograd_step}
+
+    def timed(fn) -> float:
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    modes = {m: timed(fn) for m, fn in steps.items() if m != args.mode}
+    ms = timed(steps[args.mode])  # the reported mode is timed last
+    modes[args.mode] = ms
     node_samples = w.processed_nodes * T
     value = node_samples / (ms * 1e-3)
 
@@ -267,7 +286,9 @@ def main():
            "config": {"workload": w.name, "nodes": g.num_nodes,
                       "processed_nodes": w.processed_nodes, "edges": g.num_edges, "T": T,
                       "schedule": args.method, "steps_in_schedule": sched.num_steps,
-                      "loss": "mrstft 512/1024/2048", "step": "render+loss+adjoint"},
+                      "loss": "mrstft 512/1024/2048", "step": "render+loss+adjoint",
+                      "issue": args.mode},
+           "ms_per_step_by_issue": {m: round(v, 4) for m, v in modes.items()},
            "roofline": roofline, "render_adjoint_steps": steps_hbm, "cpu_baseline": cpu}
     print(json.dumps(out))
 

@@ -239,3 +239,73 @@ class RenderBuffers:
             self.sched._h, self.plan.data_ptr(), self.T, S.data_ptr(),
             _ptrs(_param_list(self.sched, P)), self.U.data_ptr(), dY.data_ptr(),
             self.dU.data_ptr(), self.ws.data_ptr(), self.ws.numel(), n, _stream(self.device)))
+
+
+class GradStep:
+    """One gradient step of the mixing application (paper Sec. 4) with every buffer allocated up
+    front: batched render of the scheduled graph, MRSTFT loss against a fixed target, the loss
+    adjoint and the render adjoint down to per-type parameter gradients (`grads`).
+
+    `run()` enqueues the step's launches on the current stream. `capture()` records the same
+    launches once into a HIP graph and `replay()` re-issues them without host work per launch.
+    Sources, parameters and target are read through their fixed addresses, so in-place updates
+    between replays (an optimiser step on the parameters) are seen by the next replay; the loss
+    lands in `loss`, the gradients in `grads[type]`."""
+
+    def __init__(self, sched: Schedule, S: torch.Tensor, P: dict, target: torch.Tensor):
+        self.sched, self.dev = sched, S.device
+        T = int(S.shape[-1])
+        K, rows = sched.num_inputs, sched.num_outputs
+        if S.dtype != torch.float32 or not S.is_contiguous() or tuple(S.shape) != (K, 2, T):
+            raise ValueError(f"sources must be contiguous float32 [{K}, 2, T]")
+        if target.dtype != torch.float32 or not target.is_contiguous() or \
+                tuple(target.shape) != (rows, 2, T):
+            raise ValueError(f"target must be contiguous float32 [{rows}, 2, T]")
+        self.S, self.target, self.T = S, target, T
+        self.P = _param_list(sched, P)
+        self.buf = RenderBuffers(sched, T, self.dev, with_backward=True)
+        n = ctypes.c_size_t()
+        check(load().grafx_mrstft_workspace_bytes(rows, T, ctypes.byref(n)))
+        self.mws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=self.dev)
+        self.loss = torch.empty((), dtype=torch.float32, device=self.dev)
+        self.dloss = torch.ones((), dtype=torch.float32, device=self.dev)
+        self.dY = torch.empty((rows, 2, T), dtype=torch.float32, device=self.dev)
+        self.grads = {t: torch.empty_like(p) for t, p in enumerate(self.P) if p is not None}
+        self._dP = [self.grads.get(t) for t in range(9)]
+        self.graph = None
+
+    def run(self) -> torch.Tensor:
+        lib, st, b, rows = load(), _stream(self.dev), self.buf, self.sched.num_outputs
+        check(lib.grafx_render(self.sched._h, b.plan.data_ptr(), self.T, self.S.data_ptr(),
+                               _ptrs(self.P), b.U.data_ptr(), b.ws.data_ptr(), b.ws.numel(), st))
+        Y = b.Y
+        check(lib.grafx_mrstft_loss(rows, self.T, Y.data_ptr(), self.target.data_ptr(),
+                                    self.loss.data_ptr(), self.mws.data_ptr(), self.mws.numel(),
+                                    st))
+        check(lib.grafx_mrstft_backward(rows, self.T, Y.data_ptr(), self.target.data_ptr(),
+                                        self.dloss.data_ptr(), self.dY.data_ptr(),
+                                        self.mws.data_ptr(), self.mws.numel(), st))
+        check(lib.grafx_render_backward(
+            self.sched._h, b.plan.data_ptr(), self.T, self.S.data_ptr(), _ptrs(self.P),
+            b.U.data_ptr(), self.dY.data_ptr(), b.dU.data_ptr(), None, _ptrs(self._dP),
+            b.ws.data_ptr(), b.ws.numel(), st))
+        return self.loss
+
+    def capture(self) -> None:
+        """Record `run()` into a HIP graph (after one eager run on a side stream, as graph capture
+        requires)."""
+        side = torch.cuda.Stream(self.dev)
+        side.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.dev).wait_stream(side)
+        torch.cuda.synchronize(self.dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+
+    def replay(self) -> torch.Tensor:
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+        return self.loss
