@@ -49,6 +49,11 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int idx) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
 }
 
+// Raw buffer store: an element index outside the resource's range is dropped by the hardware.
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, idx * 4, 0, 0);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; remap the hardware block id so
 // that every XCD works through one contiguous range of logical blocks (neighbouring time tiles
 // of a node then share an L2, which serves their overlapping halos).

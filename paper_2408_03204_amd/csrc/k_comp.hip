@@ -85,31 +85,40 @@ struct Curve {
   float e, dG, dT, dW, dR;
 };
 
-// e = G_y - G_u of the quadratic-knee curve (Eqs. 10-11) and its partial derivatives.
+// e = G_y - G_u of the quadratic-knee curve (Eqs. 10-11) and its partial derivatives, without
+// branches: the three regions (below the knee, inside it, above it) are selected per lane.
 template <bool GRAD>
 __device__ __forceinline__ Curve curve(float Gu, const Coef& k) {
-  Curve o{0.f, 0.f, 0.f, 0.f, 0.f};
   const float d = Gu - k.thr;
+  const float q = d + k.knee;
   const bool soft = k.knee > 0.f;
-  if (soft ? (Gu < k.thr - k.knee) : (Gu < k.thr)) return o;
-  if (soft && Gu < k.thr + k.knee) {
-    const float q = d + k.knee;
-    o.e = k.c * q * q * k.inv4w;
-    if (GRAD) {
-      o.dG = k.c * q * k.inv2w;
-      o.dT = -o.dG;
-      o.dW = k.c * (q * k.inv2w - q * q * k.inv4w * (2.f * k.inv2w));
-      o.dR = -q * q * k.inv4w * k.invR2;
-    }
-    return o;
-  }
-  o.e = k.c * d;
+  const bool below = soft ? (q < 0.f) : (d < 0.f);  // Gu < T - W (soft) or Gu < T (hard)
+  const bool knee = soft && !below && d < k.knee;   // T - W <= Gu < T + W
+  Curve o;
+  const float e_knee = k.c * q * q * k.inv4w, e_lin = k.c * d;
+  o.e = below ? 0.f : (knee ? e_knee : e_lin);
   if (GRAD) {
-    o.dG = k.c;
-    o.dT = -k.c;
-    o.dR = -d * k.invR2;
+    const float g_knee = k.c * q * k.inv2w;
+    o.dG = below ? 0.f : (knee ? g_knee : k.c);
+    o.dT = -o.dG;
+    const float w_knee = k.c * (q * k.inv2w - q * q * k.inv4w * (2.f * k.inv2w));
+    o.dW = knee ? w_knee : 0.f;
+    const float r_knee = -q * q * k.inv4w * k.invR2, r_lin = -d * k.invR2;
+    o.dR = below ? 0.f : (knee ? r_knee : r_lin);
+  } else {
+    o.dG = o.dT = o.dW = o.dR = 0.f;
   }
   return o;
+}
+
+// ln x and exp x through the hardware base-2 instructions (v_log_f32, v_exp_f32). x > 0 is
+// normal here (the envelope plus 1e-8); the exp argument is a gain in natural-log units, whose
+// relative error grows with its magnitude (about 2e-6 at |x| = 30).
+__device__ __forceinline__ float ln_f(float x) {
+  return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+}
+__device__ __forceinline__ float exp_f(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }
 
 // Chunk scan of s_out = a^8 s_in + B over the block's 256 threads (reversed thread order when
@@ -224,21 +233,20 @@ __device__ __forceinline__ void stage(const GraphView& g, int node, int t0, floa
   }
 }
 
+// x = (u_l + u_r)^2, formed in float and fed to the double envelope recursion.
 __device__ __forceinline__ double energy(const float* sl, const float* sr, int idx) {
-  const double m = (double)sl[idx] + (double)sr[idx];
-  return m * m;
+  const float m = sl[idx] + sr[idx];
+  return (double)(m * m);
 }
 
 __device__ __forceinline__ void store_chunk(float* row, int64_t T, int t0, const float* sl,
                                             const float* sr) {
+  const auto rl = row_rsrc(row, T), rr = row_rsrc(row + T, T);  // samples past T are dropped
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int idx = threadIdx.x + kBlock * q;
-    const int t = t0 + idx;
-    if (t < T) {
-      row[t] = sl[idx];
-      row[T + t] = sr[idx];
-    }
+    bstore(rl, t0 + idx, sl[idx]);
+    bstore(rr, t0 + idx, sr[idx]);
   }
 }
 
@@ -276,8 +284,8 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     s = fma(k.a, s, k.b * energy(sl, sr, i0 + i));
-    const Curve cv = curve<false>(logf((float)(s + kEps)), k);
-    const float gam = expf(cv.e);
+    const Curve cv = curve<false>(ln_f((float)(s + kEps)), k);
+    const float gam = exp_f(cv.e);
     sl[i0 + i] = gam * sl[i0 + i];
     sr[i0 + i] = gam * sr[i0 + i];
   }
@@ -326,8 +334,8 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
       s = fma(k.a, s, k.b * energy(ul, ur, i0 + i));
       gv[i] = s;
       const float gs = (float)(s + kEps);
-      const Curve cv = curve<true>(logf(gs), k);
-      gam[i] = expf(cv.e);
+      const Curve cv = curve<true>(ln_f(gs), k);
+      gam[i] = exp_f(cv.e);
       const float rho = gam[i] * (yl[i0 + i] * ul[i0 + i] + yr[i0 + i] * ur[i0 + i]);
       gbar[i] = rho * cv.dG / gs;
       accT += (double)(rho * cv.dT);
@@ -352,9 +360,9 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
     const double x = energy(ul, ur, i0 + i);
     const double gprev = i > 0 ? gv[i - 1] : E;
     accA += lam * (gprev - x);
-    const double mid = 2.0 * ((double)ul[i0 + i] + (double)ur[i0 + i]) * k.b * lam;
-    yl[i0 + i] = (float)((double)(gam[i] * yl[i0 + i]) + mid);
-    yr[i0 + i] = (float)((double)(gam[i] * yr[i0 + i]) + mid);
+    const float mid = (float)(2.0 * k.b * lam) * (ul[i0 + i] + ur[i0 + i]);
+    yl[i0 + i] = fmaf(gam[i], yl[i0 + i], mid);
+    yr[i0 + i] = fmaf(gam[i], yr[i0 + i], mid);
   }
   const double sA = block_sum<double>(accA, red);
   const double sT = block_sum<double>(accT, red);
