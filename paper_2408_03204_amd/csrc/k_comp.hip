@@ -3,22 +3,27 @@
 //
 // With equal attack and release the energy envelope g[t] = a g[t-1] + (1-a) x[t],
 // x = (u_l + u_r)^2, is a linear one-pole recursion (the untruncated FIR of Eq. 9). It is computed
-// in double as a chunked scan: a block owns a chunk of 2048 samples (256 threads x 8 consecutive
-// samples); a thread folds its 8 samples, a Kogge-Stone scan across the wave and a fold across
-// the 4 waves give every thread its state relative to the chunk start. The chunk then publishes
-// its total (the state it would leave from a zero start) and folds the totals of all earlier
-// chunks of its node, c_k = sum_{j<k} total_j A^(k-1-j), A = a^2048, as one block-wide sum in a
-// fixed order. Folding totals (never partially folded prefixes) keeps the arithmetic independent
-// of timing, so results are deterministic and do not depend on the schedule.
+// in double as a chunked scan: a block owns a chunk of 3072 samples (256 threads x 12 consecutive
+// samples); a thread folds its samples, a Kogge-Stone scan across the wave and a fold across the
+// 4 waves give every thread its state relative to the chunk start. The chunk then publishes its
+// total (the state it would leave from a zero start) and folds the totals of all earlier chunks
+// of its node, c_k = sum_{j<k} total_j A^(k-1-j), A = a^3072, as one block-wide sum in a fixed
+// order. Folding totals (never partially folded prefixes) keeps the arithmetic independent of
+// timing, so results are deterministic and do not depend on the schedule. A block lives through
+// several dependent memory round trips (ticket, loads, publish and wait, stores); the chunk size
+// is chosen so that a 17-node step of 2^18 samples is resident in one round of blocks (24 KB of
+// LDS and at most 80 VGPRs per thread give 6 blocks per CU), since a second round costs a whole
+// block lifetime.
 //
 // A block's node comes from its block id; its chunk within the node comes from an atomic ticket
-// on that node's counter (one cache line per counter), taken when the block starts, so every chunk a block waits for belongs
-// to a block that started earlier and publishes without waiting: the waits always end. A total is published as one 64-bit atomic store at device scope over a "not ready"
-// sentinel and read back by 64-bit atomic loads at device scope (the XCDs do not share an L2;
-// device-scope atomics bypass the non-coherent caches). The reader consumes only that word, so
-// no ordering with other data is needed: the accesses are relaxed, which avoids L2 write-back and
-// invalidation. Every wait is bounded; a wait that runs out records an error word and poisons
-// its result instead of spinning forever.
+// on that node's counter (one cache line per counter), taken when the block starts, so every
+// chunk a block waits for belongs to a block that started earlier and publishes without waiting:
+// the waits always end. A total is published as one 64-bit atomic store at device scope over a
+// "not ready" sentinel and read back by 64-bit atomic loads at device scope (the XCDs do not
+// share an L2; device-scope atomics bypass the non-coherent caches). The reader consumes only
+// that word, so no ordering with other data is needed: the accesses are relaxed, which avoids L2
+// write-back and invalidation. Every wait is bounded; a wait that runs out records an error word
+// and poisons its result instead of spinning forever.
 //
 // The gain curve G_u = ln(g + 1e-8), quadratic knee, gain exp(G_y - G_u) is evaluated in float.
 //
@@ -35,8 +40,8 @@
 namespace grafx {
 namespace {
 
-constexpr int kPer = 8;
-constexpr int kChunk = kCompChunk;  // 256 x 8
+constexpr int kPer = 12;
+constexpr int kChunk = kCompChunk;  // 256 x kPer
 constexpr double kEps = 1e-8;
 constexpr uint64_t kNotReady = ~0ull;
 constexpr int kMaxSpin = 1 << 24;
@@ -47,8 +52,8 @@ struct Coef {
   float c;            // 1/R - 1
   float inv2w, inv4w; // 1/(2W), 1/(4W)
   float invR2;        // 1/R^2
-  double pw[9];       // pw[d] = (a^8)^(2^d); pw[8] = a^2048
-  double logA;        // ln(a^2048)
+  double pw[9];       // pw[d] = (a^kPer)^(2^d); pw[8] = a^kChunk
+  double logA;        // ln(a^kChunk)
 };
 
 __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
@@ -63,16 +68,19 @@ __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
   k.inv2w = k.knee > 0.f ? 1.0f / (2.f * k.knee) : 0.f;
   k.inv4w = k.knee > 0.f ? 1.0f / (4.f * k.knee) : 0.f;
   k.invR2 = 1.0f / (R * R);
-  k.logA = 2048.0 * log(k.a);
-  double q = k.a * k.a;
-  q = q * q;
-  k.pw[0] = q * q;
+  k.logA = (double)kChunk * log(k.a);
+  double q = 1.0, b = k.a;  // a^kPer by binary powering
+  for (int e = kPer; e > 0; e >>= 1) {
+    if (e & 1) q *= b;
+    b *= b;
+  }
+  k.pw[0] = q;
 #pragma unroll
   for (int d = 1; d < 9; ++d) k.pw[d] = k.pw[d - 1] * k.pw[d - 1];
   return k;
 }
 
-// (a^8)^n for 0 <= n < 512
+// (a^kPer)^n for 0 <= n < 512
 __device__ __forceinline__ double pow_a8(const Coef& k, int n) {
   double r = 1.0;
 #pragma unroll
@@ -121,10 +129,10 @@ __device__ __forceinline__ float exp_f(float x) {
   return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }
 
-// Chunk scan of s_out = a^8 s_in + B over the block's 256 threads (reversed thread order when
+// Chunk scan of s_out = a^kPer s_in + B over the block's 256 threads (reversed thread order when
 // REV), from a zero state entering the chunk. Returns the state entering this thread's samples;
 // `total` receives the state leaving the chunk (every thread). Thread J's state for a non-zero
-// entering state c is the returned value plus (a^8)^J' c, J' = J (forward) or 255 - J (REV).
+// entering state c is the returned value plus (a^kPer)^J' c, J' = J (forward) or 255 - J (REV).
 template <bool REV>
 __device__ __forceinline__ double chunk_scan(double B, const Coef& k, double* wtot, double& total) {
   const int lane0 = threadIdx.x & 63, w0 = threadIdx.x >> 6;
@@ -324,23 +332,34 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   double total;
   const double E0 = chunk_scan<false>(B, k, wtot, total);
   const double E = fma(pow_a8(k, scan_index(false)), carry[(int64_t)slot * chunks + chunk], E0);
-  double gv[kPer];
-  float gbar[kPer], gam[kPer];
+  // First pass (forward over the thread's samples): envelope, gain and the local adjoint terms.
+  // What the reverse pass needs is written back over the thread's own LDS slots: ul <- g[t-1] -
+  // x[t], ur <- u_l + u_r, yl/yr <- gain * ybar.
+  float gbar[kPer];
   double accT = 0.0, accW = 0.0, accR = 0.0;
   {
     double s = E;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      s = fma(k.a, s, k.b * energy(ul, ur, i0 + i));
-      gv[i] = s;
+      const int idx = i0 + i;
+      const float u_l = ul[idx], u_r = ur[idx];
+      const float m = u_l + u_r;
+      const double x = (double)(m * m);  // as in energy()
+      const double sprev = s;
+      s = fma(k.a, s, k.b * x);
       const float gs = (float)(s + kEps);
       const Curve cv = curve<true>(ln_f(gs), k);
-      gam[i] = exp_f(cv.e);
-      const float rho = gam[i] * (yl[i0 + i] * ul[i0 + i] + yr[i0 + i] * ur[i0 + i]);
+      const float gam = exp_f(cv.e);
+      const float y_l = yl[idx], y_r = yr[idx];
+      const float rho = gam * (y_l * u_l + y_r * u_r);
       gbar[i] = rho * cv.dG / gs;
       accT += (double)(rho * cv.dT);
       accW += (double)(rho * cv.dW);
       accR += (double)(rho * cv.dR);
+      ul[idx] = (float)(sprev - x);
+      ur[idx] = m;
+      yl[idx] = gam * y_l;
+      yr[idx] = gam * y_r;
     }
   }
   // reverse recursion lambda[t] = gbar[t] + a lambda[t+1]
@@ -356,13 +375,12 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   double accA = 0.0;
 #pragma unroll
   for (int i = kPer - 1; i >= 0; --i) {
+    const int idx = i0 + i;
     lam = fma(k.a, lam, (double)gbar[i]);
-    const double x = energy(ul, ur, i0 + i);
-    const double gprev = i > 0 ? gv[i - 1] : E;
-    accA += lam * (gprev - x);
-    const float mid = (float)(2.0 * k.b * lam) * (ul[i0 + i] + ur[i0 + i]);
-    yl[i0 + i] = fmaf(gam[i], yl[i0 + i], mid);
-    yr[i0 + i] = fmaf(gam[i], yr[i0 + i], mid);
+    accA += lam * (double)ul[idx];
+    const float mid = (float)(2.0 * k.b * lam) * ur[idx];
+    yl[idx] += mid;
+    yr[idx] += mid;
   }
   const double sA = block_sum<double>(accA, red);
   const double sT = block_sum<double>(accT, red);

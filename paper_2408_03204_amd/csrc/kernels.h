@@ -38,7 +38,7 @@ hipError_t launch_eq_grad(const float* P, const float* F, int n_eq, double* sbuf
                           hipStream_t s);
 
 // ---- compressor (k_comp.hip) ---------------------------------------------------------------
-constexpr int kCompChunk = 2048;
+constexpr int kCompChunk = 3072;  // 256 threads x 12 samples
 int comp_chunks(int64_t T);
 // agg, ragg: uint64 [n_comp][chunks] published chunk totals (reset to "not ready" before each
 // pass); carry: double [n_comp][chunks] envelope entering each chunk (forward, kept for the
