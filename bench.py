@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--mode", default="graph", choices=("graph", "eager", "autograd"),
                     help="how the timed step is issued: one HIP-graph replay of the whole step "
                          "(default), the same C-ABI calls issued eagerly, or through autograd")
+    ap.add_argument("--single-mode", action="store_true",
+                    help="time only --mode (no graph capture unless it is the graph mode); for "
+                         "profiler runs, where every kernel launch should belong to the timed mode")
     ap.add_argument("--T", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
@@ -190,9 +193,11 @@ def main():
         return torch.autograd.grad(L, plist)
 
     gs = GradStep(sched, S, {t: p.detach() for t, p in P.items()}, target)
-    gs.run()
-    gs.capture()
-    steps = {"graph": gs.replay, "eager": gs.run, "autograd": autograd_step}
+    wanted = {args.mode} if args.single_mode else {"graph", "eager", "autograd"}
+    if "graph" in wanted:
+        gs.capture()
+    steps = {m: fn for m, fn in (("graph", gs.replay), ("eager", gs.run),
+                                 ("autograd", autograd_step)) if m in wanted}
 
     def timed(fn) -> float:
         for _ in range(args.warmup):
