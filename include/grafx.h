@@ -87,6 +87,7 @@ typedef struct grafx_schedule_sizes {
   int32_t num_outputs; /* |V_N|                                                */
   int32_t type_count[GRAFX_NUM_TYPES]; /* nodes per type                       */
   int64_t plan_bytes;  /* device bytes needed by grafx_plan_upload             */
+  int64_t max_len;     /* largest per-node length (grafx_schedule_with_lengths); 0 otherwise */
 } grafx_schedule_sizes;
 
 /*
@@ -118,6 +119,30 @@ grafx_status grafx_schedule(int32_t num_nodes, const int32_t* node_type, int32_t
                             const int32_t* edge_src, const int32_t* edge_dst,
                             const int32_t* edge_type, int32_t method, int32_t beam_width,
                             int64_t state_limit, grafx_schedule_t** out);
+
+/*
+ * grafx_schedule_with_lengths -- grafx_schedule for a graph whose nodes carry signals of
+ * different lengths: several graphs of different T merged into one schedule (the graph-level
+ * parallelism of paper Sec. 2, "Batched processing": a batch of graphs is one disconnected
+ * graph). Node v's signal is defined on [0, node_len[v]) and is zero beyond: an input node's
+ * source row holds node_len[v] valid samples, every processor sees its inputs as zero past their
+ * lengths, and a processed node's row is computed and written on [0, node_len[v]) only (samples
+ * at or beyond the length are not written). The T passed to the render calls is then the row
+ * stride of S, U, dY and dU and must be >= every length. On a graph whose nodes all have length
+ * T the results equal grafx_schedule's bit for bit. Both ends of every edge must have the same
+ * length (each connected graph has one length), so every graph of a merged batch renders exactly
+ * as it would alone at its own T.
+ *
+ *   node_len  host int32[num_nodes] in node order, each in [1, 2^29)
+ *   (other arguments and errors as grafx_schedule; GRAFX_E_SHAPE for a length out of range or an
+ *   edge between nodes of different lengths)
+ */
+grafx_status grafx_schedule_with_lengths(int32_t num_nodes, const int32_t* node_type,
+                                         int32_t num_edges, const int32_t* edge_src,
+                                         const int32_t* edge_dst, const int32_t* edge_type,
+                                         const int32_t* node_len, int32_t method,
+                                         int32_t beam_width, int64_t state_limit,
+                                         grafx_schedule_t** out);
 
 void grafx_schedule_free(grafx_schedule_t* sched);
 

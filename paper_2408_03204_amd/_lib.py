@@ -17,9 +17,10 @@ STATUS = {0: "GRAFX_OK", 1: "GRAFX_E_ARG", 2: "GRAFX_E_GRAPH", 3: "GRAFX_E_CYCLE
           8: "GRAFX_E_HIP"}
 
 # Symbols declared in include/grafx.h (checked by the CPU test suite).
-EXPORTS = ("grafx_schedule", "grafx_schedule_free", "grafx_schedule_query",
-           "grafx_schedule_export", "grafx_plan_upload", "grafx_workspace_bytes", "grafx_render",
-           "grafx_render_backward", "grafx_render_step", "grafx_render_backward_step", "grafx_mrstft_workspace_bytes", "grafx_mrstft_loss",
+EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free",
+           "grafx_schedule_query", "grafx_schedule_export", "grafx_plan_upload",
+           "grafx_workspace_bytes", "grafx_render", "grafx_render_backward", "grafx_render_step",
+           "grafx_render_backward_step", "grafx_mrstft_workspace_bytes", "grafx_mrstft_loss",
            "grafx_mrstft_backward", "grafx_last_error")
 
 
@@ -34,7 +35,7 @@ class ScheduleSizes(ctypes.Structure):
     _fields_ = [("num_nodes", ctypes.c_int32), ("num_edges", ctypes.c_int32),
                 ("num_steps", ctypes.c_int32), ("num_inputs", ctypes.c_int32),
                 ("num_outputs", ctypes.c_int32), ("type_count", ctypes.c_int32 * NUM_TYPES),
-                ("plan_bytes", ctypes.c_int64)]
+                ("plan_bytes", ctypes.c_int64), ("max_len", ctypes.c_int64)]
 
 
 _lib = None
@@ -56,6 +57,8 @@ def load() -> ctypes.CDLL:
     sig = {
         "grafx_schedule": (i32, [i32, c_i32p, i32, c_i32p, c_i32p, c_i32p, i32, i32, i64,
                                  ctypes.POINTER(vp)]),
+        "grafx_schedule_with_lengths": (i32, [i32, c_i32p, i32, c_i32p, c_i32p, c_i32p, c_i32p,
+                                              i32, i32, i64, ctypes.POINTER(vp)]),
         "grafx_schedule_free": (None, [vp]),
         "grafx_schedule_query": (i32, [vp, ctypes.POINTER(ScheduleSizes)]),
         "grafx_schedule_export": (i32, [vp] + [c_i32p] * 8),

@@ -35,7 +35,10 @@ class Schedule:
     computed on the host by libgrafx (`grafx_schedule`)."""
 
     def __init__(self, node_type, edges, method: str | int = "beam", beam_width: int = 32,
-                 state_limit: int = 1 << 20, edge_type=None):
+                 state_limit: int = 1 << 20, edge_type=None, lengths=None):
+        """`lengths` (optional, per node in node order): signal length of each node, for graphs
+        of different lengths merged into one schedule (`merge_graphs`); the render's T is then
+        the row stride (>= every length)."""
         lib = load()
         nt = np.ascontiguousarray(np.asarray(node_type), dtype=np.int32)
         e = np.asarray(edges, dtype=np.int32).reshape(2, -1)
@@ -44,8 +47,16 @@ class Schedule:
             np.asarray(edge_type), dtype=np.int32).reshape(-1)
         m = METHODS[method] if isinstance(method, str) else int(method)
         h = ctypes.c_void_p()
-        check(lib.grafx_schedule(nt.shape[0], _iptr(nt), e.shape[1], _iptr(src), _iptr(dst),
-                                 _iptr(et), m, beam_width, state_limit, ctypes.byref(h)))
+        if lengths is None:
+            check(lib.grafx_schedule(nt.shape[0], _iptr(nt), e.shape[1], _iptr(src), _iptr(dst),
+                                     _iptr(et), m, beam_width, state_limit, ctypes.byref(h)))
+        else:
+            ln = np.ascontiguousarray(np.asarray(lengths), dtype=np.int32).reshape(-1)
+            if ln.shape[0] != nt.shape[0]:
+                raise ValueError("lengths must have one entry per node")
+            check(lib.grafx_schedule_with_lengths(nt.shape[0], _iptr(nt), e.shape[1], _iptr(src),
+                                                  _iptr(dst), _iptr(et), _iptr(ln), m, beam_width,
+                                                  state_limit, ctypes.byref(h)))
         self._h = h
         s = _lib.ScheduleSizes()
         check(lib.grafx_schedule_query(h, ctypes.byref(s)))
@@ -53,6 +64,7 @@ class Schedule:
         self.num_inputs, self.num_outputs = s.num_inputs, s.num_outputs
         self.type_count = list(s.type_count)
         self.plan_bytes = int(s.plan_bytes)
+        self.max_len = int(s.max_len)
         V, E, N = s.num_nodes, s.num_edges, s.num_steps
         arr = lambda n: np.zeros(max(n, 1), dtype=np.int32)  # noqa: E731
         self.step_type, self.step_ptr, self.perm = arr(N + 1), arr(N + 2), arr(V)
@@ -309,3 +321,50 @@ class GradStep:
             raise RuntimeError("capture() first")
         self.graph.replay()
         return self.loss
+
+
+def merge_graphs(graphs):
+    """Disconnected union of several graphs, so that one schedule renders them all (paper Sec. 2,
+    "Batched processing": a batch of graphs is processed as one graph).
+
+    `graphs`: sequence of (node_type, edges [2, E], T). Nodes and edges are concatenated in graph
+    order, so the merged sources, parameters and outputs are plain concatenations too. Returns a
+    dict: node_type, edges, lengths (each node's graph T), T (the row stride, the largest T), and
+    per graph: node offset, input-row offset (into S), output-row offset (into Y) and, per node
+    type, the parameter-row offset (into P[type])."""
+    nts, eds, lens = [], [], []
+    off = {"node": [], "input": [], "output": [], "param": []}
+    n = 0
+    cnt = np.zeros(9, dtype=np.int64)
+    for node_type, edges, T in graphs:
+        nt = np.asarray(node_type, dtype=np.int32).reshape(-1)
+        e = np.asarray(edges, dtype=np.int64).reshape(2, -1)
+        off["node"].append(n)
+        off["input"].append(int(cnt[TYPE_CODES["in"]]))
+        off["output"].append(int(cnt[TYPE_CODES["out"]]))
+        off["param"].append(cnt.copy())
+        nts.append(nt)
+        eds.append(e + n)
+        lens.append(np.full(nt.shape[0], int(T), dtype=np.int32))
+        n += nt.shape[0]
+        cnt += np.bincount(nt, minlength=9)
+    return {"node_type": np.concatenate(nts), "edges": np.concatenate(eds, axis=1).astype(np.int32),
+            "lengths": np.concatenate(lens), "T": int(max(int(g[2]) for g in graphs)),
+            "node_offset": off["node"], "input_offset": off["input"],
+            "output_offset": off["output"], "param_offset": off["param"]}
+
+
+def merge_inputs(merged, sources, params):
+    """Concatenate per-graph sources ([K_g, 2, T_g] each, zero-padded to the merged T) and
+    parameters (dicts type -> [n_t, N_t]) in graph order, as numpy arrays."""
+    T = merged["T"]
+    S = np.concatenate([np.pad(np.asarray(s, dtype=np.float32),
+                               ((0, 0), (0, 0), (0, T - np.asarray(s).shape[-1])))
+                        for s in sources], axis=0)
+    P = {}
+    for t in range(9):
+        rows = [np.asarray(p[t], dtype=np.float32) for p in params if t in p]
+        rows = [r for r in rows if r.shape[0] > 0]
+        if rows:
+            P[t] = np.ascontiguousarray(np.concatenate(rows, axis=0))
+    return S, P

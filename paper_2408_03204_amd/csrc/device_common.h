@@ -21,10 +21,17 @@ struct GraphView {
   const float* U;            // [V][2][T] node outputs (rows >= K)
   const float* dY;           // [n_out][2][T] output adjoint
   const float* dU;           // [V][2][T] input adjoints (rows of processed nodes)
-  int64_t T;
+  const int32_t* len;        // [V] per-node signal length, or null when every node has length T
+  int64_t T;                 // row stride (and the length of every node when len is null)
   int32_t K;                 // number of input nodes (= sigma positions [0, K))
   int32_t out_begin;         // sigma position of the first output node
+  int32_t vec4;              // T and every node length are multiples of 4 (16-byte vectors)
 };
+
+// Length of the signal of the node at sigma position v (its row holds valid samples [0, len)).
+__device__ __forceinline__ int64_t node_len(const GraphView& g, int v) {
+  return g.len ? (int64_t)g.len[v] : g.T;
+}
 
 // Row (stereo, [2][T]) holding the output of the node at sigma position s.
 __device__ __forceinline__ const float* out_row(const GraphView& g, int s) {

@@ -75,11 +75,13 @@ GraphView make_view(const grafx_schedule_t* h, const void* dev_plan, int64_t T, 
   g.out_ptr = plan + h->layout.out_ptr;
   g.out_dst = plan + h->layout.out_dst;
   g.param_row = plan + h->layout.param_row;
+  g.len = h->node_len.empty() ? nullptr : plan + h->layout.len;
   g.S = S;
   g.U = U;
   g.T = T;
   g.K = h->K;
   g.out_begin = h->step_ptr[h->N];
+  g.vec4 = (T % 4 == 0) && h->len4;
   return g;
 }
 
@@ -89,6 +91,9 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
   if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
   if (!dev_plan) return fail(GRAFX_E_ARG, "plan is NULL");
   if (T < 1) return fail(GRAFX_E_SHAPE, "T must be >= 1");
+  if (h->max_len > T)
+    return fail(GRAFX_E_SHAPE, "T (the row stride) is below the largest node length " +
+                                   std::to_string(h->max_len));
   if (T >= ((int64_t)1 << 29)) return fail(GRAFX_E_SHAPE, "T must be < 2^29");
   if (!U) return fail(GRAFX_E_ARG, "U is NULL");
   if (h->K > 0 && !S) return fail(GRAFX_E_ARG, "S is NULL but the graph has input nodes");

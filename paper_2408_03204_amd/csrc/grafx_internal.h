@@ -23,6 +23,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) & ~(a - 1); }
 // Device plan layout: int32 sections, each starting on a 64-element (256-byte) boundary.
 struct PlanLayout {
   size_t in_ptr, in_src, out_ptr, out_dst, param_row;  // element offsets
+  size_t len;                                            // per-node lengths (if any)
   size_t total;                                          // elements
 };
 
@@ -41,6 +42,9 @@ struct grafx_schedule_t {
   std::vector<int32_t> out_ptr;    // [V+1]
   std::vector<int32_t> out_dst;    // [E]
   std::vector<int32_t> param_row;  // [V]
+  std::vector<int32_t> node_len;   // [V] per-node signal length (sigma order); empty = all T
+  int32_t max_len = 0;             // largest node length (0 when uniform)
+  bool len4 = true;                // every node length is a multiple of 4
   grafx::PlanLayout layout{};
   std::vector<int32_t> plan;       // packed host image of the device plan
 };

@@ -159,6 +159,8 @@ __device__ __forceinline__ double chunk_scan(double B, const Coef& k, double* wt
   return fma(pow_a8(k, lane), P, ex);
 }
 
+__device__ __forceinline__ int comp_chunks_of(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
+
 __device__ __forceinline__ int scan_index(bool rev) {
   return rev ? kBlock - 1 - (int)threadIdx.x : (int)threadIdx.x;
 }
@@ -210,7 +212,7 @@ __device__ __forceinline__ double chunk_carry(uint64_t* tot, int k, int chunks, 
 
 // Gather-sum of a chunk (both channels) into LDS: ADJ = false sums the input edges over U/S,
 // ADJ = true the output edges over dU/dY. Zero beyond T.
-template <bool ADJ>
+template <bool ADJ, bool RAGGED>
 __device__ __forceinline__ void stage(const GraphView& g, int node, int t0, float* sl, float* sr) {
   const int64_t T = g.T;
   const int e0 = ADJ ? g.out_ptr[node] : g.in_ptr[node];
@@ -219,8 +221,10 @@ __device__ __forceinline__ void stage(const GraphView& g, int node, int t0, floa
 #pragma unroll
   for (int q = 0; q < kPer; ++q) l[q] = r[q] = 0.f;
   for (int e = e0; e < e1; ++e) {  // all loads of a row issued before any is consumed
-    const float* row = ADJ ? adj_row(g, g.out_dst[e]) : out_row(g, g.in_src[e]);
-    const auto rl = row_rsrc(row, T), rr = row_rsrc(row + T, T);
+    const int other = ADJ ? g.out_dst[e] : g.in_src[e];
+    const float* row = ADJ ? adj_row(g, other) : out_row(g, other);
+    const int64_t L = RAGGED ? (int64_t)g.len[other] : T;
+    const auto rl = row_rsrc(row, L), rr = row_rsrc(row + T, L);
     float xl[kPer], xr[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -247,9 +251,10 @@ __device__ __forceinline__ double energy(const float* sl, const float* sr, int i
   return (double)(m * m);
 }
 
-__device__ __forceinline__ void store_chunk(float* row, int64_t T, int t0, const float* sl,
-                                            const float* sr) {
-  const auto rl = row_rsrc(row, T), rr = row_rsrc(row + T, T);  // samples past T are dropped
+// Chunk store into a row of stride T; samples at or beyond the node's length Tn are dropped.
+__device__ __forceinline__ void store_chunk(float* row, int64_t T, int64_t Tn, int t0,
+                                            const float* sl, const float* sr) {
+  const auto rl = row_rsrc(row, Tn), rr = row_rsrc(row + T, Tn);
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int idx = threadIdx.x + kBlock * q;
@@ -260,6 +265,7 @@ __device__ __forceinline__ void store_chunk(float* row, int64_t T, int t0, const
 
 // ---- forward ----------------------------------------------------------------------------------
 
+template <bool RAGGED>
 __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U, const float* P,
                                                           int node_begin, int n_nodes, int chunks,
                                                           uint64_t* agg, double* carry,
@@ -274,9 +280,11 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
   }
+  const int64_t Tn = RAGGED ? (int64_t)g.len[node] : g.T;
+  if (RAGGED && chunk >= comp_chunks_of(Tn)) return;  // past the node's length
   const Coef k = load_coef(P, slot);
   const int t0 = chunk * kChunk;
-  stage<false>(g, node, t0, sl, sr);
+  stage<false, RAGGED>(g, node, t0, sl, sr);
   __syncthreads();
   const int i0 = kPer * threadIdx.x;
   double B = 0.0;
@@ -298,11 +306,12 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
     sr[i0 + i] = gam * sr[i0 + i];
   }
   __syncthreads();
-  store_chunk(U + (int64_t)node * 2 * g.T, g.T, t0, sl, sr);
+  store_chunk(U + (int64_t)node * 2 * g.T, g.T, Tn, t0, sl, sr);
 }
 
 // ---- adjoint ----------------------------------------------------------------------------------
 
+template <bool RAGGED>
 __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU, const float* P,
                                                           int node_begin, int n_nodes, int chunks,
                                                           const double* carry, uint64_t* ragg,
@@ -318,11 +327,17 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
   }
-  const int chunk = chunks - 1 - tk;
+  const int64_t Tn = RAGGED ? (int64_t)g.len[node] : g.T;
+  const int chunks_n = RAGGED ? comp_chunks_of(Tn) : chunks;
+  if (RAGGED && tk >= chunks_n) {  // past the node's length: this ticket zeroes one unused partial slot
+    if (threadIdx.x < 4) part[((int64_t)slot * chunks + tk) * 4 + threadIdx.x] = 0.0;
+    return;
+  }
+  const int chunk = chunks_n - 1 - tk;
   const Coef k = load_coef(P, slot);
   const int t0 = chunk * kChunk;
-  stage<false>(g, node, t0, ul, ur);
-  stage<true>(g, node, t0, yl, yr);
+  stage<false, RAGGED>(g, node, t0, ul, ur);
+  stage<true, RAGGED>(g, node, t0, yl, yr);
   __syncthreads();
   const int i0 = kPer * threadIdx.x;
   // envelope rebuilt from the forward carry
@@ -370,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   const double L0 = chunk_scan<true>(R, k, wtot, rtotal);
   uint64_t* rtots = ragg + (int64_t)slot * chunks;
   if (threadIdx.x == 0) publish(rtots + chunk, rtotal);
-  const double rin = chunk_carry<true>(rtots, chunk, chunks, k, err, red);
+  const double rin = chunk_carry<true>(rtots, chunk, chunks_n, k, err, red);  // own chunks
   double lam = fma(pow_a8(k, scan_index(true)), rin, L0);
   double accA = 0.0;
 #pragma unroll
@@ -393,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
     p[2] = sW;
     p[3] = sR;
   }
-  store_chunk(dU + (int64_t)node * 2 * g.T, g.T, t0, yl, yr);
+  store_chunk(dU + (int64_t)node * 2 * g.T, g.T, Tn, t0, yl, yr);
 }
 
 // Reset the published totals to "not ready" and the per-node tickets to 0 before a pass.
@@ -421,8 +436,13 @@ hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int nod
                            int n_nodes, uint64_t* agg, double* carry, unsigned* ticket,
                            unsigned* err, hipStream_t s) {
   const int chunks = comp_chunks(g.T);
-  comp_fwd_kernel<<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(g, U, P, node_begin, n_nodes,
-                                                                  chunks, agg, carry, ticket, err);
+  // per-node lengths get their own instantiation, so the uniform case carries no length code
+  if (g.len)
+    comp_fwd_kernel<true><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
+        g, U, P, node_begin, n_nodes, chunks, agg, carry, ticket, err);
+  else
+    comp_fwd_kernel<false><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
+        g, U, P, node_begin, n_nodes, chunks, agg, carry, ticket, err);
   return hipGetLastError();
 }
 
@@ -430,9 +450,12 @@ hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int no
                            int n_nodes, const double* carry, uint64_t* ragg, double* part,
                            unsigned* ticket, unsigned* err, hipStream_t s) {
   const int chunks = comp_chunks(g.T);
-  comp_bwd_kernel<<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(g, dU, P, node_begin, n_nodes,
-                                                                  chunks, carry, ragg, part, ticket,
-                                                                  err);
+  if (g.len)
+    comp_bwd_kernel<true><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
+        g, dU, P, node_begin, n_nodes, chunks, carry, ragg, part, ticket, err);
+  else
+    comp_bwd_kernel<false><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
+        g, dU, P, node_begin, n_nodes, chunks, carry, ragg, part, ticket, err);
   return hipGetLastError();
 }
 

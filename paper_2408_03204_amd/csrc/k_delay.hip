@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void delay_design_kernel(const float* P, fl
 }
 
 // Stage x[base .. base + kWin) of one channel of a node's gather-sum (in: input edges over U/S,
-// adj: output edges over dU/dY) into LDS, zero outside [0, T).
+// adj: output edges over dU/dY) into LDS, each row zero outside [0, length of its node).
 template <bool ADJ>
 __device__ __forceinline__ void stage_window(const GraphView& g, int node, int c, int64_t base,
                                              int len, float* w) {
@@ -58,10 +58,11 @@ __device__ __forceinline__ void stage_window(const GraphView& g, int node, int c
   for (int idx = threadIdx.x; idx < len; idx += kBlock) {
     const int64_t t = base + idx;
     float s = 0.f;
-    if (t >= 0 && t < T)
+    if (t >= 0)
       for (int e = e0; e < e1; ++e) {
-        const float* row = ADJ ? adj_row(g, g.out_dst[e]) : out_row(g, g.in_src[e]);
-        s += row[(int64_t)c * T + t];
+        const int other = ADJ ? g.out_dst[e] : g.in_src[e];
+        const float* row = ADJ ? adj_row(g, other) : out_row(g, other);
+        if (t < node_len(g, other)) s += row[(int64_t)c * T + t];
       }
     w[idx] = s;
   }
@@ -92,7 +93,8 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
   __shared__ float ys[2][kHop];
   const int tile = blockIdx.x, node = node_begin + blockIdx.y;
   const int slot = g.param_row[node];
-  const int64_t T = g.T, t0 = (int64_t)tile * kHop;
+  const int64_t T = g.T, t0 = (int64_t)tile * kHop, Tn = node_len(g, node);
+  if (t0 >= Tn) return;  // tile past the node's length (uniform over the block)
   const float* cn = taps + (int64_t)slot * kDelayCoef;
   for (int c = 0; c < 2; ++c) {
     float acc[kPer];
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
   float* y = out + (int64_t)node * 2 * T;
   for (int idx = threadIdx.x; idx < kHop; idx += kBlock) {
     const int64_t t = t0 + idx;
-    if (t < T) {
+    if (t < Tn) {
       y[t] = ys[0][idx];
       y[T + t] = ys[1][idx];
     }
@@ -132,7 +134,8 @@ __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, cons
   __shared__ float red[4][kDelayFir];
   const int group = blockIdx.x, node = node_begin + blockIdx.y;
   const int slot = g.param_row[node];
-  const int tile_end = min(tiles, (group + 1) * tpg);
+  const int tiles_n = (int)((node_len(g, node) + kHop - 1) / kHop);  // the node's own tiles
+  const int tile_end = min(min(tiles, tiles_n), (group + 1) * tpg);
   for (int cm = 0; cm < 2 * kDelayTaps; ++cm) {
     const int c = cm / kDelayTaps;
     const int d = offs[(int64_t)slot * 2 * kDelayTaps + cm];
@@ -204,10 +207,9 @@ __global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, cons
 
 int delay_tiles(int64_t T) { return (int)((T + kHop - 1) / kHop); }
 
-static int delay_tpg(int64_t T) {
-  int tpg = delay_tiles(T) / 32;
-  return tpg < 1 ? 1 : (tpg > 8 ? 8 : tpg);
-}
+// Tiles per tap-gradient block: a constant, so a node's partial sums are grouped the same way
+// whatever the row stride T (a graph merged with longer ones gets the same bits as alone).
+static int delay_tpg(int64_t) { return 4; }
 
 int delay_groups(int64_t T) {
   const int tpg = delay_tpg(T);

@@ -89,8 +89,8 @@ __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds, const Twid
 }
 
 // v[r] = sum over the node's rows of x[w0 + j + 256 r] for r in [r_lo, r_hi) (both channels as
-// re/im), zero elsewhere and outside [0, T). All loads of one row are issued before they are
-// consumed, so a tile waits for memory once per row, not once per load.
+// re/im), zero elsewhere and outside [0, length of the row's node). All loads of one row are
+// issued before they are consumed, so a tile waits for memory once per row, not once per load.
 template <bool ADJ>
 __device__ __forceinline__ void gather_window(const GraphView& g, int node, int w0, float2 (&v)[16],
                                               int r_lo, int r_hi) {
@@ -101,8 +101,10 @@ __device__ __forceinline__ void gather_window(const GraphView& g, int node, int 
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
   for (int e = e0; e < e1; ++e) {
-    const float* row = ADJ ? adj_row(g, g.out_dst[e]) : out_row(g, g.in_src[e]);
-    const auto rl = row_rsrc(row, T), rr = row_rsrc(row + T, T);
+    const int other = ADJ ? g.out_dst[e] : g.in_src[e];
+    const float* row = ADJ ? adj_row(g, other) : out_row(g, other);
+    const int64_t L = node_len(g, other);
+    const auto rl = row_rsrc(row, L), rr = row_rsrc(row + T, L);
     float2 x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -187,8 +189,9 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % tiles, node = node_begin + lb / tiles;
   const int j = threadIdx.x;
-  const int64_t T = g.T;
+  const int64_t T = g.T, Tn = node_len(g, node);
   const int t0 = tile * kEqHop;
+  if (t0 >= Tn) return;  // tile past the node's length
   Twiddles tw;
   load_twiddles(tw);
   float2 v[16];
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
 #pragma unroll
   for (int r = 4; r < 12; ++r) {
     const int t = t0 + j + 256 * (r - 4);
-    if (t < T) {
+    if (t < Tn) {
       y[t] = v[r].x;
       y[T + t] = v[r].y;
     }
@@ -223,13 +226,18 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % tiles, i_node = lb / tiles, node = node_begin + i_node;
   const int j = threadIdx.x;
-  const int64_t T = g.T;
+  const int64_t T = g.T, Tn = node_len(g, node);
   const int slot = g.param_row[node];
   const float* Hn = H + (int64_t)slot * kN;
   float* d = dU + (int64_t)node * 2 * T;
+  float* out = Fpart + ((int64_t)i_node * tiles + tile) * kEqFoldStride;
+  const int t0 = tile * kEqHop;
+  if (t0 >= Tn) {  // tile past the node's length: contributes nothing to the gradient
+    for (int k = j; k <= kN / 2; k += kBlock) out[k] = 0.f;
+    return;
+  }
   Twiddles tw;
   load_twiddles(tw);
-  const int t0 = tile * kEqHop;
   float2 v[16];
   gather_window<true>(g, node, t0 - kN / 4, v, 0, 16);
   fft4096<false>(v, lds, tw);
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
 #pragma unroll
   for (int r = 4; r < 12; ++r) {
     const int t = t0 + j + 256 * (r - 4);
-    if (t < T) {
+    if (t < Tn) {
       d[t] = v[r].x;
       d[T + t] = v[r].y;
     }
@@ -255,7 +263,6 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   for (int r = 0; r < 16; ++r) keep[j + 256 * r] = cmulc(keep[j + 256 * r], v[r]);
   // fold F[k] = Re C[k] + Re C[N - k], k = 0..N/2 (bins of other threads: through LDS)
   __syncthreads();
-  float* out = Fpart + ((int64_t)i_node * tiles + tile) * kEqFoldStride;
   for (int k = j; k <= kN / 2; k += kBlock) out[k] = keep[k].x + keep[(kN - k) & (kN - 1)].x;
 }
 

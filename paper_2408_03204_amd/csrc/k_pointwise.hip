@@ -3,10 +3,12 @@
 //
 // Types: mix / out (identity, Eq. 1b only), gain_pan (Eq. 2), imager (Eq. 3), tanh distortion.
 // One block of 256 threads covers 1024 samples of one node (both channels); blockIdx.y picks the
-// node inside the step. With T % 4 == 0 every row is 16-byte aligned and each thread moves one
-// float4 per channel and input; otherwise each thread moves 4 scalars at a 256-sample stride.
-// Inputs are summed in original edge order, so a node's arithmetic does not depend on the step
-// it was batched into.
+// node inside the step. Thread j covers samples 4j..4j+3 of the tile: with T and every node
+// length multiples of 4, rows are 16-byte aligned and it moves one float4 per channel and input;
+// otherwise it moves the 4 samples one by one. Inputs are read through raw buffer resources sized to their node's
+// length, so samples past an input's length read as zero without a branch, and are summed in
+// original edge order, so a node's arithmetic does not depend on the step it was batched into.
+// A node's own samples past its length are neither computed nor stored.
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
@@ -47,23 +49,40 @@ __device__ __forceinline__ void fwd_op(float& l, float& r, Gains k) {
   }
 }
 
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 4, 0, 0));
+}
+
+// n (4 or 1) consecutive floats of a row through a length-bounded buffer resource
+template <bool V4>
+__device__ __forceinline__ void bload_n(__amdgpu_buffer_rsrc_t r, int idx, float* out) {
+  if constexpr (V4) {
+    const float4 a = bload4(r, idx);
+    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+  } else {
+    out[0] = bload(r, idx);
+  }
+}
+
 template <int TYPE, bool V4>
 __global__ __launch_bounds__(kBlock) void pointwise_fwd_kernel(GraphView g, float* U,
                                                                const float* P, int node_begin) {
   const int node = node_begin + blockIdx.y;
-  const int64_t T = g.T;
+  const int64_t T = g.T, Tn = node_len(g, node);
   const Gains k = load_gains<TYPE>(P, g.param_row[node]);
   const int e0 = g.in_ptr[node], e1 = g.in_ptr[node + 1];
   float* y = U + (int64_t)node * 2 * T;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   if constexpr (V4) {
-    const int64_t t = base + 4 * threadIdx.x;
-    if (t >= T) return;
+    const int t = (int)(base + 4 * threadIdx.x);
+    if (t >= Tn) return;
     float4 l = make_float4(0.f, 0.f, 0.f, 0.f), r = l;
     for (int e = e0; e < e1; ++e) {
-      const float* row = out_row(g, g.in_src[e]);
-      const float4 a = *reinterpret_cast<const float4*>(row + t);
-      const float4 b = *reinterpret_cast<const float4*>(row + T + t);
+      const int src = g.in_src[e];
+      const float* row = out_row(g, src);
+      const int64_t Ls = node_len(g, src);
+      const float4 a = bload4(row_rsrc(row, Ls), t);
+      const float4 b = bload4(row_rsrc(row + T, Ls), t);
       l.x += a.x; l.y += a.y; l.z += a.z; l.w += a.w;
       r.x += b.x; r.y += b.y; r.z += b.z; r.w += b.w;
     }
@@ -76,13 +95,15 @@ __global__ __launch_bounds__(kBlock) void pointwise_fwd_kernel(GraphView g, floa
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t t = base + threadIdx.x + q * kBlock;
-      if (t >= T) break;
+      const int t = (int)(base + 4 * threadIdx.x + q);
+      if (t >= Tn) break;
       float l = 0.f, r = 0.f;
       for (int e = e0; e < e1; ++e) {
-        const float* row = out_row(g, g.in_src[e]);
-        l += row[t];
-        r += row[T + t];
+        const int src = g.in_src[e];
+        const float* row = out_row(g, src);
+        const int64_t Ls = node_len(g, src);
+        l += bload(row_rsrc(row, Ls), t);
+        r += bload(row_rsrc(row + T, Ls), t);
       }
       fwd_op<TYPE>(l, r, k);
       y[t] = l;
@@ -144,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, floa
                                                                double* part, int tiles) {
   constexpr int NP = AdjOp<TYPE>::NP;
   const int node = node_begin + blockIdx.y;
-  const int64_t T = g.T;
+  const int64_t T = g.T, Tn = node_len(g, node);
   const int slot = g.param_row[node];
   const Gains k = load_gains<TYPE>(P, slot);
   const int o0 = g.out_ptr[node], o1 = g.out_ptr[node + 1];
@@ -154,19 +175,23 @@ __global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, floa
   float acc[NP > 0 ? NP : 1] = {0.f};
   const int64_t base = (int64_t)blockIdx.x * kTile;
   constexpr int NV = V4 ? 4 : 1;
-  const int64_t t_first = V4 ? base + 4 * threadIdx.x : base + threadIdx.x;
+  // Thread j covers samples base + 4j .. base + 4j + 3 in both paths, so the gradient partials
+  // are accumulated in the same order whichever path a launch takes.
+  const int64_t t_first = base + 4 * threadIdx.x;
 #pragma unroll
   for (int q = 0; q < (V4 ? 1 : 4); ++q) {
-    const int64_t t = V4 ? t_first : t_first + q * kBlock;
-    if (t >= T) break;
+    const int64_t t = t_first + q;
+    if (t >= Tn) break;
     float gl[NV], gr[NV], yl[NV], yr[NV], ul[NV], ur[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) gl[v] = gr[v] = yl[v] = yr[v] = ul[v] = ur[v] = 0.f;
     for (int e = o0; e < o1; ++e) {
-      const float* row = adj_row(g, g.out_dst[e]);
+      const int dnode = g.out_dst[e];
+      const float* row = adj_row(g, dnode);
+      const int64_t Ld = node_len(g, dnode);
       float a[NV], b[NV];
-      load_n<V4>(row + t, a);
-      load_n<V4>(row + T + t, b);
+      bload_n<V4>(row_rsrc(row, Ld), (int)t, a);
+      bload_n<V4>(row_rsrc(row + T, Ld), (int)t, b);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         gl[v] += a[v];
@@ -179,10 +204,12 @@ __global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, floa
     }
     if constexpr (TYPE == GRAFX_TANH) {
       for (int e = i0; e < i1; ++e) {
-        const float* row = out_row(g, g.in_src[e]);
+        const int src = g.in_src[e];
+        const float* row = out_row(g, src);
+        const int64_t Ls = node_len(g, src);
         float a[NV], b[NV];
-        load_n<V4>(row + t, a);
-        load_n<V4>(row + T + t, b);
+        bload_n<V4>(row_rsrc(row, Ls), (int)t, a);
+        bload_n<V4>(row_rsrc(row + T, Ls), (int)t, b);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           ul[v] += a[v];
@@ -224,7 +251,7 @@ template <int TYPE>
 hipError_t launch_fwd_t(const GraphView& g, float* U, const float* P, int node_begin,
                         int n_nodes, hipStream_t s) {
   dim3 grid((unsigned)((g.T + kTile - 1) / kTile), (unsigned)n_nodes);
-  if (g.T % 4 == 0)
+  if (g.vec4)
     pointwise_fwd_kernel<TYPE, true><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
   else
     pointwise_fwd_kernel<TYPE, false><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
@@ -236,7 +263,7 @@ hipError_t launch_bwd_t(const GraphView& g, float* dst, const float* P, int node
                         int n_nodes, double* part, hipStream_t s) {
   const int tiles = (int)((g.T + kTile - 1) / kTile);
   dim3 grid((unsigned)tiles, (unsigned)n_nodes);
-  if (g.T % 4 == 0)
+  if (g.vec4)
     pointwise_bwd_kernel<TYPE, true><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part, tiles);
   else
     pointwise_bwd_kernel<TYPE, false><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part, tiles);

@@ -182,6 +182,34 @@ grafx_status replay(const Graph& g, const std::vector<int8_t>& types,
 }  // namespace
 }  // namespace grafx
 
+namespace grafx {
+namespace {
+
+// Packed host image of the device plan: int32 sections on 64-element boundaries.
+void build_plan(grafx_schedule_t* h) {
+  const size_t V = h->V, E = h->E;
+  PlanLayout& L = h->layout;
+  size_t off = 0;
+  auto take = [&](size_t n) { size_t o = off; off = align_up(off + n, 64); return o; };
+  L.in_ptr = take(V + 1);
+  L.in_src = take(E);
+  L.out_ptr = take(V + 1);
+  L.out_dst = take(E);
+  L.param_row = take(V);
+  L.len = take(h->node_len.size());
+  L.total = off;
+  h->plan.assign(L.total, 0);
+  std::copy(h->in_ptr.begin(), h->in_ptr.end(), h->plan.begin() + L.in_ptr);
+  std::copy(h->in_src.begin(), h->in_src.end(), h->plan.begin() + L.in_src);
+  std::copy(h->out_ptr.begin(), h->out_ptr.end(), h->plan.begin() + L.out_ptr);
+  std::copy(h->out_dst.begin(), h->out_dst.end(), h->plan.begin() + L.out_dst);
+  std::copy(h->param_row.begin(), h->param_row.end(), h->plan.begin() + L.param_row);
+  std::copy(h->node_len.begin(), h->node_len.end(), h->plan.begin() + L.len);
+}
+
+}  // namespace
+}  // namespace grafx
+
 using namespace grafx;
 
 extern "C" {
@@ -329,22 +357,48 @@ grafx_status grafx_schedule(int32_t num_nodes, const int32_t* node_type, int32_t
     h->param_row.resize(V);
     for (int i = 0; i < V; ++i) h->param_row[i] = row_of[h->perm[i]];
   }
-  // packed device plan image
-  PlanLayout& L = h->layout;
-  size_t off = 0;
-  auto take = [&](size_t n) { size_t o = off; off = align_up(off + n, 64); return o; };
-  L.in_ptr = take(V + 1);
-  L.in_src = take(E);
-  L.out_ptr = take(V + 1);
-  L.out_dst = take(E);
-  L.param_row = take(V);
-  L.total = off;
-  h->plan.assign(L.total, 0);
-  std::copy(h->in_ptr.begin(), h->in_ptr.end(), h->plan.begin() + L.in_ptr);
-  std::copy(h->in_src.begin(), h->in_src.end(), h->plan.begin() + L.in_src);
-  std::copy(h->out_ptr.begin(), h->out_ptr.end(), h->plan.begin() + L.out_ptr);
-  std::copy(h->out_dst.begin(), h->out_dst.end(), h->plan.begin() + L.out_dst);
-  std::copy(h->param_row.begin(), h->param_row.end(), h->plan.begin() + L.param_row);
+  build_plan(h);
+  *out = h;
+  return GRAFX_OK;
+}
+
+grafx_status grafx_schedule_with_lengths(int32_t num_nodes, const int32_t* node_type,
+                                         int32_t num_edges, const int32_t* edge_src,
+                                         const int32_t* edge_dst, const int32_t* edge_type,
+                                         const int32_t* node_len, int32_t method,
+                                         int32_t beam_width, int64_t state_limit,
+                                         grafx_schedule_t** out) {
+  clear_error();
+  if (!out) return fail(GRAFX_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!node_len) return fail(GRAFX_E_ARG, "node_len is NULL");
+  if (!node_type) return fail(GRAFX_E_ARG, "node_type is NULL");
+  if (num_edges > 0 && (!edge_src || !edge_dst)) return fail(GRAFX_E_ARG, "edge arrays are NULL");
+  for (int32_t v = 0; v < num_nodes; ++v)
+    if (node_len[v] < 1 || node_len[v] >= (1 << 29))
+      return fail(GRAFX_E_SHAPE, "node " + std::to_string(v) + ": length must be in [1, 2^29)");
+  for (int32_t e = 0; e < num_edges; ++e) {
+    const int32_t a = edge_src[e], b = edge_dst[e];
+    if (a < 0 || a >= num_nodes || b < 0 || b >= num_nodes) continue;  // grafx_schedule rejects
+    if (node_len[a] != node_len[b])
+      return fail(GRAFX_E_SHAPE, "edge " + std::to_string(e) +
+                                     " joins nodes of different lengths (every connected graph "
+                                     "has one length)");
+  }
+  grafx_schedule_t* h = nullptr;
+  const grafx_status st = grafx_schedule(num_nodes, node_type, num_edges, edge_src, edge_dst,
+                                         edge_type, method, beam_width, state_limit, &h);
+  if (st != GRAFX_OK) return st;
+  h->node_len.resize(h->V);
+  h->max_len = 0;
+  h->len4 = true;
+  for (int i = 0; i < h->V; ++i) {
+    const int32_t n = node_len[h->perm[i]];
+    h->node_len[i] = n;
+    h->max_len = std::max(h->max_len, n);
+    h->len4 = h->len4 && (n % 4 == 0);
+  }
+  build_plan(h);
   *out = h;
   return GRAFX_OK;
 }
@@ -361,6 +415,7 @@ grafx_status grafx_schedule_query(const grafx_schedule_t* h, grafx_schedule_size
   out->num_outputs = h->n_out;
   for (int t = 0; t < kNumTypes; ++t) out->type_count[t] = h->type_count[t];
   out->plan_bytes = static_cast<int64_t>(h->layout.total * sizeof(int32_t));
+  out->max_len = h->max_len;
   return GRAFX_OK;
 }
 

@@ -302,6 +302,31 @@ def large_console(seed=5, T=2 ** 20, n_tracks=256) -> Workload:
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
 
 
+def batched_graph(seed: int, index: int, T_choices=(2 ** 16, 2 ** 17, 2 ** 18),
+                  src_range=(8, 96)) -> Workload:
+    """One graph of the batched uneven-graph workload: K ~ U{8..96} sources, per-track chains of
+    0-4 distinct processors from {eq, compressor, gain_pan, imager, delay, tanh}, a bus tree of
+    depth 1-3 (ceil(K/8) level-1 buses, then ceil(n/4) per further level, each bus
+    mix -> eq -> compressor), master mix -> eq -> compressor -> gain_pan -> out, and its own
+    T drawn from `T_choices`. Graph `index` of seed `seed` uses its own generator streams."""
+    rng = rng_for(seed, S_STRUCT, index)
+    K = int(rng.integers(src_range[0], src_range[1] + 1))
+    depth = int(rng.integers(1, 4))
+    levels = [-(-K // 8)]
+    for _ in range(depth - 1):
+        levels.append(-(-levels[-1] // 4))
+    graph = console_graph(rng, K, levels, pool=CHAIN_POOL_C3, kmin=0, kmax=4)
+    T = int(T_choices[int(rng.integers(0, len(T_choices)))])
+    return Workload(f"batched_{seed}_{index}", graph,
+                    make_sources(rng_for(seed, S_SOURCE, index), K, T),
+                    draw_params(rng_for(seed, S_PARAM, index), graph), None, T, seed)
+
+
+def batched_graphs(count: int = 128, seed: int = 7, **kw) -> list[Workload]:
+    """`count` graphs of the batched uneven-graph workload (see `batched_graph`)."""
+    return [batched_graph(seed, i, **kw) for i in range(count)]
+
+
 def random_dag(rng, n_nodes: int, types=(MIX, GAIN_PAN, EQ, COMP), edge_p: float = 0.3,
                n_in: int | None = None, n_out: int = 1, multi: bool = True,
                allow_orphans: bool = True) -> Graph:
