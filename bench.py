@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32; unpacked issue is half of it)
 EQ_FFT = 4096
-WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console"}
+WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
+             "batch": "batched_graphs"}
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
 KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
@@ -50,6 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="console", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="beam")
+    ap.add_argument("--graphs", type=int, default=128, help="graphs in the batch workload")
     ap.add_argument("--mode", default="graph", choices=("graph", "eager", "autograd"),
                     help="how the timed step is issued: one HIP-graph replay of the whole step "
                          "(default), the same C-ABI calls issued eagerly, or through autograd")
@@ -83,8 +85,13 @@ def step_bytes(sched, n: int, T: int, backward: bool) -> int:
             rows = d_out + 2
         else:
             rows = d_out + d_in + 1
-        total += 8 * rows * T
+        total += 8 * rows * _len(sched, i, T)
     return total
+
+
+def _len(sched, i: int, T: int) -> int:
+    """Signal length of the node at reordered position i (per-node lengths, else T)."""
+    return T if sched.len_sigma is None else int(sched.len_sigma[i])
 
 
 def step_flops(sched, n: int, T: int, backward: bool) -> float:
@@ -92,11 +99,11 @@ def step_flops(sched, n: int, T: int, backward: bool) -> float:
     transforms per 2048-sample tile forward (window FFT, inverse FFT) plus the real spectral
     product, three backward (adjoint window FFT, inverse FFT, input-tile FFT) plus the spectral
     product and the complex cross-spectrum accumulation."""
-    nodes = int(sched.step_ptr[n + 1] - sched.step_ptr[n])
-    tiles = -(-T // (EQ_FFT // 2))
+    tiles = sum(-(-_len(sched, i, T) // (EQ_FFT // 2))
+                for i in range(int(sched.step_ptr[n]), int(sched.step_ptr[n + 1])))
     fft = 5.0 * EQ_FFT * np.log2(EQ_FFT)
     per_tile = 3 * fft + 2 * EQ_FFT + 8 * EQ_FFT if backward else 2 * fft + 2 * EQ_FFT
-    return nodes * tiles * per_tile
+    return tiles * per_tile
 
 
 def stored_traffic(kernel_type: str, direction: str, workload: str):
@@ -153,30 +160,41 @@ def cpu_baseline(maker, T_full: int, seed_T: int, min_seconds: float = 10.0, max
 
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path "
-              f"(--gpus {args.gpus} requested)", file=sys.stderr)
-        sys.exit(2)
+def cpu_baseline_graph(w, min_seconds: float = 10.0, max_reps: int = 6):
+    """The FP64 oracle (forward render and the adjoint of a seeded output adjoint, by autograd) on
+    one graph of the batch at its own T, repeated until about `min_seconds` of CPU work."""
+    import torch
+
+    from oracle import render as OR
+    g = w.graph
+    cores = torch.get_num_threads()
+    P = OR.as_params64(w.params, requires_grad=True)
+    keys = [t for t in P if P[t].shape[0] > 0]
+    dY = torch.as_tensor(np.random.default_rng(1).standard_normal(
+        (g.count(1), 2, w.T)), dtype=torch.float64)
+    reps, t0 = 0, time.perf_counter()
+    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+        Y = OR.render(g.node_type, g.edges, w.sources, P)
+        torch.autograd.grad((Y * dY).sum(), [P[t] for t in keys])
+        reps += 1
+    dt = time.perf_counter() - t0
+    return {"value": w.processed_nodes * w.T * reps / dt, "unit": "node-samples/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"graph 0 of the batch ({g.num_nodes} nodes, T={w.T}), forward+backward in "
+                      f"float64, {reps} step(s) in {dt:.1f} s"}
+
+
+def setup_console(args, dev):
+    """The mixing-console gradient step: render, MRSTFT loss against a target rendered with
+    hidden parameters, loss adjoint, render adjoint (GradStep; also issued through autograd)."""
     import torch
 
     import synth
-    from paper_2408_03204_amd import GradStep, RenderBuffers, Schedule, mrstft_loss, render
+    from paper_2408_03204_amd import GradStep, Schedule, mrstft_loss, render
 
     maker = getattr(synth, WORKLOADS[args.workload])
     w = maker(T=args.T) if args.T else maker()
-    T = w.T
     g = w.graph
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.copy_calibration > 0:  # a plain copy of known size, for PMC counter scaling
-        n = args.copy_calibration * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     sched = Schedule(g.node_type, g.edges, args.method)
     S = torch.as_tensor(w.sources, device=dev)
     P = {t: torch.as_tensor(p, device=dev).requires_grad_(True)
@@ -198,6 +216,104 @@ def main():
         gs.capture()
     steps = {m: fn for m, fn in (("graph", gs.replay), ("eager", gs.run),
                                  ("autograd", autograd_step)) if m in wanted}
+    config = {"workload": w.name, "nodes": g.num_nodes, "processed_nodes": w.processed_nodes,
+              "edges": g.num_edges, "T": w.T, "schedule": args.method,
+              "steps_in_schedule": sched.num_steps, "loss": "mrstft 512/1024/2048",
+              "step": "render+loss+adjoint"}
+    return {"sched": sched, "S": S, "P": {t: p.detach() for t, p in P.items()}, "T": w.T,
+            "rb": None, "node_samples": w.processed_nodes * w.T, "steps": steps,
+            "config": config, "key": args.workload,
+            "cpu": (lambda: cpu_baseline(maker, w.T, w.T))}
+
+
+def setup_batch(args, dev):
+    """Uneven graphs merged into one schedule (per-node lengths): forward render and render
+    adjoint of all graphs with a seeded output adjoint (no loss: the MRSTFT loss takes one
+    length), issued eagerly or as one captured HIP graph."""
+    import concurrent.futures
+    import functools
+
+    import torch
+
+    import synth
+    from paper_2408_03204_amd import RenderBuffers, Schedule, merge_graphs, merge_inputs
+
+    count, seed = args.graphs, 7
+    with concurrent.futures.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        ws = list(ex.map(functools.partial(synth.batched_graph, seed), range(count)))
+    m = merge_graphs([(w.graph.node_type, w.graph.edges, w.T) for w in ws])
+    S_h, P_h = merge_inputs(m, [w.sources for w in ws], [w.params for w in ws])
+    sample = ws[0]
+    node_samples = sum(w.processed_nodes * w.T for w in ws)
+    n_out = [(m["output_offset"][i], w.graph.count(synth.OUT), w.T) for i, w in enumerate(ws)]
+    del ws
+    sched = Schedule(m["node_type"], m["edges"], args.method, lengths=m["lengths"])
+    T = m["T"]
+    S = torch.as_tensor(S_h, device=dev)
+    del S_h
+    P = {t: torch.as_tensor(p, device=dev) for t, p in P_h.items()}
+    rng = np.random.default_rng(seed)
+    dY_h = np.zeros((sched.num_outputs, 2, T), dtype=np.float32)
+    for o0, n, Tg in n_out:
+        dY_h[o0:o0 + n, :, :Tg] = rng.standard_normal((n, 2, Tg), dtype=np.float32)
+    dY = torch.as_tensor(dY_h, device=dev)
+    rb = RenderBuffers(sched, T, dev, with_backward=True)
+    dP = {t: torch.empty_like(p) for t, p in P.items()}
+
+    def eager():
+        rb.forward(S, P)
+        rb.backward(S, P, dY, dP)
+
+    wanted = {args.mode} if args.single_mode else {"graph", "eager"}
+    steps = {}
+    if "graph" in wanted:
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            eager()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            eager()
+        steps["graph"] = graph.replay
+    if "eager" in wanted:
+        steps["eager"] = eager
+    counts = np.bincount(m["node_type"], minlength=9)
+    config = {"workload": f"batched_uneven_{count}graphs", "graphs": count,
+              "nodes": int(counts.sum()), "processed_nodes": int(counts.sum() - counts[0]),
+              "edges": int(m["edges"].shape[1]), "T": "per graph U{2^16, 2^17, 2^18}",
+              "row_stride": T, "schedule": args.method, "steps_in_schedule": sched.num_steps,
+              "step": "render+adjoint (seeded output adjoint)"}
+    return {"sched": sched, "S": S, "P": P, "T": T, "rb": rb, "dY": dY,
+            "node_samples": node_samples, "steps": steps, "config": config, "key": "batch",
+            "cpu": (lambda: cpu_baseline_graph(sample))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2408_03204_amd import RenderBuffers
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:  # a plain copy of known size, for PMC counter scaling
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    ctx = setup_batch(args, dev) if args.workload == "batch" else setup_console(args, dev)
+    sched, S, T = ctx["sched"], ctx["S"], ctx["T"]
+    steps = ctx["steps"]
+    if args.mode not in steps:
+        raise SystemExit(f"--mode {args.mode} is not available for this workload")
 
     def timed(fn) -> float:
         for _ in range(args.warmup):
@@ -214,15 +330,16 @@ def main():
     modes = {m: timed(fn) for m, fn in steps.items() if m != args.mode}
     ms = timed(steps[args.mode])  # the reported mode is timed last
     modes[args.mode] = ms
-    node_samples = w.processed_nodes * T
-    value = node_samples / (ms * 1e-3)
+    value = ctx["node_samples"] / (ms * 1e-3)
 
     # ---- per-step breakdown: every render / adjoint step timed with events on its stream ------
     roofline, table, steps_hbm = None, [], None
     if not args.no_breakdown:
-        rb = RenderBuffers(sched, T, dev, with_backward=True)
-        Pd = {t: p.detach() for t, p in P.items()}
-        dY = torch.randn((sched.num_outputs, 2, T), device=dev)
+        rb = ctx["rb"] or RenderBuffers(sched, T, dev, with_backward=True)
+        Pd = ctx["P"]
+        dY = ctx.get("dY")
+        if dY is None:
+            dY = torch.randn((sched.num_outputs, 2, T), device=dev)
         dPd = {t: torch.empty_like(p) for t, p in Pd.items()}
         rb.forward(S, Pd)
         rb.backward(S, Pd, dY, dPd)
@@ -266,7 +383,7 @@ def main():
             achieved = b_tot / (t_tot * 1e6)
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-        roofline.update({"traffic": stored_traffic(tname, d, args.workload),
+        roofline.update({"traffic": stored_traffic(tname, d, ctx["key"]),
                          "kernel": f"{tname} {d}", "launches": cnt,
                          "algorithmic_bytes": b_tot, "ms_total": round(t_tot, 4),
                          "hbm_GBps_at_algorithmic_bytes": round(b_tot / (t_tot * 1e6), 1)})
@@ -282,17 +399,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(maker, T, T)
+        cpu = ctx["cpu"]()
 
     out = {"metric": "node-samples/s fwd+bwd", "value": round(value, 1),
            "unit": "node-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": w.name, "nodes": g.num_nodes,
-                      "processed_nodes": w.processed_nodes, "edges": g.num_edges, "T": T,
-                      "schedule": args.method, "steps_in_schedule": sched.num_steps,
-                      "loss": "mrstft 512/1024/2048", "step": "render+loss+adjoint",
-                      "issue": args.mode},
+           "config": dict(ctx["config"], issue=args.mode),
            "ms_per_step_by_issue": {m: round(v, 4) for m, v in modes.items()},
            "roofline": roofline, "render_adjoint_steps": steps_hbm, "cpu_baseline": cpu}
     print(json.dumps(out))

@@ -74,13 +74,18 @@ class Schedule:
             self.step_type, self.step_ptr, self.perm, self.in_ptr, self.in_src, self.out_ptr,
             self.out_dst, self.param_row)]))
         self.in_src, self.out_dst = self.in_src[:E], self.out_dst[:E]
+        # per-node lengths in reordered (sigma) order, or None when every node has the render's T
+        self.len_sigma = None if lengths is None else ln[self.perm]
         self.out_begin = int(self.step_ptr[N])
         self._plans: dict = {}
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            load().grafx_schedule_free(h)
+            try:
+                load().grafx_schedule_free(h)
+            except Exception:  # interpreter shutdown: the process releases the memory anyway
+                pass
             self._h = None
 
     def type_string(self) -> tuple:

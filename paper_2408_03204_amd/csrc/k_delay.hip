@@ -47,24 +47,35 @@ __global__ __launch_bounds__(kBlock) void delay_design_kernel(const float* P, fl
   }
 }
 
-// Stage x[base .. base + kWin) of one channel of a node's gather-sum (in: input edges over U/S,
-// adj: output edges over dU/dY) into LDS, each row zero outside [0, length of its node).
+// Stage x[base .. base + len) (len <= kWin) of one channel of a node's gather-sum (in: input
+// edges over U/S, adj: output edges over dU/dY) into LDS. Each row is read through a buffer
+// resource sized to its node's length, so samples before 0 or past the length read as zero
+// without a branch, and all of a row's loads are issued before any is consumed.
 template <bool ADJ>
 __device__ __forceinline__ void stage_window(const GraphView& g, int node, int c, int64_t base,
                                              int len, float* w) {
+  constexpr int kQ = (kWin + kBlock - 1) / kBlock;
   const int64_t T = g.T;
   const int e0 = ADJ ? g.out_ptr[node] : g.in_ptr[node];
   const int e1 = ADJ ? g.out_ptr[node + 1] : g.in_ptr[node + 1];
-  for (int idx = threadIdx.x; idx < len; idx += kBlock) {
-    const int64_t t = base + idx;
-    float s = 0.f;
-    if (t >= 0)
-      for (int e = e0; e < e1; ++e) {
-        const int other = ADJ ? g.out_dst[e] : g.in_src[e];
-        const float* row = ADJ ? adj_row(g, other) : out_row(g, other);
-        if (t < node_len(g, other)) s += row[(int64_t)c * T + t];
-      }
-    w[idx] = s;
+  const int t_first = (int)base + (int)threadIdx.x;  // base > -2^30: negative offsets read 0
+  float s[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) s[q] = 0.f;
+  for (int e = e0; e < e1; ++e) {
+    const int other = ADJ ? g.out_dst[e] : g.in_src[e];
+    const float* row = (ADJ ? adj_row(g, other) : out_row(g, other)) + (int64_t)c * T;
+    const auto rs = row_rsrc(row, node_len(g, other));
+    float x[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) x[q] = bload(rs, t_first + kBlock * q);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) s[q] += x[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int idx = (int)threadIdx.x + kBlock * q;
+    if (idx < len) w[idx] = s[q];
   }
 }
 
@@ -123,40 +134,44 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
   (void)tiles;
 }
 
+// Tiles per tap-gradient block: a constant, so a node's partial sums are grouped the same way
+// whatever the row stride T (a graph merged with longer ones gets the same bits as alone). Eight
+// tiles amortise the block reduction of the 39 sums per channel-tap.
+constexpr int kTapTiles = 8;
+
 // Tap gradients: part[slot][group][c*5+m][j] = sum over the group's tiles of
 // sum_t ybar_c[t] u_c[t - d - j].
 __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, const int32_t* offs,
                                                                int node_begin, int tiles,
-                                                               int groups, int tpg,
-                                                               float* part) {
+                                                               int groups, float* part) {
   __shared__ float w[kWin];
   __shared__ float yb[kHop];
   __shared__ float red[4][kDelayFir];
   const int group = blockIdx.x, node = node_begin + blockIdx.y;
   const int slot = g.param_row[node];
   const int tiles_n = (int)((node_len(g, node) + kHop - 1) / kHop);  // the node's own tiles
-  const int tile_end = min(min(tiles, tiles_n), (group + 1) * tpg);
+  const int tile_end = min(min(tiles, tiles_n), (group + 1) * kTapTiles);
+  const int o0 = kPer * threadIdx.x;
   for (int cm = 0; cm < 2 * kDelayTaps; ++cm) {
     const int c = cm / kDelayTaps;
     const int d = offs[(int64_t)slot * 2 * kDelayTaps + cm];
     float acc[kDelayFir];
 #pragma unroll
     for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] = 0.f;
-    for (int tile = group * tpg; tile < tile_end; ++tile) {
+    for (int tile = group * kTapTiles; tile < tile_end; ++tile) {
       const int64_t t0 = (int64_t)tile * kHop;
       __syncthreads();
       stage_window<false>(g, node, c, t0 - d - kHalf, kWin, w);
       stage_window<true>(g, node, c, t0, kHop, yb);
       __syncthreads();
-      const int o0 = kPer * threadIdx.x;
       float x[kPer + 2 * kHalf];
 #pragma unroll
-      for (int i = 0; i < kPer + 2 * kHalf; ++i) x[i] = w[o0 + i];
+      for (int q = 0; q < kPer + 2 * kHalf; ++q) x[q] = w[o0 + q];
 #pragma unroll
-      for (int i = 0; i < kPer; ++i) {
-        const float yv = yb[o0 + i];
+      for (int q = 0; q < kPer; ++q) {
+        const float yv = yb[o0 + q];
 #pragma unroll
-        for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] += yv * x[i + 2 * kHalf - jj];
+        for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] += yv * x[q + 2 * kHalf - jj];
       }
     }
     // block reduction of the 39 partial sums (fixed order)
@@ -207,14 +222,7 @@ __global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, cons
 
 int delay_tiles(int64_t T) { return (int)((T + kHop - 1) / kHop); }
 
-// Tiles per tap-gradient block: a constant, so a node's partial sums are grouped the same way
-// whatever the row stride T (a graph merged with longer ones gets the same bits as alone).
-static int delay_tpg(int64_t) { return 4; }
-
-int delay_groups(int64_t T) {
-  const int tpg = delay_tpg(T);
-  return (delay_tiles(T) + tpg - 1) / tpg;
-}
+int delay_groups(int64_t T) { return (delay_tiles(T) + kTapTiles - 1) / kTapTiles; }
 
 hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -236,9 +244,9 @@ hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
   const int tiles = delay_tiles(g.T);
   delay_conv_kernel<true><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, dU, taps, offs, node_begin,
                                                                   tiles);
-  const int groups = delay_groups(g.T), tpg = delay_tpg(g.T);
+  const int groups = delay_groups(g.T);
   delay_tapgrad_kernel<<<dim3(groups, n_nodes), kBlock, 0, s>>>(g, offs, node_begin, tiles,
-                                                                groups, tpg, part);
+                                                                groups, part);
   return hipGetLastError();
 }
 
