@@ -94,11 +94,20 @@ def _len(sched, i: int, T: int) -> int:
     return T if sched.len_sigma is None else int(sched.len_sigma[i])
 
 
+DELAY_FMA = 2 * 5 * 39  # per stereo sample: 2 channels x 5 taps x 39-tap FIR
+
+
 def step_flops(sched, n: int, T: int, backward: bool) -> float:
-    """Algorithmic FP32 flops of an EQ step: 5 N log2 N per complex N-point FFT (N = 4096), two
-    transforms per 2048-sample tile forward (window FFT, inverse FFT) plus the real spectral
-    product, three backward (adjoint window FFT, inverse FFT, input-tile FFT) plus the spectral
-    product and the complex cross-spectrum accumulation."""
+    """Algorithmic FP32 flops of an FFT- or FIR-bound step. EQ: 5 N log2 N per complex N-point FFT
+    (N = 4096), two transforms per 2048-sample tile forward (window FFT, inverse FFT) plus the
+    real spectral product, three backward (adjoint window FFT, inverse FFT, input-tile FFT) plus
+    the spectral product and the complex cross-spectrum accumulation. Delay: 2 flops per FMA of
+    the 5 x 39-tap filters per channel, once forward, twice backward (input adjoint and tap
+    gradients)."""
+    if int(sched.step_type[n]) == 7:
+        samples = sum(_len(sched, i, T) for i in range(int(sched.step_ptr[n]),
+                                                         int(sched.step_ptr[n + 1])))
+        return samples * 2.0 * DELAY_FMA * (2 if backward else 1)
     tiles = sum(-(-_len(sched, i, T) // (EQ_FFT // 2))
                 for i in range(int(sched.step_ptr[n]), int(sched.step_ptr[n + 1])))
     fft = 5.0 * EQ_FFT * np.log2(EQ_FFT)
@@ -373,9 +382,9 @@ def main():
             tb[1] += nbytes
             tb[2] += 1
         (d, tname), (t_tot, b_tot, cnt) = max(agg.items(), key=lambda kv: kv[1][0])
-        if tname == "eq":  # FFT-bound: priced against the FP32 vector peak
+        if tname in ("eq", "delay"):  # FFT / FIR bound: priced against the FP32 vector peak
             flops = sum(step_flops(sched, r["step"], T, d == "bwd") for r in table
-                        if r["dir"] == d and r["type"] == "eq")
+                        if r["dir"] == d and r["type"] == tname)
             achieved = flops / (t_tot * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4)}
