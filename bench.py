@@ -37,11 +37,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32; unpacked issue
 EQ_FFT = 4096
 WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
              "batch": "batched_graphs"}
-TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh")
+TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
+              "noisegate")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
 KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
               "imager": "k_pointwise.hip", "tanh": "k_pointwise.hip", "eq": "k_eq.hip",
-              "compressor": "k_comp.hip", "delay": "k_delay.hip"}
+              "compressor": "k_comp.hip", "noisegate": "k_comp.hip", "delay": "k_delay.hip"}
 
 
 def parse():
@@ -288,7 +289,7 @@ def setup_batch(args, dev):
         steps["graph"] = graph.replay
     if "eager" in wanted:
         steps["eager"] = eager
-    counts = np.bincount(m["node_type"], minlength=9)
+    counts = np.bincount(m["node_type"], minlength=len(TYPE_NAMES))
     config = {"workload": f"batched_uneven_{count}graphs", "graphs": count,
               "nodes": int(counts.sum()), "processed_nodes": int(counts.sum() - counts[0]),
               "edges": int(m["edges"].shape[1]), "T": "per graph U{2^16, 2^17, 2^18}",

@@ -36,6 +36,8 @@
  *   6 imager     1    mid/side width                                     (Eq. 3)
  *   7 delay      220  [channel 2][slot 5][re z, im z, 20 log-magnitudes]  (Eq. 14, <= 500 ms)
  *   8 tanh       1    y = tanh(exp(p) u)                                  (not in the paper)
+ *   9 noisegate  4    (alpha, T, W, R): the compressor's envelope with a downward-expander
+ *                     curve, ratio R >= 1 below T - W, quadratic knee   (Sec. 3 "Noisegate")
  * The node input is the sum over incoming edges of the source node outputs (Eq. 1b), parallel
  * edges counted once each, summed in original edge order.
  */
@@ -65,8 +67,8 @@ typedef enum grafx_status {
 
 enum {
   GRAFX_IN = 0, GRAFX_OUT = 1, GRAFX_MIX = 2, GRAFX_GAIN_PAN = 3, GRAFX_EQ = 4,
-  GRAFX_COMPRESSOR = 5, GRAFX_IMAGER = 6, GRAFX_DELAY = 7, GRAFX_TANH = 8,
-  GRAFX_NUM_TYPES = 9
+  GRAFX_COMPRESSOR = 5, GRAFX_IMAGER = 6, GRAFX_DELAY = 7, GRAFX_TANH = 8, GRAFX_NOISEGATE = 9,
+  GRAFX_NUM_TYPES = 10
 };
 
 /* Schedule search methods (paper Sec. 2 "Type scheduling"; Sec. 4 "Speed benchmark"). */

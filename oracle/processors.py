@@ -169,6 +169,28 @@ def compressor(u: torch.Tensor, p: torch.Tensor, envelope=one_pole) -> torch.Ten
     return torch.exp(Gy - Gu)[None, :] * u
 
 
+def gate_computer(Gu, thr, knee, ratio):
+    """Noisegate static curve (Sec. 3 "Noisegate"): G_y = G_u at or above T + W, a quadratic knee
+    G_u + (1 - R)(G_u - T - W)^2 / (4W) on [T - W, T + W), and T + R (G_u - T) below T - W (an
+    expander of ratio R). A knee width W <= 0 is read as a hard knee at T."""
+    below = thr + ratio * (Gu - thr)
+    if float(torch.as_tensor(knee).detach()) <= 0.0:
+        return torch.where(Gu < thr, below, Gu)
+    mid = Gu + (1.0 - ratio) * (Gu - thr - knee) ** 2 / (4.0 * knee)
+    return torch.where(Gu < thr - knee, below, torch.where(Gu < thr + knee, mid, Gu))
+
+
+def noisegate(u: torch.Tensor, p: torch.Tensor, envelope=one_pole) -> torch.Tensor:
+    """Noisegate (Sec. 3 "Noisegate"): the compressor's energy envelope and output rule
+    (Eqs. 8, 9, 12) with the gate's static curve. p = (alpha, T, W, R)."""
+    alpha, thr, knee, ratio = p[0], p[1], p[2], p[3]
+    x = (u[0] + u[1]) ** 2
+    g = envelope(x, alpha)
+    Gu = torch.log(g + EPS_ENV)
+    Gy = gate_computer(Gu, thr, knee, ratio)
+    return torch.exp(Gy - Gu)[None, :] * u
+
+
 def envelope_loop(x: np.ndarray, alpha: float) -> np.ndarray:
     """Literal per-sample loop of Eq. 8 (pure Python; small inputs only)."""
     g = np.zeros_like(x, dtype=np.float64)
@@ -226,5 +248,5 @@ def identity(u: torch.Tensor, p=None) -> torch.Tensor:
 
 
 PROCESS = {2: identity, 3: gain_pan, 4: eq, 5: compressor, 6: imager, 7: delay, 8: tanh_dist,
-           1: identity}
-N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1}
+           9: noisegate, 1: identity}
+N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4}

@@ -17,8 +17,9 @@ from . import _lib
 from ._lib import check, load
 
 TYPE_CODES = {"in": 0, "out": 1, "mix": 2, "gain_pan": 3, "eq": 4, "compressor": 5, "imager": 6,
-              "delay": 7, "tanh": 8}
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1)
+              "delay": 7, "tanh": 8, "noisegate": 9}
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4)
+NUM_TYPES = _lib.NUM_TYPES
 METHODS = {"one_by_one": 0, "greedy": 1, "beam": 2, "optimal": 3}
 
 
@@ -107,11 +108,11 @@ class Schedule:
 
 
 def _param_list(sched: Schedule, P) -> list:
-    out = [None] * 9
+    out = [None] * NUM_TYPES
     for k, v in (P or {}).items():
         t = TYPE_CODES[k] if isinstance(k, str) else int(k)
         out[t] = v
-    for t in range(9):
+    for t in range(NUM_TYPES):
         if N_PARAMS[t] and sched.type_count[t] > 0:
             p = out[t]
             if p is None:
@@ -236,7 +237,7 @@ class RenderBuffers:
 
     def backward(self, S, P, dY, dP: dict | None = None, dS=None):
         Pl = _param_list(self.sched, P)
-        dPl = [None] * 9
+        dPl = [None] * NUM_TYPES
         for k, v in (dP or {}).items():
             dPl[TYPE_CODES[k] if isinstance(k, str) else int(k)] = v
         check(load().grafx_render_backward(
@@ -288,7 +289,7 @@ class GradStep:
         self.dloss = torch.ones((), dtype=torch.float32, device=self.dev)
         self.dY = torch.empty((rows, 2, T), dtype=torch.float32, device=self.dev)
         self.grads = {t: torch.empty_like(p) for t, p in enumerate(self.P) if p is not None}
-        self._dP = [self.grads.get(t) for t in range(9)]
+        self._dP = [self.grads.get(t) for t in range(NUM_TYPES)]
         self.graph = None
 
     def run(self) -> torch.Tensor:
@@ -340,7 +341,7 @@ def merge_graphs(graphs):
     nts, eds, lens = [], [], []
     off = {"node": [], "input": [], "output": [], "param": []}
     n = 0
-    cnt = np.zeros(9, dtype=np.int64)
+    cnt = np.zeros(NUM_TYPES, dtype=np.int64)
     for node_type, edges, T in graphs:
         nt = np.asarray(node_type, dtype=np.int32).reshape(-1)
         e = np.asarray(edges, dtype=np.int64).reshape(2, -1)
@@ -352,7 +353,7 @@ def merge_graphs(graphs):
         eds.append(e + n)
         lens.append(np.full(nt.shape[0], int(T), dtype=np.int32))
         n += nt.shape[0]
-        cnt += np.bincount(nt, minlength=9)
+        cnt += np.bincount(nt, minlength=NUM_TYPES)
     return {"node_type": np.concatenate(nts), "edges": np.concatenate(eds, axis=1).astype(np.int32),
             "lengths": np.concatenate(lens), "T": int(max(int(g[2]) for g in graphs)),
             "node_offset": off["node"], "input_offset": off["input"],
@@ -367,7 +368,7 @@ def merge_inputs(merged, sources, params):
                                ((0, 0), (0, 0), (0, T - np.asarray(s).shape[-1])))
                         for s in sources], axis=0)
     P = {}
-    for t in range(9):
+    for t in range(NUM_TYPES):
         rows = [np.asarray(p[t], dtype=np.float32) for p in params if t in p]
         rows = [r for r in rows if r.shape[0] > 0]
         if rows:

@@ -12,7 +12,9 @@ namespace grafx {
 namespace {
 
 // Workspace layout (byte offsets, 256-byte aligned sections). The forward part is kept by the
-// render for the adjoint: EQ filters, compressor carries, delay taps.
+// render for the adjoint: EQ filters, dynamics carries, delay taps. "Dynamics" rows are the
+// compressor nodes (by parameter slot) followed by the noisegate nodes: both run the same
+// envelope scan and share one set of chunk totals, carries, tickets and gradient partials.
 struct WsLayout {
   size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps, delay_offs;
   size_t fwd_end;
@@ -20,18 +22,27 @@ struct WsLayout {
   size_t total;
 };
 
+// Dynamics rows: compressors first, then noisegates.
+size_t n_dynamics(const grafx_schedule_t* h) {
+  return (size_t)h->type_count[GRAFX_COMPRESSOR] + h->type_count[GRAFX_NOISEGATE];
+}
+int dyn_row(const grafx_schedule_t* h, int t) {
+  return t == GRAFX_NOISEGATE ? h->type_count[GRAFX_COMPRESSOR] : 0;
+}
+
 WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   WsLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  const size_t n_eq = h->type_count[GRAFX_EQ], n_comp = h->type_count[GRAFX_COMPRESSOR];
+  const size_t n_eq = h->type_count[GRAFX_EQ];
+  const size_t n_comp = n_dynamics(h);
   const size_t n_del = h->type_count[GRAFX_DELAY];
   const size_t chunks = comp_chunks(T);
   L.eq_h = take(n_eq * 1024 * sizeof(double));
   L.eq_H = take(n_eq * kEqFFT * sizeof(float));
   L.comp_agg = take(n_comp * chunks * sizeof(uint64_t));
   L.comp_carry = take(n_comp * chunks * sizeof(double));
-  // one ticket counter per compressor node (forward), one per node (adjoint), each on its own
+  // one ticket counter per dynamics node (forward), one per node (adjoint), each on its own
   // cache line, then the error word
   L.comp_tickets = take((2 * n_comp * kCompTicketStride + 1) * sizeof(unsigned));
   L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
@@ -112,19 +123,19 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
 }
 
 unsigned* tickets(void* ws, const WsLayout& L, const grafx_schedule_t* h, bool bwd) {
-  return at<unsigned>(ws, L.comp_tickets) +
-         (bwd ? (size_t)h->type_count[GRAFX_COMPRESSOR] * kCompTicketStride : 0);
+  return at<unsigned>(ws, L.comp_tickets) + (bwd ? (size_t)n_dynamics(h) * kCompTicketStride : 0);
 }
 
 unsigned* error_word(void* ws, const WsLayout& L, const grafx_schedule_t* h) {
-  return at<unsigned>(ws, L.comp_tickets) +
-         (size_t)2 * h->type_count[GRAFX_COMPRESSOR] * kCompTicketStride;
+  return at<unsigned>(ws, L.comp_tickets) + (size_t)2 * n_dynamics(h) * kCompTicketStride;
 }
 
-// Reset the compressor chaining state of one pass (all compressor nodes, all steps).
+bool is_dynamics(int t) { return t == GRAFX_COMPRESSOR || t == GRAFX_NOISEGATE; }
+
+// Reset the dynamics chaining state of one pass (all compressor and noisegate nodes, all steps).
 hipError_t reset_comp(const grafx_schedule_t* h, void* ws, const WsLayout& L, bool bwd,
                       int64_t T, hipStream_t stream) {
-  const int n_comp = h->type_count[GRAFX_COMPRESSOR];
+  const int n_comp = n_dynamics(h);
   if (n_comp == 0) return hipSuccess;
   uint64_t* tot = at<uint64_t>(ws, bwd ? L.comp_ragg : L.comp_agg);
   return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd),
@@ -147,7 +158,9 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_EQ:
       return launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
     case GRAFX_COMPRESSOR:
-      return launch_comp_fwd(g, U, p, b, cnt, at<uint64_t>(ws, L.comp_agg),
+    case GRAFX_NOISEGATE:
+      return launch_comp_fwd(g, U, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
+                             at<uint64_t>(ws, L.comp_agg),
                              at<double>(ws, L.comp_carry), tickets(ws, L, h, false),
                              error_word(ws, L, h), stream);
     case GRAFX_DELAY:
@@ -177,7 +190,9 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float>(ws, L.eq_C),
                            at<float>(ws, L.eq_spec), stream);
     case GRAFX_COMPRESSOR:
-      return launch_comp_bwd(g, dU, p, b, cnt, at<double>(ws, L.comp_carry),
+    case GRAFX_NOISEGATE:
+      return launch_comp_bwd(g, dU, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
+                             at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
                              tickets(ws, L, h, true), error_word(ws, L, h), stream);
     case GRAFX_DELAY:
@@ -275,9 +290,10 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
   if (e == hipSuccess && dpar(GRAFX_TANH))
     e = launch_reduce_partials(at<double>(ws, L.part_tanh), h->type_count[GRAFX_TANH], tiles, 1,
                                dpar(GRAFX_TANH), stream);
-  if (e == hipSuccess && dpar(GRAFX_COMPRESSOR))
-    e = launch_reduce_partials(at<double>(ws, L.comp_part), h->type_count[GRAFX_COMPRESSOR],
-                               chunks, 4, dpar(GRAFX_COMPRESSOR), stream);
+  for (int t : {GRAFX_COMPRESSOR, GRAFX_NOISEGATE})
+    if (e == hipSuccess && dpar(t) && h->type_count[t] > 0)
+      e = launch_reduce_partials(at<double>(ws, L.comp_part) + (size_t)dyn_row(h, t) * chunks * 4,
+                                 h->type_count[t], chunks, 4, dpar(t), stream);
   if (e == hipSuccess && dpar(GRAFX_EQ))
     e = launch_eq_grad(par(GRAFX_EQ), at<float>(ws, L.eq_spec), h->type_count[GRAFX_EQ],
                        at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
@@ -297,7 +313,7 @@ grafx_status grafx_render_step(const grafx_schedule_t* h, const void* dev_plan, 
   const WsLayout L = ws_layout(h, T, false);
   const GraphView g = make_view(h, dev_plan, T, S, U);
   hipError_t e = hipSuccess;
-  if (h->step_type[step] == GRAFX_COMPRESSOR) e = reset_comp(h, ws, L, false, T, stream);
+  if (is_dynamics(h->step_type[step])) e = reset_comp(h, ws, L, false, T, stream);
   if (e == hipSuccess) e = enqueue_fwd_step(h, g, P, U, ws, L, step, stream);
   return hip_status(e, "render_step launch");
 }
@@ -316,7 +332,7 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* d
   g.dY = dY;
   g.dU = dU;
   hipError_t e = hipSuccess;
-  if (h->step_type[step] == GRAFX_COMPRESSOR) e = reset_comp(h, ws, L, true, T, stream);
+  if (is_dynamics(h->step_type[step])) e = reset_comp(h, ws, L, true, T, stream);
   if (e == hipSuccess) e = enqueue_bwd_step(h, g, P, dU, ws, L, step, stream);
   return hip_status(e, "render_backward_step launch");
 }

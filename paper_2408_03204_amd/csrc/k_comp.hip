@@ -1,4 +1,5 @@
-// Feed-forward compressor (paper Sec. 3 "Compressor", Eqs. 8-12), parallel across nodes and
+// Feed-forward compressor (paper Sec. 3 "Compressor", Eqs. 8-12) and noisegate (Sec. 3
+// "Noisegate": the same envelope with a downward-expander curve), parallel across nodes and
 // time chunks, one pass over the signal per direction.
 //
 // With equal attack and release the energy envelope g[t] = a g[t-1] + (1-a) x[t],
@@ -49,7 +50,8 @@ constexpr int kMaxSpin = 1 << 24;
 struct Coef {
   double a, b;        // alpha, 1 - alpha
   float thr, knee;    // T, W
-  float c;            // 1/R - 1
+  float c;            // 1/R - 1 (compressor)
+  float g1;           // 1 - R (noisegate)
   float inv2w, inv4w; // 1/(2W), 1/(4W)
   float invR2;        // 1/R^2
   double pw[9];       // pw[d] = (a^kPer)^(2^d); pw[8] = a^kChunk
@@ -65,6 +67,7 @@ __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
   k.knee = p[2];
   const float R = p[3];
   k.c = 1.0f / R - 1.0f;
+  k.g1 = 1.0f - R;
   k.inv2w = k.knee > 0.f ? 1.0f / (2.f * k.knee) : 0.f;
   k.inv4w = k.knee > 0.f ? 1.0f / (4.f * k.knee) : 0.f;
   k.invR2 = 1.0f / (R * R);
@@ -96,7 +99,7 @@ struct Curve {
 // e = G_y - G_u of the quadratic-knee curve (Eqs. 10-11) and its partial derivatives, without
 // branches: the three regions (below the knee, inside it, above it) are selected per lane.
 template <bool GRAD>
-__device__ __forceinline__ Curve curve(float Gu, const Coef& k) {
+__device__ __forceinline__ Curve comp_curve(float Gu, const Coef& k) {
   const float d = Gu - k.thr;
   const float q = d + k.knee;
   const bool soft = k.knee > 0.f;
@@ -117,6 +120,38 @@ __device__ __forceinline__ Curve curve(float Gu, const Coef& k) {
     o.dG = o.dT = o.dW = o.dR = 0.f;
   }
   return o;
+}
+
+// Noisegate curve (Sec. 3 "Noisegate"): e = 0 at or above T + W, (1 - R)(G_u - T - W)^2 / (4W) on
+// the knee, (R - 1)(G_u - T) below T - W (hard knee at T when W <= 0), and its derivatives.
+template <bool GRAD>
+__device__ __forceinline__ Curve gate_curve(float Gu, const Coef& k) {
+  const float d = Gu - k.thr;
+  const float q = d - k.knee;  // G_u - T - W
+  const bool soft = k.knee > 0.f;
+  const bool below = soft ? (d + k.knee < 0.f) : (d < 0.f);  // Gu < T - W (soft) or Gu < T
+  const bool knee = soft && !below && q < 0.f;               // T - W <= Gu < T + W
+  Curve o;
+  const float e_knee = k.g1 * q * q * k.inv4w, e_lin = -k.g1 * d;
+  o.e = below ? e_lin : (knee ? e_knee : 0.f);
+  if (GRAD) {
+    const float g_knee = k.g1 * q * k.inv2w;
+    o.dG = below ? -k.g1 : (knee ? g_knee : 0.f);
+    o.dT = -o.dG;
+    const float w_knee = -k.g1 * (q * k.inv2w + q * q * k.inv4w * (2.f * k.inv2w));
+    o.dW = knee ? w_knee : 0.f;
+    const float r_knee = -q * q * k.inv4w;
+    o.dR = below ? d : (knee ? r_knee : 0.f);
+  } else {
+    o.dG = o.dT = o.dW = o.dR = 0.f;
+  }
+  return o;
+}
+
+template <bool GRAD, bool GATE>
+__device__ __forceinline__ Curve curve(float Gu, const Coef& k) {
+  if constexpr (GATE) return gate_curve<GRAD>(Gu, k);
+  else return comp_curve<GRAD>(Gu, k);
 }
 
 // ln x and exp x through the hardware base-2 instructions (v_log_f32, v_exp_f32). x > 0 is
@@ -265,17 +300,18 @@ __device__ __forceinline__ void store_chunk(float* row, int64_t T, int64_t Tn, i
 
 // ---- forward ----------------------------------------------------------------------------------
 
-template <bool RAGGED>
+template <bool RAGGED, bool GATE>
 __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U, const float* P,
                                                           int node_begin, int n_nodes, int chunks,
-                                                          uint64_t* agg, double* carry,
+                                                          int ws_off, uint64_t* agg, double* carry,
                                                           unsigned* ticket, unsigned* err) {
   __shared__ float sl[kChunk], sr[kChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
   const int node = node_begin + (int)blockIdx.x / chunks;
-  const int slot = g.param_row[node];
-  const int chunk = take_ticket(ticket + (int64_t)slot * kCompTicketStride, &sh_ticket);
+  const int slot = g.param_row[node];  // row in P
+  const int ws = slot + ws_off;         // row of the dynamics workspace (compressors, then gates)
+  const int chunk = take_ticket(ticket + (int64_t)ws * kCompTicketStride, &sh_ticket);
   if (chunk >= chunks) {  // tickets not reset before the launch: do nothing
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
@@ -292,15 +328,15 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
   for (int i = 0; i < kPer; ++i) B = fma(k.a, B, k.b * energy(sl, sr, i0 + i));
   double total;
   const double E0 = chunk_scan<false>(B, k, wtot, total);
-  uint64_t* tots = agg + (int64_t)slot * chunks;
+  uint64_t* tots = agg + (int64_t)ws * chunks;
   if (threadIdx.x == 0) publish(tots + chunk, total);
   const double cin = chunk_carry<false>(tots, chunk, chunks, k, err, red);
-  if (threadIdx.x == 0) carry[(int64_t)slot * chunks + chunk] = cin;
+  if (threadIdx.x == 0) carry[(int64_t)ws * chunks + chunk] = cin;
   double s = fma(pow_a8(k, scan_index(false)), cin, E0);
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     s = fma(k.a, s, k.b * energy(sl, sr, i0 + i));
-    const Curve cv = curve<false>(ln_f((float)(s + kEps)), k);
+    const Curve cv = curve<false, GATE>(ln_f((float)(s + kEps)), k);
     const float gam = exp_f(cv.e);
     sl[i0 + i] = gam * sl[i0 + i];
     sr[i0 + i] = gam * sr[i0 + i];
@@ -311,9 +347,9 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
 
 // ---- adjoint ----------------------------------------------------------------------------------
 
-template <bool RAGGED>
+template <bool RAGGED, bool GATE>
 __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU, const float* P,
-                                                          int node_begin, int n_nodes, int chunks,
+                                                          int node_begin, int n_nodes, int chunks, int ws_off,
                                                           const double* carry, uint64_t* ragg,
                                                           double* part, unsigned* ticket,
                                                           unsigned* err) {
@@ -321,8 +357,9 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
   const int node = node_begin + (int)blockIdx.x / chunks;
-  const int slot = g.param_row[node];
-  const int tk = take_ticket(ticket + (int64_t)slot * kCompTicketStride, &sh_ticket);
+  const int slot = g.param_row[node];  // row in P
+  const int ws = slot + ws_off;         // row of the dynamics workspace (compressors, then gates)
+  const int tk = take_ticket(ticket + (int64_t)ws * kCompTicketStride, &sh_ticket);
   if (tk >= chunks) {  // tickets not reset before the launch: do nothing
     if (threadIdx.x == 0) atomicOr(err, 2u);
     return;
@@ -330,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   const int64_t Tn = RAGGED ? (int64_t)g.len[node] : g.T;
   const int chunks_n = RAGGED ? comp_chunks_of(Tn) : chunks;
   if (RAGGED && tk >= chunks_n) {  // past the node's length: this ticket zeroes one unused partial slot
-    if (threadIdx.x < 4) part[((int64_t)slot * chunks + tk) * 4 + threadIdx.x] = 0.0;
+    if (threadIdx.x < 4) part[((int64_t)ws * chunks + tk) * 4 + threadIdx.x] = 0.0;
     return;
   }
   const int chunk = chunks_n - 1 - tk;
@@ -346,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   for (int i = 0; i < kPer; ++i) B = fma(k.a, B, k.b * energy(ul, ur, i0 + i));
   double total;
   const double E0 = chunk_scan<false>(B, k, wtot, total);
-  const double E = fma(pow_a8(k, scan_index(false)), carry[(int64_t)slot * chunks + chunk], E0);
+  const double E = fma(pow_a8(k, scan_index(false)), carry[(int64_t)ws * chunks + chunk], E0);
   // First pass (forward over the thread's samples): envelope, gain and the local adjoint terms.
   // What the reverse pass needs is written back over the thread's own LDS slots: ul <- g[t-1] -
   // x[t], ur <- u_l + u_r, yl/yr <- gain * ybar.
@@ -363,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
       const double sprev = s;
       s = fma(k.a, s, k.b * x);
       const float gs = (float)(s + kEps);
-      const Curve cv = curve<true>(ln_f(gs), k);
+      const Curve cv = curve<true, GATE>(ln_f(gs), k);
       const float gam = exp_f(cv.e);
       const float y_l = yl[idx], y_r = yr[idx];
       const float rho = gam * (y_l * u_l + y_r * u_r);
@@ -383,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   for (int i = kPer - 1; i >= 0; --i) R = fma(k.a, R, (double)gbar[i]);
   double rtotal;
   const double L0 = chunk_scan<true>(R, k, wtot, rtotal);
-  uint64_t* rtots = ragg + (int64_t)slot * chunks;
+  uint64_t* rtots = ragg + (int64_t)ws * chunks;
   if (threadIdx.x == 0) publish(rtots + chunk, rtotal);
   const double rin = chunk_carry<true>(rtots, chunk, chunks_n, k, err, red);  // own chunks
   double lam = fma(pow_a8(k, scan_index(true)), rin, L0);
@@ -402,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   const double sW = block_sum<double>(accW, red);
   const double sR = block_sum<double>(accR, red);
   if (threadIdx.x == 0) {
-    double* p = part + ((int64_t)slot * chunks + chunk) * 4;
+    double* p = part + ((int64_t)ws * chunks + chunk) * 4;
     p[0] = sA;
     p[1] = sT;
     p[2] = sW;
@@ -432,30 +469,48 @@ hipError_t launch_comp_reset(uint64_t* tot, int64_t n, unsigned* tickets, int n_
   return hipGetLastError();
 }
 
+template <bool RAGGED, bool GATE>
+static void launch_fwd_t(const GraphView& g, float* U, const float* P, int node_begin,
+                         int n_nodes, int chunks, int ws_off, uint64_t* agg, double* carry,
+                         unsigned* ticket, unsigned* err, hipStream_t s) {
+  comp_fwd_kernel<RAGGED, GATE><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
+      g, U, P, node_begin, n_nodes, chunks, ws_off, agg, carry, ticket, err);
+}
+
+template <bool RAGGED, bool GATE>
+static void launch_bwd_t(const GraphView& g, float* dU, const float* P, int node_begin,
+                         int n_nodes, int chunks, int ws_off, const double* carry, uint64_t* ragg,
+                         double* part, unsigned* ticket, unsigned* err, hipStream_t s) {
+  comp_bwd_kernel<RAGGED, GATE><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
+      g, dU, P, node_begin, n_nodes, chunks, ws_off, carry, ragg, part, ticket, err);
+}
+
+// Per-node lengths and the noisegate curve get their own instantiations, so the uniform
+// compressor carries no code for either.
 hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int node_begin,
-                           int n_nodes, uint64_t* agg, double* carry, unsigned* ticket,
-                           unsigned* err, hipStream_t s) {
+                           int n_nodes, int ws_off, bool gate, uint64_t* agg, double* carry,
+                           unsigned* ticket, unsigned* err, hipStream_t s) {
   const int chunks = comp_chunks(g.T);
-  // per-node lengths get their own instantiation, so the uniform case carries no length code
   if (g.len)
-    comp_fwd_kernel<true><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
-        g, U, P, node_begin, n_nodes, chunks, agg, carry, ticket, err);
+    (gate ? launch_fwd_t<true, true> : launch_fwd_t<true, false>)(
+        g, U, P, node_begin, n_nodes, chunks, ws_off, agg, carry, ticket, err, s);
   else
-    comp_fwd_kernel<false><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
-        g, U, P, node_begin, n_nodes, chunks, agg, carry, ticket, err);
+    (gate ? launch_fwd_t<false, true> : launch_fwd_t<false, false>)(
+        g, U, P, node_begin, n_nodes, chunks, ws_off, agg, carry, ticket, err, s);
   return hipGetLastError();
 }
 
 hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
-                           int n_nodes, const double* carry, uint64_t* ragg, double* part,
-                           unsigned* ticket, unsigned* err, hipStream_t s) {
+                           int n_nodes, int ws_off, bool gate, const double* carry,
+                           uint64_t* ragg, double* part, unsigned* ticket, unsigned* err,
+                           hipStream_t s) {
   const int chunks = comp_chunks(g.T);
   if (g.len)
-    comp_bwd_kernel<true><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
-        g, dU, P, node_begin, n_nodes, chunks, carry, ragg, part, ticket, err);
+    (gate ? launch_bwd_t<true, true> : launch_bwd_t<true, false>)(
+        g, dU, P, node_begin, n_nodes, chunks, ws_off, carry, ragg, part, ticket, err, s);
   else
-    comp_bwd_kernel<false><<<(unsigned)(chunks * n_nodes), kBlock, 0, s>>>(
-        g, dU, P, node_begin, n_nodes, chunks, carry, ragg, part, ticket, err);
+    (gate ? launch_bwd_t<false, true> : launch_bwd_t<false, false>)(
+        g, dU, P, node_begin, n_nodes, chunks, ws_off, carry, ragg, part, ticket, err, s);
   return hipGetLastError();
 }
 

@@ -48,12 +48,16 @@ int comp_chunks(int64_t T);
 constexpr int kCompTicketStride = 64;
 hipError_t launch_comp_reset(uint64_t* tot, int64_t n, unsigned* tickets, int n_tickets,
                              hipStream_t s);
+// Compressors and noisegates share one workspace family ("dynamics"): rows [0, n_comp) belong to
+// the compressors, [n_comp, n_comp + n_gate) to the noisegates; ws_off is the family row of the
+// launch's type (0 or n_comp) and `gate` selects the noisegate curve.
 hipError_t launch_comp_fwd(const GraphView& g, float* U, const float* P, int node_begin,
-                           int n_nodes, uint64_t* agg, double* carry, unsigned* ticket,
-                           unsigned* err, hipStream_t s);
-hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
-                           int n_nodes, const double* carry, uint64_t* ragg, double* part,
+                           int n_nodes, int ws_off, bool gate, uint64_t* agg, double* carry,
                            unsigned* ticket, unsigned* err, hipStream_t s);
+hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
+                           int n_nodes, int ws_off, bool gate, const double* carry,
+                           uint64_t* ragg, double* part, unsigned* ticket, unsigned* err,
+                           hipStream_t s);
 
 // ---- delay (k_delay.hip) -------------------------------------------------------------------
 constexpr int kDelayTaps = 5, kDelayFir = 39, kDelaySlot = 4410;

@@ -24,11 +24,13 @@ import numpy as np
 
 FS = 44100
 
-IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH = range(9)
-TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh")
+IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE = range(10)
+TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
+              "noisegate")
+NUM_TYPES = len(TYPE_NAMES)
 TYPE_CODES = {n: i for i, n in enumerate(TYPE_NAMES)}
 # parameters per node of each type (0 for in/out/mix)
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1)
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4)
 
 # delay layout: [channel 2][tap 5][re z, im z, 20 log-magnitudes]
 DELAY_TAPS = 5
@@ -152,6 +154,17 @@ def comp_params(rng, n, knee_db=3.0):
     return np.stack([alpha, thr, knee, ratio], axis=1).astype(np.float32)
 
 
+def gate_params(rng, n, knee_db=3.0):
+    """Noisegate (alpha, T, W, R): time constant U[1,100] ms, threshold U[-50,-30] dB, knee
+    half-width 3 dB, expansion ratio U[2,8]. T and W are in natural-log energy units."""
+    tau = rng.uniform(1e-3, 100e-3, size=n)
+    alpha = np.exp(-1.0 / (tau * FS))
+    thr = rng.uniform(-50.0, -30.0, size=n) * LN10_10
+    knee = np.full(n, knee_db * LN10_10)
+    ratio = rng.uniform(2.0, 8.0, size=n)
+    return np.stack([alpha, thr, knee, ratio], axis=1).astype(np.float32)
+
+
 def delay_params(rng, n, max_ms=500.0):
     """Per channel and 100 ms slot: an integer delay inside the slot encoded as a unit phasor
     z = exp(-2 pi i d / 4410), and 20 log-magnitudes for the slot's 39-tap filter: a flat level
@@ -171,13 +184,13 @@ def delay_params(rng, n, max_ms=500.0):
 
 
 PARAM_DRAW = {GAIN_PAN: gain_pan_params, EQ: eq_params, COMP: comp_params,
-              IMAGER: imager_params, DELAY: delay_params, TANH: tanh_params}
+              IMAGER: imager_params, DELAY: delay_params, TANH: tanh_params, GATE: gate_params}
 
 
 def draw_params(rng: np.random.Generator, graph: Graph) -> dict[int, np.ndarray]:
     """One parameter matrix per processor type present, rows in node order."""
     out = {}
-    for t in range(9):
+    for t in range(NUM_TYPES):
         if N_PARAMS[t] == 0:
             continue
         out[t] = PARAM_DRAW[t](rng, graph.count(t)).reshape(graph.count(t), N_PARAMS[t])
@@ -187,14 +200,14 @@ def draw_params(rng: np.random.Generator, graph: Graph) -> dict[int, np.ndarray]
 def default_params(graph: Graph) -> dict[int, np.ndarray]:
     """Neutral settings: unit gains, flat EQ, ratio-1 compressor, zero drive."""
     out = {}
-    for t in range(9):
+    for t in range(NUM_TYPES):
         if N_PARAMS[t] == 0:
             continue
         n = graph.count(t)
         p = np.zeros((n, N_PARAMS[t]), dtype=np.float32)
-        if t == COMP:
+        if t in (COMP, GATE):
             p[:, 0] = math.exp(-1.0 / (0.010 * FS))
-            p[:, 1] = -20.0 * LN10_10
+            p[:, 1] = (-20.0 if t == COMP else -40.0) * LN10_10
             p[:, 2] = 3.0 * LN10_10
             p[:, 3] = 1.0
         out[t] = p

@@ -56,6 +56,29 @@ def test_bit_exact_larger_dags(seed):
         assert_same(g, code, name, beam=32)
 
 
+@pytest.mark.parametrize("seed", range(10))
+def test_bit_exact_dags_with_noisegates(seed):
+    rng = synth.rng_for(3000 + seed, 0)
+    g = synth.random_dag(rng, int(rng.integers(8, 40)), types=(2, 3, 5, 9, 9), edge_p=0.15)
+    assert (g.node_type == synth.GATE).any()
+    for code, name in METHODS[:3]:
+        assert_same(g, code, name, beam=8)
+
+
+def test_noisegates_share_the_compressor_workspace():
+    """Compressors and noisegates run one envelope scan and share its chunk state: relabelling
+    every noisegate as a compressor leaves the workspace size unchanged."""
+    rng = synth.rng_for(3100, 0)
+    g = synth.random_dag(rng, 30, types=(2, 5, 9), edge_p=0.2)
+    assert (g.node_type == synth.GATE).any() and (g.node_type == synth.COMP).any()
+    relabelled = np.where(g.node_type == synth.GATE, synth.COMP, g.node_type).astype(np.int32)
+    a, b = Schedule(g.node_type, g.edges), Schedule(relabelled, g.edges)
+    for T in (1, 3072, 3073, 2 ** 17 + 5):
+        for bwd in (False, True):
+            assert a.workspace_bytes(T, bwd) == b.workspace_bytes(T, bwd)
+    assert a.type_count[synth.GATE] == int((g.node_type == synth.GATE).sum())
+
+
 def test_bit_exact_consoles():
     for w in (synth.tiny_console(T=8), synth.mixing_console(T=8), synth.large_console(T=8)):
         for code, name in METHODS[:3]:

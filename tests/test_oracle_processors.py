@@ -146,6 +146,52 @@ def test_compressor_static_gain_closed_form():
     assert abs(float(y[0, -1]) / c - expect) < 1e-12
 
 
+# --- noisegate (Sec. 3 "Noisegate": the compressor's envelope, a downward-expander curve) ------
+
+def test_noisegate_above_threshold_is_identity():
+    u = _rand((2, 4000), 11)
+    p = torch.tensor([0.99, -60.0, 0.69, 4.0], dtype=F64)  # T + W far below any ln(g)
+    assert torch.equal(P.noisegate(u, p), u)
+
+
+def test_noisegate_ratio_one_is_identity():
+    u = _rand((2, 4000), 12) * 1e-3
+    p = torch.tensor([0.99, 5.0, 0.69, 1.0], dtype=F64)  # everything below T, but R = 1
+    assert torch.max(torch.abs(P.noisegate(u, p) - u)) < 1e-15 * 1e-3
+
+
+def test_gate_knee_continuity():
+    thr, knee, ratio = -8.0, 0.7, 4.0
+    eps = 1e-9
+    Gu = torch.tensor([thr - knee, thr + knee], dtype=F64)
+    lo = P.gate_computer(Gu - eps, thr, knee, ratio)
+    hi = P.gate_computer(Gu + eps, thr, knee, ratio)
+    assert torch.max(torch.abs(hi - lo)) < 1e-8
+    assert abs(float(P.gate_computer(Gu[:1], thr, knee, ratio)) - (thr - ratio * knee)) < 1e-12
+    # slopes: R below, 1 above, continuous at both knee edges
+    for edge, slope in ((thr - knee, ratio), (thr + knee, 1.0)):
+        x = torch.tensor([edge - 2e-6, edge - 1e-6, edge + 1e-6, edge + 2e-6], dtype=F64)
+        y = P.gate_computer(x, thr, knee, ratio)
+        sl = float((y[1] - y[0]) / 1e-6)
+        sr = float((y[3] - y[2]) / 1e-6)
+        assert abs(sl - slope) < 1e-5 and abs(sr - slope) < 1e-5
+    # hard knee (W = 0): expander below T, identity above
+    y = P.gate_computer(torch.tensor([thr - 1.0, thr + 1.0], dtype=F64), thr, 0.0, ratio)
+    assert abs(float(y[0]) - (thr - ratio)) < 1e-12 and abs(float(y[1]) - (thr + 1.0)) < 1e-12
+
+
+def test_noisegate_static_gain_closed_form():
+    # constant input long after the envelope settled (g -> x) and below the knee: the gain is
+    # exp(G_y - G_u) = exp((R - 1)(ln(x + eps) - T))
+    T_, c = 20000, 0.01
+    u = torch.full((2, T_), c, dtype=F64)
+    alpha, thr, knee, ratio = 0.9, -2.0, 0.5, 3.0
+    y = P.noisegate(u, torch.tensor([alpha, thr, knee, ratio], dtype=F64))
+    x = (2 * c) ** 2
+    expect = math.exp((ratio - 1) * (math.log(x + 1e-8) - thr))
+    assert abs(float(y[0, -1]) / c - expect) < 1e-12 * max(1.0, expect)
+
+
 # --- gain/pan, imager, tanh (Eqs. 2-3) ----------------------------------------------------------
 
 def test_gain_pan_and_imager_closed_forms():

@@ -128,9 +128,16 @@ def _directional_check(fn, tensors, seed, eps=1e-6, rtol=2e-5, scales=None):
         assert abs(fd - an) <= rtol * max(1.0, abs(an)), (fd, an)
 
 
-@pytest.mark.parametrize("seed", range(4))
+GATE_TYPES = (synth.MIX, synth.GAIN_PAN, synth.EQ, synth.COMP, synth.GATE, synth.IMAGER, synth.TANH)
+
+
+@pytest.mark.parametrize("seed", range(6))
 def test_render_gradients_match_finite_differences(seed):
-    w = synth.random_workload(90 + seed, 9, T=5000, edge_p=0.35)
+    # cases 4 and 5 draw graphs with noisegates (seeds 105, 115: 3 and 2 of them)
+    w = synth.random_workload(90 + seed, 9, T=5000, edge_p=0.35) if seed < 4 else \
+        synth.random_workload((105, 115)[seed - 4], 9, T=5000, edge_p=0.35, types=GATE_TYPES)
+    if seed >= 4:
+        assert w.graph.count(synth.GATE) >= 2
     g = w.graph
     types = sorted(t for t in w.params if w.params[t].shape[0] > 0)
     # the delay's offsets are piecewise constant in z: keep them out of the perturbation
@@ -147,8 +154,8 @@ def test_render_gradients_match_finite_differences(seed):
         return (R.render(g.node_type, g.edges, S_, pd) * weights).sum()
 
     # the compressor's alpha sits near 1 where the output is strongly curved in it
-    scales = [1.0] + [torch.tensor([1e-2, 1, 1, 1], dtype=F64) if t == synth.COMP else 1.0
-                      for t in types]
+    scales = [1.0] + [torch.tensor([1e-2, 1, 1, 1], dtype=F64) if t in (synth.COMP, synth.GATE)
+                      else 1.0 for t in types]
     _directional_check(fn, [S] + ps, seed, scales=scales)
 
 
