@@ -17,6 +17,8 @@ Readings of passages the paper leaves open (each is listed with its reason in th
 * compressor mid signal: u_l + u_r (a sum, as printed); the envelope starts from g[-1] = 0;
   G_u = ln(g + 1e-8); the FIR of Eq. 9 is untruncated, i.e. equal to the one-pole recursion;
   the gain exp(G_y - G_u) multiplies the amplitude as printed; W <= 0 means a hard knee.
+* attack/release ballistics (Eq. 8 unrestricted): the attack coefficient applies while the
+  envelope rises, i.e. when x[t] > g[t-1]; a tie counts as release.
 * delay (Eq. 14, limited to 500 ms): five 100 ms slots of 4410 samples per channel; the delay
   inside slot m is read from the phase of z as rint(-arg(z) * 4410 / 2 pi) mod 4410, computed in
   float32 because it decides an integer; each slot's 39-tap filter follows the EQ recipe with
@@ -191,6 +193,63 @@ def noisegate(u: torch.Tensor, p: torch.Tensor, envelope=one_pole) -> torch.Tens
     return torch.exp(Gy - Gu)[None, :] * u
 
 
+class _Ballistics(torch.autograd.Function):
+    """Eq. 8 with distinct attack and release coefficients: alpha[t] = alpha_a while the envelope
+    rises (x[t] > g[t-1]) and alpha_r otherwise (an unchanged envelope, x[t] = g[t-1], counts as
+    release; both branches give the same g there); g[-1] = 0. Literal per-sample loop in float64.
+    With the branch pattern fixed the recursion is linear, so the adjoint is the one-pole adjoint
+    with a per-sample coefficient: lambda[t] = gbar[t] + alpha[t+1] lambda[t+1];
+    xbar[t] = (1 - alpha[t]) lambda[t]; the gradient of each coefficient sums
+    lambda[t] (g[t-1] - x[t]) over the samples that use it (the switch itself has zero
+    derivative almost everywhere)."""
+
+    @staticmethod
+    def forward(ctx, x, alpha_a, alpha_r):
+        xs = x.detach().numpy()
+        aa, ar = float(alpha_a), float(alpha_r)
+        g = np.empty_like(xs)
+        attack = np.zeros(xs.shape[0], dtype=bool)
+        prev = 0.0
+        for t in range(xs.shape[0]):
+            up = xs[t] > prev
+            a = aa if up else ar
+            prev = a * prev + (1.0 - a) * xs[t]
+            g[t] = prev
+            attack[t] = up
+        g = torch.as_tensor(g, dtype=F64)
+        att = torch.as_tensor(attack)
+        ctx.save_for_backward(x, alpha_a, alpha_r, g, att)
+        return g
+
+    @staticmethod
+    def backward(ctx, gbar):
+        x, alpha_a, alpha_r, g, att = ctx.saved_tensors
+        a = np.where(att.numpy(), float(alpha_a), float(alpha_r))
+        gb = gbar.detach().numpy()
+        lam = np.empty_like(gb)
+        nxt = 0.0  # alpha[t+1] lambda[t+1]
+        for t in range(gb.shape[0] - 1, -1, -1):
+            lam[t] = gb[t] + nxt
+            nxt = a[t] * lam[t]
+        lam = torch.as_tensor(lam, dtype=F64)
+        gprev = torch.cat([torch.zeros(1, dtype=F64), g[:-1]])
+        d = lam * (gprev - x)
+        xbar = torch.as_tensor(1.0 - a, dtype=F64) * lam
+        return (xbar, d[att].sum().reshape(alpha_a.shape),
+                d[~att].sum().reshape(alpha_r.shape))
+
+
+def ballistics(x: torch.Tensor, alpha_a: torch.Tensor, alpha_r: torch.Tensor) -> torch.Tensor:
+    return _Ballistics.apply(x, alpha_a, alpha_r)
+
+
+def compressor_ar(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """Compressor with distinct attack and release ballistics (Eq. 8 unrestricted, then
+    Eqs. 10-12 as for the compressor). p = (alpha_a, alpha_r, T, W, R)."""
+    return compressor(u, torch.stack([p[0], p[2], p[3], p[4]]),
+                      envelope=lambda x, _a: ballistics(x, p[0], p[1]))
+
+
 def envelope_loop(x: np.ndarray, alpha: float) -> np.ndarray:
     """Literal per-sample loop of Eq. 8 (pure Python; small inputs only)."""
     g = np.zeros_like(x, dtype=np.float64)
@@ -248,5 +307,5 @@ def identity(u: torch.Tensor, p=None) -> torch.Tensor:
 
 
 PROCESS = {2: identity, 3: gain_pan, 4: eq, 5: compressor, 6: imager, 7: delay, 8: tanh_dist,
-           9: noisegate, 1: identity}
-N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4}
+           9: noisegate, 10: compressor_ar, 1: identity}
+N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4, 10: 5}

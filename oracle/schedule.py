@@ -39,7 +39,7 @@ import dataclasses
 import numpy as np
 
 IN, OUT = 0, 1
-NUM_TYPES = 10
+NUM_TYPES = 11
 
 ONE_BY_ONE, GREEDY, BEAM, OPTIMAL = 0, 1, 2, 3
 METHOD_NAMES = {"one_by_one": ONE_BY_ONE, "greedy": GREEDY, "beam": BEAM, "optimal": OPTIMAL}

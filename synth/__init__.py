@@ -24,13 +24,13 @@ import numpy as np
 
 FS = 44100
 
-IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE = range(10)
+IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE, COMP_AR = range(11)
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
-              "noisegate")
+              "noisegate", "compressor_ar")
 NUM_TYPES = len(TYPE_NAMES)
 TYPE_CODES = {n: i for i, n in enumerate(TYPE_NAMES)}
 # parameters per node of each type (0 for in/out/mix)
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4)
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5)
 
 # delay layout: [channel 2][tap 5][re z, im z, 20 log-magnitudes]
 DELAY_TAPS = 5
@@ -154,6 +154,17 @@ def comp_params(rng, n, knee_db=3.0):
     return np.stack([alpha, thr, knee, ratio], axis=1).astype(np.float32)
 
 
+def comp_ar_params(rng, n, knee_db=3.0):
+    """(alpha_a, alpha_r, T, W, R): attack and release time constants U[1,100] ms each,
+    threshold U[-30,-10] dB, knee half-width 3 dB, ratio U[2,8]."""
+    tau = rng.uniform(1e-3, 100e-3, size=(n, 2))
+    alpha = np.exp(-1.0 / (tau * FS))
+    thr = rng.uniform(-30.0, -10.0, size=n) * LN10_10
+    knee = np.full(n, knee_db * LN10_10)
+    ratio = rng.uniform(2.0, 8.0, size=n)
+    return np.stack([alpha[:, 0], alpha[:, 1], thr, knee, ratio], axis=1).astype(np.float32)
+
+
 def gate_params(rng, n, knee_db=3.0):
     """Noisegate (alpha, T, W, R): time constant U[1,100] ms, threshold U[-50,-30] dB, knee
     half-width 3 dB, expansion ratio U[2,8]. T and W are in natural-log energy units."""
@@ -184,7 +195,8 @@ def delay_params(rng, n, max_ms=500.0):
 
 
 PARAM_DRAW = {GAIN_PAN: gain_pan_params, EQ: eq_params, COMP: comp_params,
-              IMAGER: imager_params, DELAY: delay_params, TANH: tanh_params, GATE: gate_params}
+              IMAGER: imager_params, DELAY: delay_params, TANH: tanh_params, GATE: gate_params,
+              COMP_AR: comp_ar_params}
 
 
 def draw_params(rng: np.random.Generator, graph: Graph) -> dict[int, np.ndarray]:
@@ -210,6 +222,11 @@ def default_params(graph: Graph) -> dict[int, np.ndarray]:
             p[:, 1] = (-20.0 if t == COMP else -40.0) * LN10_10
             p[:, 2] = 3.0 * LN10_10
             p[:, 3] = 1.0
+        elif t == COMP_AR:
+            p[:, 0:2] = math.exp(-1.0 / (0.010 * FS))
+            p[:, 2] = -20.0 * LN10_10
+            p[:, 3] = 3.0 * LN10_10
+            p[:, 4] = 1.0
         out[t] = p
     return out
 
@@ -276,20 +293,21 @@ class Workload:
         return self.graph.num_nodes - self.graph.count(IN)
 
 
-def tiny_console(seed=1, T=2 ** 15) -> Workload:
-    """4 sources, each in -> gain_pan -> eq -> compressor, into one mix -> gain_pan -> out."""
+def tiny_console(seed=1, T=2 ** 15, attack_release=False) -> Workload:
+    """4 sources, each in -> gain_pan -> eq -> compressor, into one mix -> gain_pan -> out.
+    With `attack_release` the compressors have distinct attack and release times."""
     g = GraphBuilder()
     ends = []
     for _ in range(4):
         i = g.add(IN)
-        a, b = g.chain([GAIN_PAN, EQ, COMP])
+        a, b = g.chain([GAIN_PAN, EQ, COMP_AR if attack_release else COMP])
         g.connect(i, a)
         ends.append(b)
     m, _ = g.chain([MIX, GAIN_PAN, OUT])
     for e in ends:
         g.connect(e, m)
     graph = g.build()
-    return Workload("tiny_console_4src", graph, make_sources(rng_for(seed, S_SOURCE), 4, T),
+    return Workload("tiny_console_4src" + ("_ar" if attack_release else ""), graph, make_sources(rng_for(seed, S_SOURCE), 4, T),
                     draw_params(rng_for(seed, S_PARAM), graph),
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
 

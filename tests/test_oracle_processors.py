@@ -146,6 +146,96 @@ def test_compressor_static_gain_closed_form():
     assert abs(float(y[0, -1]) / c - expect) < 1e-12
 
 
+# --- attack/release ballistics (Eq. 8 with distinct coefficients) ------------------------------
+
+def _bal(x, aa, ar):
+    return P.ballistics(torch.as_tensor(x, dtype=F64), torch.tensor(aa, dtype=F64),
+                        torch.tensor(ar, dtype=F64))
+
+
+def test_ballistics_equal_coefficients_is_one_pole():
+    x = np.random.default_rng(11).uniform(0, 1, 4000) ** 2
+    g = _bal(x, 0.993, 0.993).numpy()
+    ref = scipy.signal.lfilter([1 - 0.993], [1, -0.993], x)
+    assert np.max(np.abs(g - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("aa,ar", [(0.9, 0.999), (0.999, 0.95)])
+def test_ballistics_attack_then_release_closed_form(aa, ar):
+    """A step up from zero is all attack: g = c (1 - aa^(n+1)); after the step down to 0 it is
+    all release: g = g_end ar^(n+1)."""
+    c, n1, n2 = 0.25, 700, 900
+    x = np.concatenate([np.full(n1, c), np.zeros(n2)])
+    g = _bal(x, aa, ar).numpy()
+    t = np.arange(n1)
+    up = c * (1 - aa ** (t + 1))
+    assert np.max(np.abs(g[:n1] - up)) < 1e-15
+    t2 = np.arange(n2)
+    assert np.max(np.abs(g[n1:] - up[-1] * ar ** (t2 + 1))) < 1e-15
+
+
+@pytest.mark.parametrize("aa,ar", [(0.95, 0.999), (0.999, 0.9), (0.99, 0.99)])
+def test_ballistics_is_max_or_min_of_two_affine_maps(aa, ar):
+    """Since g_a - g_r = (ar - aa)(x - g_prev), the branch rule picks the larger of the two
+    one-pole updates when attack is the faster one (aa <= ar) and the smaller otherwise."""
+    x = np.random.default_rng(12).uniform(0, 1, 3000) ** 3
+    g = _bal(x, aa, ar).numpy()
+    pick = max if aa <= ar else min
+    prev, ref = 0.0, np.empty_like(x)
+    for t in range(x.shape[0]):
+        prev = pick(aa * prev + (1 - aa) * x[t], ar * prev + (1 - ar) * x[t])
+        ref[t] = prev
+    assert np.max(np.abs(g - ref)) < 1e-15
+
+
+def test_ballistics_adjoint_matches_autograd_of_the_loop_and_fd():
+    """The hand-written adjoint against torch autograd through the per-sample recursion written
+    with torch ops (where the branch is a comparison, not differentiated), and against central
+    finite differences in both coefficients."""
+    rng = np.random.default_rng(13)
+    x = torch.as_tensor(rng.uniform(0, 1, 400) ** 2).requires_grad_(True)
+    aa = torch.tensor(0.93, dtype=F64, requires_grad=True)
+    ar = torch.tensor(0.985, dtype=F64, requires_grad=True)
+    w = torch.as_tensor(rng.normal(size=400))
+    g1 = torch.autograd.grad((P.ballistics(x, aa, ar) * w).sum(), (x, aa, ar))
+    prev, out = torch.zeros((), dtype=F64), []
+    for t in range(400):
+        a = aa if bool(x[t] > prev) else ar
+        prev = a * prev + (1 - a) * x[t]
+        out.append(prev)
+    g2 = torch.autograd.grad((torch.stack(out) * w).sum(), (x, aa, ar))
+    for a_, b_ in zip(g1, g2):
+        assert torch.max(torch.abs(a_ - b_)) < 1e-11
+    for which in (1, 2):
+        h = 1e-7
+        args = [x.detach(), aa.detach(), ar.detach()]
+        hi = list(args); hi[which] = args[which] + h
+        lo = list(args); lo[which] = args[which] - h
+        fd = float(((P.ballistics(*hi) - P.ballistics(*lo)) * w).sum()) / (2 * h)
+        assert abs(fd - float(g1[which])) < 1e-5 * max(1.0, abs(fd))
+
+
+def test_compressor_ar_with_equal_coefficients_is_compressor():
+    u = _rand((2, 3000), 3) * 4
+    p5 = torch.tensor([0.995, 0.995, -3.0, 0.6, 4.0], dtype=F64)
+    p4 = torch.tensor([0.995, -3.0, 0.6, 4.0], dtype=F64)
+    assert torch.max(torch.abs(P.compressor_ar(u, p5) - P.compressor(u, p4))) < 1e-14
+
+
+def test_compressor_ar_parameter_gradients_match_fd():
+    u = _rand((2, 600), 4) * 4
+    p = torch.tensor([0.97, 0.995, -3.0, 0.6, 4.0], dtype=F64, requires_grad=True)
+    w = torch.as_tensor(np.random.default_rng(14).normal(size=(2, 600)))
+    (gp,) = torch.autograd.grad((P.compressor_ar(u, p) * w).sum(), (p,))
+    for i in range(5):
+        h = 1e-7
+        e = torch.zeros(5, dtype=F64)
+        e[i] = h
+        fd = float(((P.compressor_ar(u, p.detach() + e) - P.compressor_ar(u, p.detach() - e))
+                    * w).sum()) / (2 * h)
+        assert abs(fd - float(gp[i])) < 1e-5 * max(1.0, abs(fd)), (i, fd, float(gp[i]))
+
+
 # --- noisegate (Sec. 3 "Noisegate": the compressor's envelope, a downward-expander curve) ------
 
 def test_noisegate_above_threshold_is_identity():

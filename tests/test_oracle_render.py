@@ -129,15 +129,21 @@ def _directional_check(fn, tensors, seed, eps=1e-6, rtol=2e-5, scales=None):
 
 
 GATE_TYPES = (synth.MIX, synth.GAIN_PAN, synth.EQ, synth.COMP, synth.GATE, synth.IMAGER, synth.TANH)
+AR_TYPES = (synth.MIX, synth.GAIN_PAN, synth.EQ, synth.COMP_AR, synth.IMAGER, synth.TANH)
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(8))
 def test_render_gradients_match_finite_differences(seed):
-    # cases 4 and 5 draw graphs with noisegates (seeds 105, 115: 3 and 2 of them)
-    w = synth.random_workload(90 + seed, 9, T=5000, edge_p=0.35) if seed < 4 else \
-        synth.random_workload((105, 115)[seed - 4], 9, T=5000, edge_p=0.35, types=GATE_TYPES)
-    if seed >= 4:
+    # cases 4 and 5 draw graphs with noisegates (seeds 105, 115: 3 and 2 of them), cases 6 and 7
+    # graphs with attack/release compressors (seeds 131, 138: 4 and 3 of them)
+    if seed < 4:
+        w = synth.random_workload(90 + seed, 9, T=5000, edge_p=0.35)
+    elif seed < 6:
+        w = synth.random_workload((105, 115)[seed - 4], 9, T=5000, edge_p=0.35, types=GATE_TYPES)
         assert w.graph.count(synth.GATE) >= 2
+    else:
+        w = synth.random_workload((131, 138)[seed - 6], 9, T=5000, edge_p=0.35, types=AR_TYPES)
+        assert w.graph.count(synth.COMP_AR) >= 3
     g = w.graph
     types = sorted(t for t in w.params if w.params[t].shape[0] > 0)
     # the delay's offsets are piecewise constant in z: keep them out of the perturbation
@@ -155,6 +161,7 @@ def test_render_gradients_match_finite_differences(seed):
 
     # the compressor's alpha sits near 1 where the output is strongly curved in it
     scales = [1.0] + [torch.tensor([1e-2, 1, 1, 1], dtype=F64) if t in (synth.COMP, synth.GATE)
+                      else torch.tensor([1e-2, 1e-2, 1, 1, 1], dtype=F64) if t == synth.COMP_AR
                       else 1.0 for t in types]
     _directional_check(fn, [S] + ps, seed, scales=scales)
 
