@@ -38,11 +38,12 @@ EQ_FFT = 4096
 WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
              "batch": "batched_graphs"}
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
-              "noisegate")
+              "noisegate", "compressor_ar")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
 KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
               "imager": "k_pointwise.hip", "tanh": "k_pointwise.hip", "eq": "k_eq.hip",
-              "compressor": "k_comp.hip", "noisegate": "k_comp.hip", "delay": "k_delay.hip"}
+              "compressor": "k_comp.hip", "noisegate": "k_comp.hip", "compressor_ar": "k_comp_ar.hip",
+              "delay": "k_delay.hip"}
 
 
 def parse():

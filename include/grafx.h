@@ -38,6 +38,8 @@
  *   8 tanh       1    y = tanh(exp(p) u)                                  (not in the paper)
  *   9 noisegate  4    (alpha, T, W, R): the compressor's envelope with a downward-expander
  *                     curve, ratio R >= 1 below T - W, quadratic knee   (Sec. 3 "Noisegate")
+ *  10 compressor_ar 5 (alpha_a, alpha_r, T, W, R): the compressor with distinct attack and
+ *                     release coefficients, alpha_a while x[t] > g[t-1]  (Eq. 8 unrestricted)
  * The node input is the sum over incoming edges of the source node outputs (Eq. 1b), parallel
  * edges counted once each, summed in original edge order.
  */
@@ -68,7 +70,7 @@ typedef enum grafx_status {
 enum {
   GRAFX_IN = 0, GRAFX_OUT = 1, GRAFX_MIX = 2, GRAFX_GAIN_PAN = 3, GRAFX_EQ = 4,
   GRAFX_COMPRESSOR = 5, GRAFX_IMAGER = 6, GRAFX_DELAY = 7, GRAFX_TANH = 8, GRAFX_NOISEGATE = 9,
-  GRAFX_NUM_TYPES = 10
+  GRAFX_COMPRESSOR_AR = 10, GRAFX_NUM_TYPES = 11
 };
 
 /* Schedule search methods (paper Sec. 2 "Type scheduling"; Sec. 4 "Speed benchmark"). */

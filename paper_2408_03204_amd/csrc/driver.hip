@@ -2,6 +2,7 @@
 // of its adjoint, the plan upload and the workspace layout. Every argument is checked before the
 // first launch; the drivers only enqueue kernels on the caller's stream.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "device_common.h"
@@ -17,8 +18,10 @@ namespace {
 // envelope scan and share one set of chunk totals, carries, tickets and gradient partials.
 struct WsLayout {
   size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps, delay_offs;
+  size_t ar_slots, ar_carry, ar_pat, ar_tickets;
   size_t fwd_end;
   size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part;
+  size_t ar_ragg, ar_part;
   size_t total;
 };
 
@@ -28,6 +31,18 @@ size_t n_dynamics(const grafx_schedule_t* h) {
 }
 int dyn_row(const grafx_schedule_t* h, int t) {
   return t == GRAFX_NOISEGATE ? h->type_count[GRAFX_COMPRESSOR] : 0;
+}
+
+// Published words per attack/release node: kArPasses pass rows of (A, B, flag), then the final
+// (A, B) of every chunk.
+size_t ar_slot_words(size_t chunks) { return (size_t)kArPasses * chunks * 3 + chunks * 2; }
+
+// Most branch-pattern passes of the attack/release forward before the serial fallback
+// (GRAFX_AR_MAX_PASSES, 1..kArPasses; a small value exercises the fallback).
+int ar_max_pass() {
+  const char* e = std::getenv("GRAFX_AR_MAX_PASSES");
+  const int v = e ? std::atoi(e) : kArPasses;
+  return std::min(std::max(v, 1), kArPasses);
 }
 
 WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
@@ -47,6 +62,13 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   L.comp_tickets = take((2 * n_comp * kCompTicketStride + 1) * sizeof(unsigned));
   L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
   L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
+  // attack/release compressors: per-pass and final chunk maps (reset), entering states and final
+  // branch patterns (kept for the adjoint), forward then adjoint ticket counters
+  const size_t n_ar = h->type_count[GRAFX_COMPRESSOR_AR];
+  L.ar_slots = take(n_ar * ar_slot_words(chunks) * sizeof(uint64_t));
+  L.ar_carry = take(n_ar * chunks * sizeof(double));
+  L.ar_pat = take(n_ar * chunks * kBlock * sizeof(uint16_t));
+  L.ar_tickets = take(2 * n_ar * kCompTicketStride * sizeof(unsigned));
   L.fwd_end = off;
   if (with_bwd) {
     const size_t tiles = pointwise_tiles(T);
@@ -65,6 +87,8 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.eq_spec = take(n_eq * kEqFoldStride * sizeof(float));
     L.eq_s = take(n_eq * 1024 * sizeof(double));
     L.delay_part = take(n_del * delay_groups(T) * kDelayCoef * sizeof(float));
+    L.ar_ragg = take(n_ar * chunks * 2 * sizeof(uint64_t));
+    L.ar_part = take(n_ar * chunks * kArParams * sizeof(double));
   }
   L.total = off;
   return L;
@@ -142,6 +166,20 @@ hipError_t reset_comp(const grafx_schedule_t* h, void* ws, const WsLayout& L, bo
                            n_comp * kCompTicketStride, stream);
 }
 
+// Reset the attack/release chaining state of one pass.
+hipError_t reset_ar(const grafx_schedule_t* h, void* ws, const WsLayout& L, bool bwd, int64_t T,
+                    hipStream_t stream) {
+  const int n_ar = h->type_count[GRAFX_COMPRESSOR_AR];
+  if (n_ar == 0) return hipSuccess;
+  const size_t chunks = comp_chunks(T);
+  unsigned* t = at<unsigned>(ws, L.ar_tickets) + (bwd ? (size_t)n_ar * kCompTicketStride : 0);
+  if (bwd)
+    return launch_comp_reset(at<uint64_t>(ws, L.ar_ragg), (int64_t)(n_ar * chunks * 2), t,
+                             n_ar * kCompTicketStride, stream);
+  return launch_comp_reset(at<uint64_t>(ws, L.ar_slots), (int64_t)(n_ar * ar_slot_words(chunks)),
+                           t, n_ar * kCompTicketStride, stream);
+}
+
 hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
                             float* U, void* ws, const WsLayout& L, int n, hipStream_t stream) {
   const int t = h->step_type[n];
@@ -166,6 +204,14 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_DELAY:
       return launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
                               cnt, stream);
+    case GRAFX_COMPRESSOR_AR: {
+      const size_t n_ar = h->type_count[GRAFX_COMPRESSOR_AR], chunks = comp_chunks(g.T);
+      uint64_t* slots = at<uint64_t>(ws, L.ar_slots);
+      return launch_comp_ar_fwd(g, U, p, b, cnt, ar_max_pass(), slots,
+                                slots + n_ar * (size_t)kArPasses * chunks * 3,
+                                at<double>(ws, L.ar_carry), at<uint16_t>(ws, L.ar_pat),
+                                at<unsigned>(ws, L.ar_tickets), error_word(ws, L, h), stream);
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -198,6 +244,13 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_DELAY:
       return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
                               b, cnt, at<float>(ws, L.delay_part), stream);
+    case GRAFX_COMPRESSOR_AR:
+      return launch_comp_ar_bwd(g, dU, p, b, cnt, at<double>(ws, L.ar_carry),
+                                at<uint16_t>(ws, L.ar_pat), at<uint64_t>(ws, L.ar_ragg),
+                                at<double>(ws, L.ar_part),
+                                at<unsigned>(ws, L.ar_tickets) +
+                                    (size_t)h->type_count[GRAFX_COMPRESSOR_AR] * kCompTicketStride,
+                                error_word(ws, L, h), stream);
     default:
       return hipErrorInvalidValue;
   }
@@ -254,6 +307,7 @@ grafx_status grafx_render(const grafx_schedule_t* h, const void* dev_plan, int64
     e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
                             at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
   if (e == hipSuccess) e = reset_comp(h, ws, L, false, T, stream);
+  if (e == hipSuccess) e = reset_ar(h, ws, L, false, T, stream);
   for (int n = 1; n <= h->N && e == hipSuccess; ++n)
     e = enqueue_fwd_step(h, g, P, U, ws, L, n, stream);
   return hip_status(e, "render launch");
@@ -276,6 +330,7 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
   auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
   auto dpar = [&](int t) -> float* { return dP ? dP[t] : nullptr; };
   hipError_t e = reset_comp(h, ws, L, true, T, stream);
+  if (e == hipSuccess) e = reset_ar(h, ws, L, true, T, stream);
   for (int n = h->N - 1; n >= 1 && e == hipSuccess; --n)
     e = enqueue_bwd_step(h, g, P, dU, ws, L, n, stream);
   if (e == hipSuccess && dS && h->K > 0)  // adjoint of the input step: sum over output edges
@@ -294,6 +349,9 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     if (e == hipSuccess && dpar(t) && h->type_count[t] > 0)
       e = launch_reduce_partials(at<double>(ws, L.comp_part) + (size_t)dyn_row(h, t) * chunks * 4,
                                  h->type_count[t], chunks, 4, dpar(t), stream);
+  if (e == hipSuccess && dpar(GRAFX_COMPRESSOR_AR))
+    e = launch_reduce_partials(at<double>(ws, L.ar_part), h->type_count[GRAFX_COMPRESSOR_AR],
+                               chunks, kArParams, dpar(GRAFX_COMPRESSOR_AR), stream);
   if (e == hipSuccess && dpar(GRAFX_EQ))
     e = launch_eq_grad(par(GRAFX_EQ), at<float>(ws, L.eq_spec), h->type_count[GRAFX_EQ],
                        at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
@@ -314,6 +372,7 @@ grafx_status grafx_render_step(const grafx_schedule_t* h, const void* dev_plan, 
   const GraphView g = make_view(h, dev_plan, T, S, U);
   hipError_t e = hipSuccess;
   if (is_dynamics(h->step_type[step])) e = reset_comp(h, ws, L, false, T, stream);
+  if (h->step_type[step] == GRAFX_COMPRESSOR_AR) e = reset_ar(h, ws, L, false, T, stream);
   if (e == hipSuccess) e = enqueue_fwd_step(h, g, P, U, ws, L, step, stream);
   return hip_status(e, "render_step launch");
 }
@@ -333,6 +392,7 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* d
   g.dU = dU;
   hipError_t e = hipSuccess;
   if (is_dynamics(h->step_type[step])) e = reset_comp(h, ws, L, true, T, stream);
+  if (h->step_type[step] == GRAFX_COMPRESSOR_AR) e = reset_ar(h, ws, L, true, T, stream);
   if (e == hipSuccess) e = enqueue_bwd_step(h, g, P, dU, ws, L, step, stream);
   return hip_status(e, "render_backward_step launch");
 }

@@ -11,7 +11,7 @@
 namespace grafx {
 
 constexpr int kNumTypes = GRAFX_NUM_TYPES;
-constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1, 4};
+constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5};
 
 // Thread-local error message, set by every failing entry point.
 grafx_status fail(grafx_status code, const std::string& msg);

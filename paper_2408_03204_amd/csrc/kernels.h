@@ -59,6 +59,22 @@ hipError_t launch_comp_bwd(const GraphView& g, float* dU, const float* P, int no
                            uint64_t* ragg, double* part, unsigned* ticket, unsigned* err,
                            hipStream_t s);
 
+// ---- compressor with attack/release ballistics (k_comp_ar.hip) -----------------------------
+constexpr int kArParams = 5;   // alpha_a, alpha_r, T, W, R
+constexpr int kArPasses = 16;  // branch-pattern passes before a chunk falls back to the serial loop
+// pslot: uint64 [n_ar][kArPasses][chunks][3] and fin: uint64 [n_ar][chunks][2], both reset to
+// "not ready"; carry: double [n_ar][chunks] and pats: uint16 [n_ar][chunks][kBlock] are written
+// for the adjoint; ragg: uint64 [n_ar][chunks][2] (reset); part: double [n_ar][chunks][5];
+// ticket: kCompTicketStride words per node (reset to 0); err as for the compressor.
+hipError_t launch_comp_ar_fwd(const GraphView& g, float* U, const float* P, int node_begin,
+                              int n_nodes, int max_pass, uint64_t* pslot, uint64_t* fin,
+                              double* carry, uint16_t* pats, unsigned* ticket, unsigned* err,
+                              hipStream_t s);
+hipError_t launch_comp_ar_bwd(const GraphView& g, float* dU, const float* P, int node_begin,
+                              int n_nodes, const double* carry, const uint16_t* pats,
+                              uint64_t* ragg, double* part, unsigned* ticket, unsigned* err,
+                              hipStream_t s);
+
 // ---- delay (k_delay.hip) -------------------------------------------------------------------
 constexpr int kDelayTaps = 5, kDelayFir = 39, kDelaySlot = 4410;
 constexpr int kDelayCoef = 2 * kDelayTaps * kDelayFir;  // 390 per node
