@@ -21,6 +21,7 @@ captured once from the same C-ABI calls); `--mode eager` issues those calls one 
 from __future__ import annotations
 
 import argparse
+import functools
 import hashlib
 import json
 import os
@@ -36,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32; unpacked issue is half of it)
 EQ_FFT = 4096
 WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
-             "batch": "batched_graphs"}
+             "batch": "batched_graphs", "console_ar": "mixing_console"}
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
               "noisegate", "compressor_ar")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
@@ -204,6 +205,8 @@ def setup_console(args, dev):
     from paper_2408_03204_amd import GradStep, Schedule, mrstft_loss, render
 
     maker = getattr(synth, WORKLOADS[args.workload])
+    if args.workload == "console_ar":  # the same console, attack/release compressors
+        maker = functools.partial(maker, attack_release=True)
     w = maker(T=args.T) if args.T else maker()
     g = w.graph
     sched = Schedule(g.node_type, g.edges, args.method)

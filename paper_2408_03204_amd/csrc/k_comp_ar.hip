@@ -9,10 +9,12 @@
 // derives the next one from the envelope it produced. If a pass leaves the pattern of a time
 // prefix unchanged, that prefix is exact: at the first sample where a pattern is wrong, the
 // envelope before it is exact, so the next pattern corrects that sample and differs there.
-// Hence a chunk is final once its own pattern and those of all earlier chunks are unchanged by
-// the same pass (random signals settle in 2-7 passes). Chunk c of pass k waits only for maps and
-// flags of earlier chunks of pass k: a chunk that settles early fills its later pass slots with
-// its final map, so no wait depends on a later chunk and every wait ends. A chunk still unsettled
+// Hence a chunk is final once its own pattern and those of all earlier chunks were left unchanged
+// by the previous pass (random signals settle in 3-8 passes). Each pass publishes, per chunk, its
+// map and whether the chunk's pattern changed in the previous pass, so one round of publication
+// serves both the entering state and the settling test. Chunk c of pass k waits only for words of
+// earlier chunks of pass k: a chunk that settles fills its later pass slots with its final map, so
+// no wait depends on a later chunk and every wait ends. A chunk still unsettled
 // after the last pass takes the exact state entering it from the final maps of the earlier
 // chunks and runs the literal recursion over its 3072 samples on one thread, which settles it.
 //
@@ -144,6 +146,26 @@ __device__ __forceinline__ double fold_maps(uint64_t* base, int stride, int n, u
   return total.B;
 }
 
+// fold_maps<true> over the pass rows (A, B, flag) of the chunks before `chunk`, which also
+// returns in `all` whether `own` and every earlier chunk's flag are set (block-uniform).
+__device__ __forceinline__ double fold_maps_flags(uint64_t* row, int chunk, unsigned* err,
+                                                  Aff* wtot, bool own, bool& all) {
+  const int per = (chunk + kBlock - 1) / kBlock;
+  const int lo = min(chunk, (int)threadIdx.x * per), hi = min(chunk, lo + per);
+  Aff m = {1.0, 0.0};
+  bool ok = own;
+  for (int r = lo; r < hi; ++r) {
+    uint64_t* w = row + (int64_t)r * 3;
+    const Aff o = {await_total(w, err), await_total(w + 1, err)};
+    ok = ok && await_total(w + 2, err) == 1.0;
+    m = after(o, m);
+  }
+  all = __syncthreads_and(ok) != 0;
+  Aff total;
+  aff_scan<false>(m, wtot, total);
+  return total.B;
+}
+
 // ---- forward ----------------------------------------------------------------------------------
 
 // pslot: [n_ar][kArPasses][chunks][3] (A, B, stable flag) per pass; fin: [n_ar][chunks][2] final
@@ -179,42 +201,42 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
   }
   uint64_t* ps = pslot + (int64_t)slot * kArPasses * chunks * 3;
   uint64_t* fn = fin + (int64_t)slot * chunks * 2;
-  int pat = 0;  // pass 0: every sample taken as release
+  int pat = 0;   // pass 0: every sample taken as release
+  int prev = 0;  // the pattern of the previous pass
   bool done = false;
   double cin = 0.0;
   Aff tot = {1.0, 0.0};
   for (int pass = 0; pass < max_pass && !done; ++pass) {
-    Aff ex = aff_scan<false>(thread_map(x, pat, k), wtot, tot);
+    const Aff ex = aff_scan<false>(thread_map(x, pat, k), wtot, tot);
+    // did the previous pass leave this chunk's pattern unchanged?
+    const bool same = __syncthreads_and(pass > 0 && pat == prev) != 0;
     uint64_t* row = ps + (int64_t)pass * chunks * 3;
     if (threadIdx.x == 0) {
       publish(row + (int64_t)chunk * 3, tot.A);
       publish(row + (int64_t)chunk * 3 + 1, tot.B);
+      publish(row + (int64_t)chunk * 3 + 2, same ? 1.0 : 0.0);
     }
-    cin = fold_maps<true>(row, 3, chunk, err, wtot);
-    // the next pattern, from the envelope of this pass
-    double s = fma(ex.A, cin, ex.B);
-    int np = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const double xi = (double)x[i];
-      np |= (int)(xi > s) << i;
-      const bool up = (pat >> i) & 1;
-      s = fma(up ? k.aa : k.ar, s, (up ? k.ba : k.br) * xi);
-    }
-    const bool stable = __syncthreads_and(np == pat) != 0;
-    if (threadIdx.x == 0) publish(row + (int64_t)chunk * 3 + 2, stable ? 1.0 : 0.0);
-    int ok = 1;
-    for (int j = threadIdx.x; j < chunk; j += kBlock)
-      ok &= await_total(row + (int64_t)j * 3 + 2, err) == 1.0;
-    done = __syncthreads_and(ok && stable) != 0;
-    if (done) {  // final: the later passes of this chunk see the same map, stable
+    bool all_same;
+    cin = fold_maps_flags(row, chunk, err, wtot, same, all_same);
+    if (all_same) {  // the pattern of this pass is exact up to the chunk's end, and so is cin
+      done = true;
       for (int q = pass + 1 + (int)threadIdx.x; q < max_pass; q += kBlock) {
         uint64_t* r = ps + ((int64_t)q * chunks + chunk) * 3;
         publish(r, tot.A);
         publish(r + 1, tot.B);
         publish(r + 2, 1.0);
       }
-    } else {
+    } else {  // the next pattern, from the envelope of this pass
+      double s = fma(ex.A, cin, ex.B);
+      int np = 0;
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const double xi = (double)x[i];
+        np |= (int)(xi > s) << i;
+        const bool up = (pat >> i) & 1;
+        s = fma(up ? k.aa : k.ar, s, (up ? k.ba : k.br) * xi);
+      }
+      prev = pat;
       pat = np;
     }
   }

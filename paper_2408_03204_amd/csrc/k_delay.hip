@@ -140,19 +140,28 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
 constexpr int kTapTiles = 8;
 
 // Tap gradients: part[slot][group][c*5+m][j] = sum over the group's tiles of
-// sum_t ybar_c[t] u_c[t - d - j].
+// sum_t ybar_c[t] u_c[t - d - j]. One block per (node, group, channel-slot): the ten sums of a
+// group are independent, so splitting them over blocks keeps ten times more stage-and-compute
+// chains in flight (the kernel is bound by their latency). Logical blocks are laid out node,
+// group, channel-slot and spread XCD-contiguously, so the five slots of a channel, which stage
+// the same adjoint tiles, share an L2.
 __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, const int32_t* offs,
                                                                int node_begin, int tiles,
                                                                int groups, float* part) {
   __shared__ float w[kWin];
   __shared__ float yb[kHop];
   __shared__ float red[4][kDelayFir];
-  const int group = blockIdx.x, node = node_begin + blockIdx.y;
+  constexpr int kCM = 2 * kDelayTaps;
+  const int nb = (int)(gridDim.x * gridDim.y);
+  const int lb = xcd_logical_block((int)(blockIdx.y * gridDim.x + blockIdx.x), nb);
+  const int per_node = groups * kCM;
+  const int node = node_begin + lb / per_node;
+  const int group = (lb % per_node) / kCM, cm = lb % kCM;
   const int slot = g.param_row[node];
   const int tiles_n = (int)((node_len(g, node) + kHop - 1) / kHop);  // the node's own tiles
   const int tile_end = min(min(tiles, tiles_n), (group + 1) * kTapTiles);
   const int o0 = kPer * threadIdx.x;
-  for (int cm = 0; cm < 2 * kDelayTaps; ++cm) {
+  {
     const int c = cm / kDelayTaps;
     const int d = offs[(int64_t)slot * 2 * kDelayTaps + cm];
     float acc[kDelayFir];
@@ -245,8 +254,8 @@ hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
   delay_conv_kernel<true><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, dU, taps, offs, node_begin,
                                                                   tiles);
   const int groups = delay_groups(g.T);
-  delay_tapgrad_kernel<<<dim3(groups, n_nodes), kBlock, 0, s>>>(g, offs, node_begin, tiles,
-                                                                groups, part);
+  delay_tapgrad_kernel<<<dim3(groups * 2 * kDelayTaps, n_nodes), kBlock, 0, s>>>(
+      g, offs, node_begin, tiles, groups, part);
   return hipGetLastError();
 }
 

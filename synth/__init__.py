@@ -312,12 +312,16 @@ def tiny_console(seed=1, T=2 ** 15, attack_release=False) -> Workload:
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
 
 
-def mixing_console(seed=2, T=2 ** 18, n_tracks=64, n_bus=8) -> Workload:
+def mixing_console(seed=2, T=2 ** 18, n_tracks=64, n_bus=8, attack_release=False) -> Workload:
     """64 tracks with chains of 1-3 from {eq, compressor, gain_pan, imager}, 8 buses of
-    mix -> eq -> compressor, master mix -> eq -> compressor -> gain_pan -> out."""
+    mix -> eq -> compressor, master mix -> eq -> compressor -> gain_pan -> out. With
+    `attack_release` every compressor has distinct attack and release times (same graph)."""
     graph = console_graph(rng_for(seed, S_STRUCT), n_tracks, [n_bus])
+    if attack_release:
+        graph = Graph(np.where(graph.node_type == COMP, COMP_AR, graph.node_type).astype(np.int32),
+                      graph.edges)
     K = graph.count(IN)
-    return Workload(f"mixing_console_{n_tracks}trk", graph,
+    return Workload(f"mixing_console_{n_tracks}trk" + ("_ar" if attack_release else ""), graph,
                     make_sources(rng_for(seed, S_SOURCE), K, T),
                     draw_params(rng_for(seed, S_PARAM), graph),
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
