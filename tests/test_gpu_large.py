@@ -1,0 +1,102 @@
+"""GPU parity on the large console (256 tracks, 904 nodes, T = 2^20): one render and one adjoint
+of a seeded output adjoint, the backward keeping only the node outputs U and recomputing every
+node's internals (aggregated input, spectra, envelope) from them, plus the compressor's chunk
+carries. A whole-graph FP64 oracle at this size would hold on the order of 10^11 bytes of
+autograd state, so the check is local and sampled: for nodes of every processing type spread
+over the schedule, the single-node FP64 oracle is fed the GPU's own rows (the node's aggregated
+input from U, its output adjoint from dU and dY) and must reproduce the node's output row
+(within 1e-5 of its peak), its input-adjoint row and its parameter-gradient row (within 1e-3 of
+their largest entries). The output rows must equal the sums of their input rows."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import GRAD_TOL, RENDER_TOL, grad_err, rel_err, say
+from oracle import render as OR
+from paper_2408_03204_amd import RenderBuffers, Schedule
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+PER_TYPE = 5
+
+
+@pytest.mark.timeout(400)
+def test_large_console_sampled_nodes_forward_and_adjoint():
+    w = synth.large_console()
+    g = w.graph
+    say(f"[large] {w.name} nodes={g.num_nodes} T={w.T}")
+    dev = torch.device("cuda")
+    sched = Schedule(g.node_type, g.edges, "beam")
+    S = torch.as_tensor(w.sources, device=dev)
+    P = {t: torch.as_tensor(p, device=dev) for t, p in w.params.items() if p.shape[0] > 0}
+    rb = RenderBuffers(sched, w.T, dev, with_backward=True)
+    rb.forward(S, P)
+    dY = torch.as_tensor(np.random.default_rng(11).standard_normal(
+        (sched.num_outputs, 2, w.T)).astype(np.float32), device=dev)
+    dP = {t: torch.empty_like(p) for t, p in P.items()}
+    rb.backward(S, P, dY, dP)
+    torch.cuda.synchronize()
+    say("   render and adjoint done")
+
+    pos = np.empty(g.num_nodes, dtype=np.int64)
+    pos[sched.perm] = np.arange(g.num_nodes)
+    rows = OR.param_rows(g.node_type)
+    ins = [[] for _ in range(g.num_nodes)]
+    outs = [[] for _ in range(g.num_nodes)]
+    for e in range(g.num_edges):
+        s, d = int(g.edges[0, e]), int(g.edges[1, e])
+        ins[d].append(s)
+        outs[s].append(d)
+    out_begin = sched.out_begin
+
+    def out_row(v):  # output of node v, float64 on the host
+        if g.node_type[v] == synth.IN:
+            return torch.as_tensor(w.sources[rows[v]], dtype=F64)
+        return rb.U[pos[v]].double().cpu()
+
+    def adj_in(v):  # adjoint of node v's output: sum over its out-edges
+        a = torch.zeros((2, w.T), dtype=F64)
+        for d in outs[v]:
+            a += dY[pos[d] - out_begin].double().cpu() if pos[d] >= out_begin else \
+                rb.dU[pos[d]].double().cpu()
+        return a
+
+    # output rows are the sums of their inputs
+    for o in range(out_begin, g.num_nodes):
+        v = int(sched.perm[o])
+        u = sum(out_row(s) for s in ins[v])
+        assert rel_err(rb.U[o].double().cpu().numpy(), u.numpy()) <= 1e-6
+
+    # sampled processing nodes, spread over the schedule order within each type
+    order = sorted((v for v in range(g.num_nodes) if g.node_type[v] not in (synth.IN, synth.OUT)),
+                   key=lambda v: pos[v])
+    picked = []
+    for t in sorted(set(int(g.node_type[v]) for v in order)):
+        vs = [v for v in order if g.node_type[v] == t]
+        idx = np.unique(np.linspace(0, len(vs) - 1, min(PER_TYPE, len(vs))).round().astype(int))
+        picked += [vs[i] for i in idx]
+    P64 = OR.as_params64(w.params)
+    worst = {}
+    for v in picked:
+        t = int(g.node_type[v])
+        u = sum(out_row(s) for s in ins[v]).clone().requires_grad_(True)
+        p = P64[t][rows[v]].clone().requires_grad_(True) if t in P64 else None
+        y = OR.node_forward(t, u, p)
+        e_y = rel_err(rb.U[pos[v]].double().cpu().numpy(), y.detach().numpy())
+        ybar = adj_in(v)
+        wrt = [u] + ([p] if p is not None else [])
+        grads = torch.autograd.grad(y, wrt, ybar, allow_unused=True)
+        e_u = grad_err(rb.dU[pos[v]].cpu().numpy(), grads[0].numpy())
+        e_p = 0.0
+        if p is not None:
+            gp = grads[1] if grads[1] is not None else torch.zeros_like(p)
+            e_p = grad_err(dP[t][rows[v]].cpu().numpy(), gp.numpy())
+        name = synth.TYPE_NAMES[t]
+        worst[name] = tuple(max(a, b) for a, b in zip(worst.get(name, (0.0, 0.0, 0.0)),
+                                                       (e_y, e_u, e_p)))
+        assert e_y <= RENDER_TOL, (v, name, "y", e_y)
+        assert e_u <= GRAD_TOL, (v, name, "ubar", e_u)
+        assert e_p <= GRAD_TOL, (v, name, "dp", e_p)
+    say(f"   {len(picked)} nodes; worst (y, ubar, dp) per type:",
+        {k: tuple(f"{x:.1e}" for x in e) for k, e in worst.items()})
