@@ -12,9 +12,11 @@ written to be checked against the paper by eye:
 * `render`    -- the graph evaluated one node at a time in topological order (Sec. 2,
                  "Definitions", Eq. 1).
 * `mrstft`    -- the multi-resolution STFT loss used to drive gradient descent (Sec. 4).
+* `encoder`   -- the learned parameter initialiser of the gradient-descent application: log-mel
+                 features, the convolutional encoder, its training loss and Adam.
 
 Gradients come from torch autograd in float64. The oracle shares no code with the HIP library.
 Parity status of every function is listed in the module that defines it; the only function
 without an independent pin is marked "parity unpinned" there.
 """
-from . import mrstft, processors, render, schedule  # noqa: F401
+from . import encoder, mrstft, processors, render, schedule  # noqa: F401

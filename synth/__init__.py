@@ -312,6 +312,57 @@ def tiny_console(seed=1, T=2 ** 15, attack_release=False) -> Workload:
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
 
 
+# ---------------------------------------------------------------------------------------------
+# labelled tiny consoles (training and evaluation data of the learned initialiser)
+
+LABEL_RANGES = [(-12.0, 6.0), (-12.0, 6.0)] + [(-12.0, 12.0)] * 6 + [(1.0, 100.0),
+                                                                   (-30.0, -10.0), (2.0, 8.0)]
+N_LABELS = len(LABEL_RANGES)
+
+
+def eq_from_bands(band_db: np.ndarray) -> np.ndarray:
+    """Six band gains (dB) -> 1024 log-magnitudes, the rule of `eq_params`."""
+    centres = 20.0 * 1000.0 ** ((np.arange(6) + 0.5) / 6)
+    f = np.arange(1024) * FS / 2047.0
+    lf = np.log(np.maximum(f, 1e-3))
+    return np.interp(lf, np.log(centres), band_db) * LN10_20
+
+
+def track_params_from_labels(u: np.ndarray) -> tuple:
+    """Labels in [0, 1]^11 -> (gain_pan [2], eq [1024], compressor [4]) rows: gain/pan dB per
+    channel [-12, 6], six EQ band gains [-12, 12] dB, compressor time constant [1, 100] ms,
+    threshold [-30, -10] dB, ratio [2, 8], knee 3 dB."""
+    v = [lo + (hi - lo) * float(x) for x, (lo, hi) in zip(u, LABEL_RANGES)]
+    gp = np.array(v[0:2]) * LN10_20
+    eq = eq_from_bands(np.array(v[2:8]))
+    comp = np.array([math.exp(-1.0 / (v[8] * 1e-3 * FS)), v[9] * LN10_10, 3.0 * LN10_10, v[10]])
+    return gp, eq, comp
+
+
+def labelled_tiny_consoles(seed: int, count: int, T: int = 2 ** 15):
+    """`count` tiny consoles (4 tracks of gain_pan -> eq -> compressor, mix, master gain_pan,
+    out), console i drawn from its own streams: sources as `make_sources`, per-track labels
+    U[0, 1]^11 mapped by `track_params_from_labels`, master gain U[-12, 6] dB per channel.
+    Returns (workloads, labels [count, 4, 11]); each workload's `params` are the drawn ones and
+    its `target_params` is None."""
+    g = tiny_console(T=8).graph
+    out, labels = [], np.empty((count, 4, N_LABELS))
+    for i in range(count):
+        rng = rng_for(seed, S_PARAM, i)
+        u = rng.uniform(0.0, 1.0, size=(4, N_LABELS))
+        labels[i] = u
+        rows = [track_params_from_labels(x) for x in u]
+        params = default_params(g)
+        params[GAIN_PAN] = np.concatenate(
+            [np.stack([r[0] for r in rows]),
+             rng.uniform(-12.0, 6.0, size=(1, 2)) * LN10_20]).astype(np.float32)
+        params[EQ] = np.stack([r[1] for r in rows]).astype(np.float32)
+        params[COMP] = np.stack([r[2] for r in rows]).astype(np.float32)
+        out.append(Workload(f"labelled_tiny_{i}", g, make_sources(rng_for(seed, S_SOURCE, i), 4,
+                                                                    T), params, None, T, seed))
+    return out, labels
+
+
 def mixing_console(seed=2, T=2 ** 18, n_tracks=64, n_bus=8, attack_release=False) -> Workload:
     """64 tracks with chains of 1-3 from {eq, compressor, gain_pan, imager}, 8 buses of
     mix -> eq -> compressor, master mix -> eq -> compressor -> gain_pan -> out. With
