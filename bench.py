@@ -37,7 +37,8 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32; unpacked issue is half of it)
 EQ_FFT = 4096
 WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
-             "batch": "batched_graphs", "console_ar": "mixing_console"}
+             "batch": "batched_graphs", "console_ar": "mixing_console",
+             "learned_init": "labelled_tiny_consoles"}
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
               "noisegate", "compressor_ar")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
@@ -65,6 +66,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--breakdown-json", default=None, help="write the per-step timing table here")
+    ap.add_argument("--train-consoles", type=int, default=25000,
+                    help="learned_init: labelled tiny consoles rendered for training (4 examples each)")
+    ap.add_argument("--epochs", type=int, default=6, help="learned_init: training epochs")
+    ap.add_argument("--eval-consoles", type=int, default=8, help="learned_init: held-out consoles")
+    ap.add_argument("--gd-steps", type=int, default=200, help="learned_init: plain GD steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (scales PMC counters)")
     return ap.parse_args()
@@ -304,12 +310,65 @@ def setup_batch(args, dev):
             "cpu": (lambda: cpu_baseline_graph(sample))}
 
 
+def run_learned_init(args, pool):
+    """Time to the plain run's final MRSTFT loss: gradient descent from the encoder's prediction
+    against gradient descent from the default parameters, on held-out tiny consoles. The encoder
+    is first trained on consoles rendered by the library (not timed)."""
+    import torch
+
+    from paper_2408_03204_amd import learned_init as LI
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log = (lambda m: print(m, file=sys.stderr, flush=True))
+    t0 = time.perf_counter()
+    dry, mixf, lab = LI.render_dataset(11, args.train_consoles, pool, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"rendered {dry.shape[0]} training examples in {t1 - t0:.1f} s")
+    net, hist = LI.train(dry, mixf, lab, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del dry, mixf
+    rows = LI.gd_compare(net.w, n_consoles=args.eval_consoles, steps=args.gd_steps, log=log)
+    hit = [r for r in rows if r["learned_ms"] is not None]
+    ratios = [r["plain_ms"] / r["learned_ms"] for r in hit]
+    out = {"metric": "time to the plain GD final MRSTFT loss: plain / learned init",
+           "value": round(float(np.median(ratios)), 3) if ratios else None, "unit": "x",
+           "n_gpus": 1, "steps": args.gd_steps, "warmup": 0, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 (encoder inference bf16)",
+           "data": "synthetic",
+           "config": {"workload": "learned_init_tiny_console_4trk", "T": 2 ** 15,
+                      "train_consoles": args.train_consoles,
+                      "train_examples": 4 * args.train_consoles, "epochs": args.epochs,
+                      "eval_consoles": args.eval_consoles, "gd_steps": args.gd_steps,
+                      "optimizer": "adam lr 0.01"},
+           "reached": f"{len(hit)}/{len(rows)}",
+           "plain_ms_median": round(float(np.median([r["plain_ms"] for r in rows])), 3),
+           "learned_ms_median": round(float(np.median([r["learned_ms"] for r in hit])), 3)
+           if hit else None,
+           "learned_steps_median": float(np.median([r["learned_steps_to_target"] for r in hit]))
+           if hit else None,
+           "training_loss_by_epoch": [round(h, 5) for h in hist],
+           "train_seconds": round(t2 - t1, 1), "render_dataset_seconds": round(t1 - t0, 1),
+           "per_console": rows}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "learned_init":
+        from paper_2408_03204_amd import learned_init as LI
+        pool = LI.make_pool(16)  # forked before this process first touches the GPU
+        try:
+            run_learned_init(args, pool)
+        finally:
+            pool.shutdown()
+        return
     import torch
 
     from paper_2408_03204_amd import RenderBuffers

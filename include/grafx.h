@@ -273,6 +273,64 @@ grafx_status grafx_mrstft_backward(int32_t rows, int64_t T, const float* Y,
                                    const float* target, const float* dloss, float* dY, void* ws,
                                    size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Learned parameter initialiser for the gradient-descent mixing application (Sec. 4): a
+ * convolutional encoder predicts the normalised parameters of a track's gain_pan -> eq ->
+ * compressor chain from the log-mel features of the dry track and of the target mix.
+ *
+ * grafx_logmel: features [n_signals][128][F] (device float32, overwritten) of stereo signals
+ *   [n_signals][2][T] (device float32), F = (T - 1024) / 256 + 1: mono (l + r) / 2, frames of
+ *   1024 samples at hop 256 inside [0, T), periodic Hann window, power spectrum, 128 triangular
+ *   filters on the HTK mel scale (130 edges evenly spaced in mel over [0, 22050] Hz, peak 1),
+ *   feature (ln(E + 1e-6) + 5) / 5. E_SHAPE unless 1024 <= T < 2^29.
+ * grafx_encoder_gather: encoder input x [batch][256][F]: rows 0..127 of sample b are
+ *   dry_features[dry[b]], rows 128..255 mix_features[mix[b]] (feature tables [n][128][F]; int32
+ *   device index arrays of length batch, each index below its table's n, not checked); if
+ *   label_table ([n_dry][11]) is not NULL, labels[b] = label_table[dry[b]] as well.
+ * grafx_encoder_sizes: number of float32 weights (one flat buffer: per layer l = 1..6 the
+ *   weights [64][C_in][5] (C_in = 256, then 64) and the bias [64], then the head [11][64] and
+ *   its bias [11]), of activation floats and of backward scratch floats for a batch of
+ *   `batch` inputs of `frames` frames (1 <= batch, frames <= 2^20, else E_SHAPE).
+ * grafx_encoder_forward: six convolutions (kernel 5, stride 2, zero padding 2, bias, ReLU), mean
+ *   over frames, linear head, sigmoid: out [batch][11] in (0, 1) (device, overwritten). acts
+ *   (device, act_floats) receives the activations the backward needs. bf16 != 0 runs the
+ *   convolutions on the matrix cores in bfloat16 with float32 accumulation (inference).
+ * grafx_encoder_backward: mean squared error against labels [batch][11] (device) into *loss
+ *   (device scalar, may be NULL) and its gradient with respect to every weight into dweights
+ *   (device, n_weights floats, overwritten); x, weights, acts and out as left by a float32
+ *   forward call; grads is scratch of grad_floats. Fixed summation orders: bit-reproducible.
+ * grafx_adam: one Adam step over n float32 values in place: m = b1 m + (1 - b1) g,
+ *   v = b2 v + (1 - b2) g^2, p -= lr s (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ *   with s = lr_scale[i] (device, n floats) or 1 when lr_scale is NULL (a zero scale freezes a
+ *   value); step >= 1 counts from 1 (E_ARG otherwise).
+ * grafx_encoder_params: parameter rows of the chain from normalised outputs [batch][11]:
+ *   gain_pan [batch][2] (dB [-12, 6] per channel as natural-log gains), eq [batch][1024] (six
+ *   band gains [-12, 12] dB at 20 * 1000^((b + 0.5) / 6) Hz, linear in log-frequency over bins
+ *   k fs / 2047 Hz, constant beyond the outer bands), compressor [batch][4] (alpha from a time
+ *   constant of [1, 100] ms, threshold [-30, -10] dB, knee 3 dB, ratio [2, 8]).
+ * All pointers are device pointers except the size outputs; every call only enqueues work.
+ */
+grafx_status grafx_logmel(int32_t n_signals, int64_t T, const float* signals, float* features,
+                          hipStream_t stream);
+grafx_status grafx_encoder_gather(int32_t batch, int32_t frames, const float* dry_features,
+                                  const int32_t* dry, const float* mix_features,
+                                  const int32_t* mix, const float* label_table, float* labels,
+                                  float* x, hipStream_t stream);
+grafx_status grafx_encoder_sizes(int32_t batch, int32_t frames, size_t* n_weights,
+                                 size_t* act_floats, size_t* grad_floats);
+grafx_status grafx_encoder_forward(int32_t batch, int32_t frames, const float* x,
+                                   const float* weights, int32_t bf16, float* acts, float* out,
+                                   hipStream_t stream);
+grafx_status grafx_encoder_backward(int32_t batch, int32_t frames, const float* x,
+                                    const float* weights, const float* acts, const float* out,
+                                    const float* labels, float* loss, float* dweights,
+                                    float* grads, hipStream_t stream);
+grafx_status grafx_adam(int64_t n, float* p, const float* g, float* m, float* v,
+                        const float* lr_scale, int32_t step, float lr, float beta1, float beta2,
+                        float eps, hipStream_t stream);
+grafx_status grafx_encoder_params(int32_t batch, const float* out, float* gain_pan, float* eq,
+                                  float* comp, hipStream_t stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* grafx_last_error(void);
 

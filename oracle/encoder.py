@@ -111,6 +111,21 @@ def init_weights(seed: int = 0) -> list:
     return ws
 
 
+def unflatten(flat) -> list:
+    """One flat weight vector [W1, b1, ..., W6, b6, Wh, bh] -> the list of float64 tensors."""
+    v = torch.as_tensor(np.asarray(flat), dtype=F64)
+    out, o, c_in = [], 0, C_IN
+    for _ in range(N_LAYERS):
+        n = C_HID * c_in * KSIZE
+        out += [v[o:o + n].reshape(C_HID, c_in, KSIZE).clone(), v[o + n:o + n + C_HID].clone()]
+        o += n + C_HID
+        c_in = C_HID
+    out += [v[o:o + N_OUT * C_HID].reshape(N_OUT, C_HID).clone(),
+            v[o + N_OUT * C_HID:o + N_OUT * C_HID + N_OUT].clone()]
+    assert o + N_OUT * C_HID + N_OUT == v.numel()
+    return out
+
+
 def conv_layer(x: torch.Tensor, W: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     """x [B, C_in, F] -> ReLU(conv1d(x, W, stride 2, zero padding 2) + b) [B, C_out, ceil(F/2)]."""
     return torch.relu(torch.nn.functional.conv1d(x, W, b, stride=STRIDE, padding=PAD))

@@ -21,7 +21,9 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_schedule_query", "grafx_schedule_export", "grafx_plan_upload",
            "grafx_workspace_bytes", "grafx_render", "grafx_render_backward", "grafx_render_step",
            "grafx_render_backward_step", "grafx_mrstft_workspace_bytes", "grafx_mrstft_loss",
-           "grafx_mrstft_backward", "grafx_last_error")
+           "grafx_mrstft_backward", "grafx_logmel", "grafx_encoder_gather",
+           "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
+           "grafx_encoder_params", "grafx_last_error")
 
 
 class GrafxError(RuntimeError):
@@ -73,6 +75,15 @@ def load() -> ctypes.CDLL:
         "grafx_mrstft_workspace_bytes": (i32, [i32, i64, ctypes.POINTER(sz)]),
         "grafx_mrstft_loss": (i32, [i32, i64, vp, vp, vp, vp, sz, vp]),
         "grafx_mrstft_backward": (i32, [i32, i64, vp, vp, vp, vp, vp, sz, vp]),
+        "grafx_logmel": (i32, [i32, i64, vp, vp, vp]),
+        "grafx_encoder_gather": (i32, [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "grafx_encoder_sizes": (i32, [i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz),
+                                      ctypes.POINTER(sz)]),
+        "grafx_encoder_forward": (i32, [i32, i32, vp, vp, i32, vp, vp, vp]),
+        "grafx_encoder_backward": (i32, [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "grafx_adam": (i32, [i64, vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_float, vp]),
+        "grafx_encoder_params": (i32, [i32, vp, vp, vp, vp, vp]),
         "grafx_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

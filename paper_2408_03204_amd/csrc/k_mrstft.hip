@@ -391,6 +391,61 @@ __global__ __launch_bounds__(kBlock) void ola_kernel(int rows, int64_t T, FrameB
   dY[idx] = acc;
 }
 
+
+// ---- log-mel features of the learned initialiser -----------------------------------------------
+// Frames of 1024 samples at hop 256 inside [0, T), periodic Hann window; one group of 64 threads
+// per frame transforms left + i right, separates the channel spectra and forms the power of their
+// mean (the mono signal); 128 triangular filters on the HTK mel scale (130 edges evenly spaced in
+// mel over [0, fs/2], filter b rising from edge b to b + 1 and falling to b + 2, peak 1) sum the
+// power, and the feature is (ln(E + 1e-6) + 5) / 5.
+constexpr int kMels = 128;
+constexpr float kFs = 44100.f;
+
+__device__ __forceinline__ float mel_edge_hz(int e) {
+  const float top = 2595.f * log10f(1.f + 0.5f * kFs / 700.f);
+  return 700.f * (exp10f(top * (float)e / (float)(kMels + 1) / 2595.f) - 1.f);
+}
+
+__global__ __launch_bounds__(kBlock) void logmel_kernel(int64_t T, int frames, const float* sig,
+                                                        float* feats) {
+  constexpr int N = 1024, G = Grp<N>::G, FPB = kBlock / G, S = lpad(N - 1) + 1;
+  __shared__ float2 lds[FPB * S];
+  const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
+  const int f = blockIdx.x * FPB + grp, row = blockIdx.y;
+  if (f >= frames) return;  // whole one-wave group: no block barrier below
+  float2* s = lds + grp * S;
+  frame_spectrum<N>(sig + (int64_t)row * 2 * T, T, (int64_t)f * (N / 4), s, j);
+  group_sync<G>();
+  constexpr int NB = N / (2 * G);  // bins j + G i, i < NB, per thread; bin N/2 on thread 0
+  float pw[NB + 1];
+#pragma unroll
+  for (int i = 0; i <= NB; ++i) {
+    const int k = i < NB ? j + G * i : N / 2;
+    float2 xl, xr;
+    split(s[lpad(k)], s[lpad((N - k) & (N - 1))], xl, xr);
+    const float re = 0.5f * (xl.x + xr.x), im = 0.5f * (xl.y + xr.y);
+    pw[i] = fmaf(re, re, im * im);
+  }
+  group_sync<G>();
+  float* P = reinterpret_cast<float*>(s);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) P[j + G * i] = pw[i];
+  if (j == 0) P[N / 2] = pw[NB];
+  group_sync<G>();
+  constexpr float kBinHz = kFs / N;
+  for (int b = j; b < kMels; b += G) {
+    const float lo = mel_edge_hz(b), mid = mel_edge_hz(b + 1), hi = mel_edge_hz(b + 2);
+    const int k0 = max(0, (int)ceilf(lo / kBinHz)), k1 = min(N / 2, (int)floorf(hi / kBinHz));
+    float e = 0.f;
+    for (int k = k0; k <= k1; ++k) {
+      const float fk = (float)k * kBinHz;
+      const float wgt = fmaxf(0.f, fminf((fk - lo) / (mid - lo), (hi - fk) / (hi - mid)));
+      e = fmaf(wgt, P[k], e);
+    }
+    feats[((int64_t)row * kMels + b) * frames + f] = (logf(e + 1e-6f) + 5.f) * 0.2f;
+  }
+}
+
 }  // namespace
 
 size_t mrstft_ws_bytes(int rows, int64_t T) { return layout(rows, T).total; }
@@ -442,5 +497,15 @@ hipError_t launch_mrstft_bwd(int rows, int64_t T, const float* Y, const float* t
   ola_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(rows, T, fbs, dY);
   return hipGetLastError();
 }
+
+hipError_t launch_logmel(int n_sig, int64_t T, const float* sig, float* feats, hipStream_t s) {
+  const int frames = logmel_frames(T);
+  if (n_sig <= 0 || frames <= 0) return hipSuccess;
+  constexpr int FPB = kBlock / Grp<1024>::G;
+  logmel_kernel<<<dim3((frames + FPB - 1) / FPB, n_sig), kBlock, 0, s>>>(T, frames, sig, feats);
+  return hipGetLastError();
+}
+
+int logmel_frames(int64_t T) { return T >= 1024 ? (int)((T - 1024) / 256 + 1) : 0; }
 
 }  // namespace grafx

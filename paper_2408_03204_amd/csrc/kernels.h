@@ -95,6 +95,9 @@ hipError_t launch_delay_grad(const float* P, const float* part, int n, int group
 size_t mrstft_ws_bytes(int rows, int64_t T);
 hipError_t launch_mrstft_loss(int rows, int64_t T, const float* Y, const float* tgt, float* loss,
                               void* ws, hipStream_t s);
+// log-mel features [n_sig][128][F] of stereo signals [n_sig][2][T] (frames of 1024 at hop 256)
+int logmel_frames(int64_t T);
+hipError_t launch_logmel(int n_sig, int64_t T, const float* sig, float* feats, hipStream_t s);
 hipError_t launch_mrstft_bwd(int rows, int64_t T, const float* Y, const float* tgt,
                              const float* dloss, float* dY, void* ws, hipStream_t s);
 

@@ -339,18 +339,19 @@ def track_params_from_labels(u: np.ndarray) -> tuple:
     return gp, eq, comp
 
 
-def labelled_tiny_consoles(seed: int, count: int, T: int = 2 ** 15):
+def labelled_tiny_consoles(seed: int, count: int, T: int = 2 ** 15, first: int = 0):
     """`count` tiny consoles (4 tracks of gain_pan -> eq -> compressor, mix, master gain_pan,
     out), console i drawn from its own streams: sources as `make_sources`, per-track labels
     U[0, 1]^11 mapped by `track_params_from_labels`, master gain U[-12, 6] dB per channel.
-    Returns (workloads, labels [count, 4, 11]); each workload's `params` are the drawn ones and
-    its `target_params` is None."""
+    Consoles `first` .. `first + count - 1` of the seed. Returns (workloads, labels
+    [count, 4, 11]); each workload's `params` are the drawn ones, its `target_params` None."""
     g = tiny_console(T=8).graph
     out, labels = [], np.empty((count, 4, N_LABELS))
-    for i in range(count):
+    for n in range(count):
+        i = first + n
         rng = rng_for(seed, S_PARAM, i)
         u = rng.uniform(0.0, 1.0, size=(4, N_LABELS))
-        labels[i] = u
+        labels[n] = u
         rows = [track_params_from_labels(x) for x in u]
         params = default_params(g)
         params[GAIN_PAN] = np.concatenate(
@@ -361,6 +362,21 @@ def labelled_tiny_consoles(seed: int, count: int, T: int = 2 ** 15):
         out.append(Workload(f"labelled_tiny_{i}", g, make_sources(rng_for(seed, S_SOURCE, i), 4,
                                                                     T), params, None, T, seed))
     return out, labels
+
+
+def encoder_weights(seed: int = 0) -> np.ndarray:
+    """Initial weights of the learned initialiser's encoder as one flat float32 vector, layout
+    [W1 (64 x 256 x 5), b1 (64), W2 (64 x 64 x 5), b2, ..., W6, b6, Wh (11 x 64), bh (11)]:
+    He-uniform weights (bound sqrt(6 / fan_in)), Glorot-uniform head, zero biases."""
+    rng = rng_for(seed, S_PARAM, 99)
+    parts, c_in = [], 256
+    for _ in range(6):
+        bound = math.sqrt(6.0 / (c_in * 5))
+        parts += [rng.uniform(-bound, bound, 64 * c_in * 5), np.zeros(64)]
+        c_in = 64
+    bound = math.sqrt(6.0 / (64 + 11))
+    parts += [rng.uniform(-bound, bound, 11 * 64), np.zeros(11)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 def mixing_console(seed=2, T=2 ** 18, n_tracks=64, n_bus=8, attack_release=False) -> Workload:
