@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=6, help="learned_init: training epochs")
     ap.add_argument("--eval-consoles", type=int, default=8, help="learned_init: held-out consoles")
     ap.add_argument("--gd-steps", type=int, default=200, help="learned_init: plain GD steps")
+    ap.add_argument("--workers", type=int, default=16,
+                    help="learned_init: processes drawing the training consoles (0: this one)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (scales PMC counters)")
     return ap.parse_args()
@@ -330,6 +332,33 @@ def run_learned_init(args, pool):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     del dry, mixf
+    # encoder inference at the training batch: bf16 MFMA convolutions against float32
+    from paper_2408_03204_amd import encoder as ENC
+    Fr = ENC.n_frames(2 ** 15)
+    xb = torch.randn((256, 2 * ENC.N_MELS, Fr), device=dev)
+    inf = ENC.Encoder(net.w, 256, Fr)
+    conv_flops, f_in, c_in = 0, Fr, 2 * ENC.N_MELS
+    for _ in range(6):
+        f_out = (f_in + 1) // 2
+        conv_flops += 2 * 256 * 64 * f_out * c_in * 5
+        f_in, c_in = f_out, 64
+    inf_ms = {}
+    for bf in (True, False):
+        for _ in range(3):
+            inf.forward(xb, bf16=bf)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            inf.forward(xb, bf16=bf)
+        e1.record()
+        torch.cuda.synchronize()
+        inf_ms["bf16" if bf else "f32"] = e0.elapsed_time(e1) / 20
+    tf = conv_flops / (inf_ms["bf16"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                "frac": round(tf / 2500.0, 5), "traffic": None,
+                "kernel": "conv_fwd_mfma (bf16, whole encoder forward, batch 256)",
+                "flops_per_launch": conv_flops, "ms": round(inf_ms["bf16"], 4),
+                "f32_forward_ms": round(inf_ms["f32"], 4)}
     rows = LI.gd_compare(net.w, n_consoles=args.eval_consoles, steps=args.gd_steps, log=log)
     hit = [r for r in rows if r["learned_ms"] is not None]
     ratios = [r["plain_ms"] / r["learned_ms"] for r in hit]
@@ -349,6 +378,7 @@ def run_learned_init(args, pool):
            if hit else None,
            "learned_steps_median": float(np.median([r["learned_steps_to_target"] for r in hit]))
            if hit else None,
+           "roofline": roofline,
            "training_loss_by_epoch": [round(h, 5) for h in hist],
            "train_seconds": round(t2 - t1, 1), "render_dataset_seconds": round(t1 - t0, 1),
            "per_console": rows}
@@ -363,7 +393,10 @@ def main():
         sys.exit(2)
     if args.workload == "learned_init":
         from paper_2408_03204_amd import learned_init as LI
-        pool = LI.make_pool(16)  # forked before this process first touches the GPU
+        if args.workers <= 0:
+            run_learned_init(args, LI.InlinePool())
+            return
+        pool = LI.make_pool(args.workers)  # forked before this process first touches the GPU
         try:
             run_learned_init(args, pool)
         finally:

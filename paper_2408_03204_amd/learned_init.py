@@ -45,6 +45,14 @@ def _idle(seconds):
     return os.getpid()
 
 
+class InlinePool:
+    """Draws the consoles in this process (no workers)."""
+
+    @staticmethod
+    def map(fn, jobs):
+        return map(fn, jobs)
+
+
 def make_pool(workers: int = 16):
     """Worker processes for drawing the consoles' sources and parameters (numpy only). Create it
     before the process first uses the GPU: the workers are forked copies of this process, and

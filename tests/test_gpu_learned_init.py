@@ -13,15 +13,9 @@ from paper_2408_03204_amd import learned_init as LI
 pytestmark = pytest.mark.gpu
 
 
-class InlinePool:
-    @staticmethod
-    def map(fn, jobs):
-        return map(fn, jobs)
-
-
 def test_pipeline_small():
     dev = torch.device("cuda")
-    dry, mixf, lab = LI.render_dataset(21, 96, InlinePool(), chunk=32, device=dev)
+    dry, mixf, lab = LI.render_dataset(21, 96, LI.InlinePool(), chunk=32, device=dev)
     torch.cuda.synchronize()
     assert dry.shape[0] == 4 * 96 and mixf.shape[0] == 96 and lab.shape == (4 * 96, 11)
     assert torch.isfinite(dry).all() and torch.isfinite(mixf).all()
