@@ -311,39 +311,87 @@ __device__ __forceinline__ short to_bf16(float f) {  // round to nearest even
   return (short)(u >> 16);
 }
 
-// One block = 4 waves = the 64 output channels (16 per wave) of 16 columns n = b * Fout + t.
-// v_mfma_f32_16x16x16_bf16 operands, lane l = i + 16 q: A row i, K entries 4q..4q+3; B column i,
-// K entries 4q..4q+3; D column i, rows 4q..4q+3.
+// A block computes all 64 output channels over 64 columns n = b * Fout + t. The K dimension
+// (in channel x tap, K = Cin * 5) advances in chunks of 128: the block stages the weight chunk
+// A[64][128] and the gathered input chunk Bt[64 columns][128] in LDS as bfloat16 (nearest even),
+// then wave w multiplies rows 16 w .. 16 w + 15 against the four 16-column tiles, eight K steps
+// of v_mfma_f32_16x16x16_bf16 each. Large chunks amortise the global-load latency of staging,
+// which bounds the kernel at these sizes. Operands per lane l = i + 16 q: A row i, K entries 4q..4q+3;
+// B column i, K entries 4q..4q+3; D column i, rows 4q..4q+3. Rows of the LDS tiles are padded
+// by 4 bf16 so the 16 lanes of a fragment read distinct banks.
+constexpr int kMN = 64, kKC = 128, kLd = kKC + 4;
+constexpr int kStage = kKC / 4;  // K entries staged per thread and chunk
+
 __global__ __launch_bounds__(kBlock) void conv_fwd_mfma_kernel(int B, int Cin, int Fin, int Fout,
                                                                const float* x, const float* W,
                                                                const float* bias, float* y) {
+  __shared__ short As[kMN * kLd], Bs[kMN * kLd];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 15, q = lane >> 4;
-  const int co0 = wave * 16;
   const int N = B * Fout, K = Cin * kKs;
-  const int n = blockIdx.x * 16 + i;
-  const bool live = n < N;
-  const int b = live ? n / Fout : 0, t = live ? n % Fout : 0;
-  const float* xb = x + (int64_t)b * Cin * Fin;
-  const float* wr = W + (int64_t)(co0 + i) * K;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a, bv;
+  const int n0 = blockIdx.x * kMN;
+  // staging roles. A: thread r covers channel r / 4 and the kStage consecutive K entries
+  // kStage (r % 4) .. (contiguous weights). B: thread r covers column r % 64 and the K entries
+  // kStage (r / 64) .., so a wave reads 64 neighbouring columns (frames two samples apart) at
+  // every K entry.
+  const int srow = threadIdx.x >> 2, sk = (threadIdx.x & 3) * kStage;
+  const int bn = threadIdx.x & 63, bk = (threadIdx.x >> 6) * kStage;
+  const int n_s = n0 + bn;
+  const bool live_s = n_s < N;
+  const int b_s = live_s ? n_s / Fout : 0, t_s = live_s ? n_s % Fout : 0;
+  // one wave-uniform descriptor per tensor (per-lane descriptors would make the compiler loop
+  // over the lanes for every load); the host keeps both tensors below 2^29 elements
+  const auto rx = row_rsrc(x, (int64_t)B * Cin * Fin);
+  const auto rw = row_rsrc(W, (int64_t)kCh * K);
+  const int xbase = b_s * Cin * Fin, wbase = srow * K;
+  f32x4 acc[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int kk = k0 + 4 * q + e;
-      a[e] = to_bf16(wr[kk]);
-      const int ci = kk / kKs, k = kk % kKs;
-      const int src = 2 * t + k - 2;
-      bv[e] = to_bf16(live && src >= 0 && src < Fin ? xb[(int64_t)ci * Fin + src] : 0.f);
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+    __syncthreads();  // the previous chunk's fragments have been read
+    float va[kStage], vb[kStage];  // every load of the chunk in flight before any is used
+#pragma unroll
+    for (int e = 0; e < kStage; ++e) {  // branch-free: out-of-range offsets read 0 in hardware
+      const int ka = k0 + sk + e;
+      va[e] = bload(rw, ka < K ? wbase + ka : -1);
+      const int kb = k0 + bk + e;
+      const int ci = kb / kKs, tap = kb % kKs;
+      const int src = 2 * t_s + tap - 2;
+      const bool ok = live_s && kb < K && src >= 0 && src < Fin;
+      vb[e] = bload(rx, ok ? xbase + ci * Fin + src : -1);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < kStage; ++e) {
+      As[srow * kLd + sk + e] = to_bf16(va[e]);
+      Bs[bn * kLd + bk + e] = to_bf16(vb[e]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKC; ks += 16) {
+      bf16x4 a;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = As[(wave * 16 + i) * kLd + ks + 4 * q + e];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bf16x4 bv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[e] = Bs[(j * 16 + i) * kLd + ks + 4 * q + e];
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[j], 0, 0, 0);
+      }
+    }
   }
-  if (live) {
+  float bsum[4];  // this lane's four channels, loaded once before the stores
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bsum[e] = bias[wave * 16 + 4 * q + e];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + j * 16 + i;
+    if (n >= N) continue;
+    const int b = n / Fout, t = n % Fout;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int co = co0 + 4 * q + e;
-      y[((int64_t)b * kCh + co) * Fout + t] = fmaxf(acc[e] + bias[co], 0.f);
+      const int co = wave * 16 + 4 * q + e;
+      y[((int64_t)b * kCh + co) * Fout + t] = fmaxf(acc[j][e] + bsum[e], 0.f);
     }
   }
 }
@@ -414,6 +462,8 @@ grafx_status grafx_encoder_forward(int32_t batch, int32_t frames, const float* x
   grafx_status st = check_dims(batch, frames);
   if (st != GRAFX_OK) return st;
   if (!x || !weights || !acts || !out) return fail(GRAFX_E_ARG, "NULL argument");
+  if (bf16 && (int64_t)batch * kCin * frames >= ((int64_t)1 << 29))
+    return fail(GRAFX_E_SHAPE, "bf16 forward: batch x 256 x frames must be below 2^29");
   const EncLayout L = enc_layout(batch, frames);
   const float* in = x;
   hipError_t e = hipSuccess;
@@ -422,7 +472,7 @@ grafx_status grafx_encoder_forward(int32_t batch, int32_t frames, const float* x
     const int Cin = cin_of(l);
     if (bf16) {
       const int cols = batch * L.F[l];
-      conv_fwd_mfma_kernel<<<(cols + 15) / 16, kBlock, 0, stream>>>(
+      conv_fwd_mfma_kernel<<<(cols + kMN - 1) / kMN, kBlock, 0, stream>>>(
           batch, Cin, L.F[l - 1], L.F[l], in, weights + L.w[l], weights + L.b[l], y);
     } else {
       const int64_t n = (int64_t)batch * kCh * L.F[l];
