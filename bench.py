@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--gd-steps", type=int, default=200, help="learned_init: plain GD steps")
     ap.add_argument("--workers", type=int, default=16,
                     help="learned_init: processes drawing the training consoles (0: this one)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the schedule's tuning settings by timing them first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (scales PMC counters)")
     return ap.parse_args()
@@ -204,6 +206,17 @@ def cpu_baseline_graph(w, min_seconds: float = 10.0, max_reps: int = 6):
                       f"float64, {reps} step(s) in {dt:.1f} s"}
 
 
+def _tune(args, sched, S, P) -> dict:
+    """Optionally autotune the schedule; returns the settings in force for the config record."""
+    from paper_2408_03204_amd import Schedule
+    if args.autotune:
+        from paper_2408_03204_amd.autotune import tune_pointwise
+        times = tune_pointwise(sched, S, P)
+        print(f"autotune (pointwise unroll -> ms): {times}", file=sys.stderr)
+    return {"pointwise_unroll": sched.get_tuning(Schedule.TUNE_POINTWISE_UNROLL),
+            "autotuned": bool(args.autotune)}
+
+
 def setup_console(args, dev):
     """The mixing-console gradient step: render, MRSTFT loss against a target rendered with
     hidden parameters, loss adjoint, render adjoint (GradStep; also issued through autograd)."""
@@ -232,6 +245,7 @@ def setup_console(args, dev):
         L = mrstft_loss(Y, target)
         return torch.autograd.grad(L, plist)
 
+    tuning = _tune(args, sched, S, {t: p.detach() for t, p in P.items()})
     gs = GradStep(sched, S, {t: p.detach() for t, p in P.items()}, target)
     wanted = {args.mode} if args.single_mode else {"graph", "eager", "autograd"}
     if "graph" in wanted:
@@ -241,7 +255,7 @@ def setup_console(args, dev):
     config = {"workload": w.name, "nodes": g.num_nodes, "processed_nodes": w.processed_nodes,
               "edges": g.num_edges, "T": w.T, "schedule": args.method,
               "steps_in_schedule": sched.num_steps, "loss": "mrstft 512/1024/2048",
-              "step": "render+loss+adjoint"}
+              "step": "render+loss+adjoint", **tuning}
     return {"sched": sched, "S": S, "P": {t: p.detach() for t, p in P.items()}, "T": w.T,
             "rb": None, "node_samples": w.processed_nodes * w.T, "steps": steps,
             "config": config, "key": args.workload,
@@ -281,6 +295,7 @@ def setup_batch(args, dev):
     dY = torch.as_tensor(dY_h, device=dev)
     rb = RenderBuffers(sched, T, dev, with_backward=True)
     dP = {t: torch.empty_like(p) for t, p in P.items()}
+    tuning = _tune(args, sched, S, P)
 
     def eager():
         rb.forward(S, P)
@@ -306,7 +321,7 @@ def setup_batch(args, dev):
               "nodes": int(counts.sum()), "processed_nodes": int(counts.sum() - counts[0]),
               "edges": int(m["edges"].shape[1]), "T": "per graph U{2^16, 2^17, 2^18}",
               "row_stride": T, "schedule": args.method, "steps_in_schedule": sched.num_steps,
-              "step": "render+adjoint (seeded output adjoint)"}
+              "step": "render+adjoint (seeded output adjoint)", **tuning}
     return {"sched": sched, "S": S, "P": P, "T": T, "rb": rb, "dY": dY,
             "node_samples": node_samples, "steps": steps, "config": config, "key": "batch",
             "cpu": (lambda: cpu_baseline_graph(sample))}

@@ -253,6 +253,22 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* sched, const voi
                                         size_t ws_bytes, int32_t step, hipStream_t stream);
 
 /*
+ * Tuning settings of a schedule (chosen by a caller-side autotuner from measured step times).
+ * They change which threads and blocks share the work, hence the grouping of the per-block
+ * parameter-gradient partial sums (results stay within the parity tolerances; each setting is
+ * deterministic), never the per-sample arithmetic or the workspace size.
+ *   GRAFX_TUNE_POINTWISE_UNROLL: 1024-sample parts per block of the pointwise kernels (mix, out,
+ *   gain_pan, imager, tanh): 1 (default), 2 or 4.
+ * grafx_schedule_set_tuning: E_ARG for a NULL schedule, an unknown knob or a value not listed.
+ * A setting applies to every later call with the schedule; calls that overlap with a change on
+ * another thread are not synchronised with it.
+ */
+enum { GRAFX_TUNE_POINTWISE_UNROLL = 0 };
+grafx_status grafx_schedule_set_tuning(grafx_schedule_t* sched, int32_t knob, int32_t value);
+grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* sched, int32_t knob,
+                                       int32_t* value);
+
+/*
  * Multi-resolution STFT loss between two sets of stereo signals (the loss of the paper's
  * gradient-descent mixing application, Sec. 4): resolutions 512, 1024 and 2048, hop r/4,
  * periodic Hann window, frames that fit inside [0, T), magnitudes sqrt(|X|^2 + 1e-8);

@@ -23,7 +23,8 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_render_backward_step", "grafx_mrstft_workspace_bytes", "grafx_mrstft_loss",
            "grafx_mrstft_backward", "grafx_logmel", "grafx_encoder_gather",
            "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
-           "grafx_encoder_params", "grafx_last_error")
+           "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
+           "grafx_last_error")
 
 
 class GrafxError(RuntimeError):
@@ -84,6 +85,8 @@ def load() -> ctypes.CDLL:
         "grafx_adam": (i32, [i64, vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
                              ctypes.c_float, ctypes.c_float, vp]),
         "grafx_encoder_params": (i32, [i32, vp, vp, vp, vp, vp]),
+        "grafx_schedule_set_tuning": (i32, [vp, i32, i32]),
+        "grafx_schedule_get_tuning": (i32, [vp, i32, c_i32p]),
         "grafx_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -101,6 +101,17 @@ class Schedule:
             self._plans[device] = t
         return self._plans[device]
 
+    TUNE_POINTWISE_UNROLL = 0
+
+    def set_tuning(self, knob: int, value: int) -> None:
+        """A tuning setting of the schedule (see include/grafx.h, grafx_schedule_set_tuning)."""
+        check(load().grafx_schedule_set_tuning(self._h, knob, value))
+
+    def get_tuning(self, knob: int) -> int:
+        v = ctypes.c_int32()
+        check(load().grafx_schedule_get_tuning(self._h, knob, ctypes.byref(v)))
+        return int(v.value)
+
     def workspace_bytes(self, T: int, with_backward: bool) -> int:
         n = ctypes.c_size_t()
         check(load().grafx_workspace_bytes(self._h, T, int(with_backward), ctypes.byref(n)))

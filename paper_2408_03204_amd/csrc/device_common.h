@@ -26,6 +26,7 @@ struct GraphView {
   int32_t K;                 // number of input nodes (= sigma positions [0, K))
   int32_t out_begin;         // sigma position of the first output node
   int32_t vec4;              // T and every node length are multiples of 4 (16-byte vectors)
+  int32_t pw_unroll;         // pointwise kernels: 1024-sample parts per block (1, 2 or 4)
 };
 
 // Length of the signal of the node at sigma position v (its row holds valid samples [0, len)).

@@ -117,6 +117,7 @@ GraphView make_view(const grafx_schedule_t* h, const void* dev_plan, int64_t T, 
   g.K = h->K;
   g.out_begin = h->step_ptr[h->N];
   g.vec4 = (T % 4 == 0) && h->len4;
+  g.pw_unroll = h->pw_unroll;
   return g;
 }
 
@@ -335,7 +336,7 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = enqueue_bwd_step(h, g, P, dU, ws, L, n, stream);
   if (e == hipSuccess && dS && h->K > 0)  // adjoint of the input step: sum over output edges
     e = launch_pointwise_bwd(GRAFX_IN, g, dS, nullptr, 0, h->K, nullptr, stream);
-  const int tiles = pointwise_tiles(T), chunks = comp_chunks(T);
+  const int tiles = pointwise_tiles(T, h->pw_unroll), chunks = comp_chunks(T);
   if (e == hipSuccess && dpar(GRAFX_GAIN_PAN))
     e = launch_reduce_partials(at<double>(ws, L.part_gp), h->type_count[GRAFX_GAIN_PAN], tiles, 2,
                                dpar(GRAFX_GAIN_PAN), stream);
@@ -395,6 +396,24 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* d
   if (h->step_type[step] == GRAFX_COMPRESSOR_AR) e = reset_ar(h, ws, L, true, T, stream);
   if (e == hipSuccess) e = enqueue_bwd_step(h, g, P, dU, ws, L, step, stream);
   return hip_status(e, "render_backward_step launch");
+}
+
+grafx_status grafx_schedule_set_tuning(grafx_schedule_t* h, int32_t knob, int32_t value) {
+  clear_error();
+  if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
+  if (knob != GRAFX_TUNE_POINTWISE_UNROLL) return fail(GRAFX_E_ARG, "unknown tuning knob");
+  if (value != 1 && value != 2 && value != 4)
+    return fail(GRAFX_E_ARG, "pointwise unroll must be 1, 2 or 4");
+  h->pw_unroll = value;
+  return GRAFX_OK;
+}
+
+grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* h, int32_t knob, int32_t* value) {
+  clear_error();
+  if (!h || !value) return fail(GRAFX_E_ARG, "NULL argument");
+  if (knob != GRAFX_TUNE_POINTWISE_UNROLL) return fail(GRAFX_E_ARG, "unknown tuning knob");
+  *value = h->pw_unroll;
+  return GRAFX_OK;
 }
 
 grafx_status grafx_mrstft_workspace_bytes(int32_t rows, int64_t T, size_t* bytes) {

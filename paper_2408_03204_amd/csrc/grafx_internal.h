@@ -29,7 +29,8 @@ struct PlanLayout {
 
 }  // namespace grafx
 
-// The schedule handle (host memory only; immutable after creation).
+// The schedule handle (host memory only). Its graph and plan are immutable after creation; only
+// the tuning settings (grafx_schedule_set_tuning) change.
 struct grafx_schedule_t {
   int32_t V = 0, E = 0, N = 0, K = 0, n_out = 0;
   int32_t type_count[grafx::kNumTypes] = {0};
@@ -45,6 +46,7 @@ struct grafx_schedule_t {
   std::vector<int32_t> node_len;   // [V] per-node signal length (sigma order); empty = all T
   int32_t max_len = 0;             // largest node length (0 when uniform)
   bool len4 = true;                // every node length is a multiple of 4
+  int32_t pw_unroll = 1;           // tuning: pointwise 1024-sample parts per block
   grafx::PlanLayout layout{};
   std::vector<int32_t> plan;       // packed host image of the device plan
 };

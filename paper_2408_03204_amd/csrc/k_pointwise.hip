@@ -2,8 +2,9 @@
 // Gather, Aggregate, Process, Store of one iteration), and the matching adjoint step.
 //
 // Types: mix / out (identity, Eq. 1b only), gain_pan (Eq. 2), imager (Eq. 3), tanh distortion.
-// One block of 256 threads covers 1024 samples of one node (both channels); blockIdx.y picks the
-// node inside the step. Thread j covers samples 4j..4j+3 of the tile: with T and every node
+// One block of 256 threads covers 1024 x UN samples of one node (both channels), UN = 1, 2 or 4
+// being a tuning setting of the schedule; blockIdx.y picks the node inside the step. Thread j
+// covers samples 4j..4j+3 of each 1024-sample part of the tile: with T and every node
 // length multiples of 4, rows are 16-byte aligned and it moves one float4 per channel and input;
 // otherwise it moves the 4 samples one by one. Inputs are read through raw buffer resources sized to their node's
 // length, so samples past an input's length read as zero without a branch, and are summed in
@@ -64,50 +65,69 @@ __device__ __forceinline__ void bload_n(__amdgpu_buffer_rsrc_t r, int idx, float
   }
 }
 
-template <int TYPE, bool V4>
+template <int TYPE, bool V4, int UN>
 __global__ __launch_bounds__(kBlock) void pointwise_fwd_kernel(GraphView g, float* U,
                                                                const float* P, int node_begin) {
   const int node = node_begin + blockIdx.y;
   const int64_t T = g.T, Tn = node_len(g, node);
+  const int64_t base = (int64_t)blockIdx.x * (kTile * UN);
+  if (base >= Tn) return;  // tile past the node's length (uniform over the block)
   const Gains k = load_gains<TYPE>(P, g.param_row[node]);
   const int e0 = g.in_ptr[node], e1 = g.in_ptr[node + 1];
   float* y = U + (int64_t)node * 2 * T;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  if constexpr (V4) {
-    const int t = (int)(base + 4 * threadIdx.x);
-    if (t >= Tn) return;
-    float4 l = make_float4(0.f, 0.f, 0.f, 0.f), r = l;
-    for (int e = e0; e < e1; ++e) {
-      const int src = g.in_src[e];
-      const float* row = out_row(g, src);
-      const int64_t Ls = node_len(g, src);
-      const float4 a = bload4(row_rsrc(row, Ls), t);
-      const float4 b = bload4(row_rsrc(row + T, Ls), t);
-      l.x += a.x; l.y += a.y; l.z += a.z; l.w += a.w;
-      r.x += b.x; r.y += b.y; r.z += b.z; r.w += b.w;
-    }
-    fwd_op<TYPE>(l.x, r.x, k);
-    fwd_op<TYPE>(l.y, r.y, k);
-    fwd_op<TYPE>(l.z, r.z, k);
-    fwd_op<TYPE>(l.w, r.w, k);
-    *reinterpret_cast<float4*>(y + t) = l;
-    *reinterpret_cast<float4*>(y + T + t) = r;
-  } else {
+  // thread j covers samples base + kTile u + 4 j .. + 3 for u < UN; every load of an input row
+  // is issued before any is summed (samples past an input's length read as zero)
+  float l[UN][4], r[UN][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = (int)(base + 4 * threadIdx.x + q);
-      if (t >= Tn) break;
-      float l = 0.f, r = 0.f;
-      for (int e = e0; e < e1; ++e) {
-        const int src = g.in_src[e];
-        const float* row = out_row(g, src);
-        const int64_t Ls = node_len(g, src);
-        l += bload(row_rsrc(row, Ls), t);
-        r += bload(row_rsrc(row + T, Ls), t);
+  for (int u = 0; u < UN; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) l[u][q] = r[u][q] = 0.f;
+  for (int e = e0; e < e1; ++e) {
+    const int src = g.in_src[e];
+    const float* row = out_row(g, src);
+    const int64_t Ls = node_len(g, src);
+    const auto rl = row_rsrc(row, Ls), rr = row_rsrc(row + T, Ls);
+    float a[UN][4], b[UN][4];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int t = (int)(base + kTile * u + 4 * threadIdx.x);
+      if constexpr (V4) {
+        const float4 x = bload4(rl, t), z = bload4(rr, t);
+        a[u][0] = x.x; a[u][1] = x.y; a[u][2] = x.z; a[u][3] = x.w;
+        b[u][0] = z.x; b[u][1] = z.y; b[u][2] = z.z; b[u][3] = z.w;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[u][q] = bload(rl, t + q);
+          b[u][q] = bload(rr, t + q);
+        }
       }
-      fwd_op<TYPE>(l, r, k);
-      y[t] = l;
-      y[T + t] = r;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        l[u][q] += a[u][q];
+        r[u][q] += b[u][q];
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < UN; ++u) {
+    const int64_t t = base + kTile * u + 4 * threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fwd_op<TYPE>(l[u][q], r[u][q], k);
+    if constexpr (V4) {
+      if (t < Tn) {
+        *reinterpret_cast<float4*>(y + t) = make_float4(l[u][0], l[u][1], l[u][2], l[u][3]);
+        *reinterpret_cast<float4*>(y + T + t) = make_float4(r[u][0], r[u][1], r[u][2], r[u][3]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (t + q < Tn) {
+          y[t + q] = l[u][q];
+          y[T + t + q] = r[u][q];
+        }
     }
   }
 }
@@ -159,7 +179,7 @@ __device__ __forceinline__ void adj_op(float yl, float yr, float ul_in, float ur
   }
 }
 
-template <int TYPE, bool V4>
+template <int TYPE, bool V4, int UN>
 __global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, float* dst,
                                                                const float* P, int node_begin,
                                                                double* part, int tiles) {
@@ -173,54 +193,58 @@ __global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, floa
   const float* yrow = g.U + (int64_t)node * 2 * T;  // used by gain_pan / imager only
   float* d = dst + (int64_t)node * 2 * T;
   float acc[NP > 0 ? NP : 1] = {0.f};
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t base = (int64_t)blockIdx.x * (kTile * UN);
   constexpr int NV = V4 ? 4 : 1;
-  // Thread j covers samples base + 4j .. base + 4j + 3 in both paths, so the gradient partials
-  // are accumulated in the same order whichever path a launch takes.
-  const int64_t t_first = base + 4 * threadIdx.x;
+  // Thread j covers samples base + kTile u + 4j .. + 3 (u < UN) in both paths, in the same order,
+  // so the gradient partials are accumulated identically whichever path a launch takes. Blocks
+  // past the node's length still write their (zero) partials.
 #pragma unroll
-  for (int q = 0; q < (V4 ? 1 : 4); ++q) {
-    const int64_t t = t_first + q;
-    if (t >= Tn) break;
-    float gl[NV], gr[NV], yl[NV], yr[NV], ul[NV], ur[NV];
+  for (int u = 0; u < UN; ++u) {
+    const int64_t t_first = base + kTile * u + 4 * threadIdx.x;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) gl[v] = gr[v] = yl[v] = yr[v] = ul[v] = ur[v] = 0.f;
-    for (int e = o0; e < o1; ++e) {
-      const int dnode = g.out_dst[e];
-      const float* row = adj_row(g, dnode);
-      const int64_t Ld = node_len(g, dnode);
-      float a[NV], b[NV];
-      bload_n<V4>(row_rsrc(row, Ld), (int)t, a);
-      bload_n<V4>(row_rsrc(row + T, Ld), (int)t, b);
+    for (int q = 0; q < (V4 ? 1 : 4); ++q) {
+      const int64_t t = t_first + q;
+      if (t >= Tn) break;
+      float gl[NV], gr[NV], yl[NV], yr[NV], ul[NV], ur[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        gl[v] += a[v];
-        gr[v] += b[v];
-      }
-    }
-    if constexpr (TYPE == GRAFX_GAIN_PAN || TYPE == GRAFX_IMAGER) {
-      load_n<V4>(yrow + t, yl);
-      load_n<V4>(yrow + T + t, yr);
-    }
-    if constexpr (TYPE == GRAFX_TANH) {
-      for (int e = i0; e < i1; ++e) {
-        const int src = g.in_src[e];
-        const float* row = out_row(g, src);
-        const int64_t Ls = node_len(g, src);
+      for (int v = 0; v < NV; ++v) gl[v] = gr[v] = yl[v] = yr[v] = ul[v] = ur[v] = 0.f;
+      for (int e = o0; e < o1; ++e) {
+        const int dnode = g.out_dst[e];
+        const float* row = adj_row(g, dnode);
+        const int64_t Ld = node_len(g, dnode);
         float a[NV], b[NV];
-        bload_n<V4>(row_rsrc(row, Ls), (int)t, a);
-        bload_n<V4>(row_rsrc(row + T, Ls), (int)t, b);
+        bload_n<V4>(row_rsrc(row, Ld), (int)t, a);
+        bload_n<V4>(row_rsrc(row + T, Ld), (int)t, b);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          ul[v] += a[v];
-          ur[v] += b[v];
+          gl[v] += a[v];
+          gr[v] += b[v];
         }
       }
-    }
+      if constexpr (TYPE == GRAFX_GAIN_PAN || TYPE == GRAFX_IMAGER) {
+        load_n<V4>(yrow + t, yl);
+        load_n<V4>(yrow + T + t, yr);
+      }
+      if constexpr (TYPE == GRAFX_TANH) {
+        for (int e = i0; e < i1; ++e) {
+          const int src = g.in_src[e];
+          const float* row = out_row(g, src);
+          const int64_t Ls = node_len(g, src);
+          float a[NV], b[NV];
+          bload_n<V4>(row_rsrc(row, Ls), (int)t, a);
+          bload_n<V4>(row_rsrc(row + T, Ls), (int)t, b);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) adj_op<TYPE>(yl[v], yr[v], ul[v], ur[v], gl[v], gr[v], k, acc);
-    store_n<V4>(d + t, gl);
-    store_n<V4>(d + T + t, gr);
+          for (int v = 0; v < NV; ++v) {
+            ul[v] += a[v];
+            ur[v] += b[v];
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) adj_op<TYPE>(yl[v], yr[v], ul[v], ur[v], gl[v], gr[v], k, acc);
+      store_n<V4>(d + t, gl);
+      store_n<V4>(d + T + t, gr);
+    }
   }
   (void)i0;
   (void)i1;
@@ -247,32 +271,57 @@ __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const double* p
   }
 }
 
+template <int TYPE, int UN>
+void fwd_un(const GraphView& g, float* U, const float* P, int node_begin, int n_nodes,
+            hipStream_t s) {
+  dim3 grid((unsigned)((g.T + kTile * UN - 1) / (kTile * UN)), (unsigned)n_nodes);
+  if (g.vec4)
+    pointwise_fwd_kernel<TYPE, true, UN><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
+  else
+    pointwise_fwd_kernel<TYPE, false, UN><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
+}
+
 template <int TYPE>
 hipError_t launch_fwd_t(const GraphView& g, float* U, const float* P, int node_begin,
                         int n_nodes, hipStream_t s) {
-  dim3 grid((unsigned)((g.T + kTile - 1) / kTile), (unsigned)n_nodes);
-  if (g.vec4)
-    pointwise_fwd_kernel<TYPE, true><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
-  else
-    pointwise_fwd_kernel<TYPE, false><<<grid, kBlock, 0, s>>>(g, U, P, node_begin);
+  switch (g.pw_unroll) {
+    case 2: fwd_un<TYPE, 2>(g, U, P, node_begin, n_nodes, s); break;
+    case 4: fwd_un<TYPE, 4>(g, U, P, node_begin, n_nodes, s); break;
+    default: fwd_un<TYPE, 1>(g, U, P, node_begin, n_nodes, s); break;
+  }
   return hipGetLastError();
+}
+
+template <int TYPE, int UN>
+void bwd_un(const GraphView& g, float* dst, const float* P, int node_begin, int n_nodes,
+            double* part, hipStream_t s) {
+  const int tiles = (int)((g.T + kTile * UN - 1) / (kTile * UN));
+  dim3 grid((unsigned)tiles, (unsigned)n_nodes);
+  if (g.vec4)
+    pointwise_bwd_kernel<TYPE, true, UN><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part,
+                                                                 tiles);
+  else
+    pointwise_bwd_kernel<TYPE, false, UN><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part,
+                                                                  tiles);
 }
 
 template <int TYPE>
 hipError_t launch_bwd_t(const GraphView& g, float* dst, const float* P, int node_begin,
                         int n_nodes, double* part, hipStream_t s) {
-  const int tiles = (int)((g.T + kTile - 1) / kTile);
-  dim3 grid((unsigned)tiles, (unsigned)n_nodes);
-  if (g.vec4)
-    pointwise_bwd_kernel<TYPE, true><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part, tiles);
-  else
-    pointwise_bwd_kernel<TYPE, false><<<grid, kBlock, 0, s>>>(g, dst, P, node_begin, part, tiles);
+  switch (g.pw_unroll) {
+    case 2: bwd_un<TYPE, 2>(g, dst, P, node_begin, n_nodes, part, s); break;
+    case 4: bwd_un<TYPE, 4>(g, dst, P, node_begin, n_nodes, part, s); break;
+    default: bwd_un<TYPE, 1>(g, dst, P, node_begin, n_nodes, part, s); break;
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-int pointwise_tiles(int64_t T) { return (int)((T + kTile - 1) / kTile); }
+int pointwise_tiles(int64_t T, int unroll) {
+  const int64_t tile = (int64_t)kTile * (unroll > 0 ? unroll : 1);
+  return (int)((T + tile - 1) / tile);
+}
 
 hipError_t launch_pointwise_fwd(int type, const GraphView& g, float* U, const float* P,
                                 int node_begin, int n_nodes, hipStream_t s) {

@@ -11,7 +11,8 @@ namespace grafx {
 struct GraphView;
 
 // ---- pointwise family: mix / out / gain_pan / imager / tanh (k_pointwise.hip) --------------
-int pointwise_tiles(int64_t T);  // blocks per node along time (partials per node)
+// blocks per node along time (partials per node) when every thread covers `unroll` float4 groups
+int pointwise_tiles(int64_t T, int unroll = 1);
 hipError_t launch_pointwise_fwd(int type, const GraphView& g, float* U, const float* P,
                                 int node_begin, int n_nodes, hipStream_t s);
 // dst: dU (or dS for the input step); part: double [slots][tiles][NP] (NP = 2, 1, 1, 0)

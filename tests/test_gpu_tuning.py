@@ -1,0 +1,78 @@
+"""GPU: the pointwise kernels under every tuning setting (1, 2 or 4 parts of 1024 samples per
+block). Renders and input adjoints are bit-identical across settings (the per-sample arithmetic
+does not move), parameter gradients stay within tolerance of the FP64 oracle (only the grouping
+of their partial sums changes), merged graphs still get their own bits, and the autotuner leaves
+one of the candidates set."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import GRAD_TOL, check_render, device_inputs, grad_err, oracle_grads, say
+from paper_2408_03204_amd import RenderBuffers, Schedule
+from paper_2408_03204_amd.autotune import tune_pointwise
+
+pytestmark = pytest.mark.gpu
+KNOB = Schedule.TUNE_POINTWISE_UNROLL
+TYPES = (synth.MIX, synth.GAIN_PAN, synth.IMAGER, synth.TANH, synth.EQ)
+
+
+@pytest.mark.parametrize("T", [3 * 4096 + 555, 5 * 4096 + 1024 + 4])
+def test_pointwise_unroll_settings(T):
+    w = synth.random_workload(1500, 16, T, types=TYPES, edge_p=0.3, n_out=2)
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    S, P = device_inputs(w)
+    dY = np.random.default_rng(3).normal(size=(sched.num_outputs, 2, T)).astype(np.float32)
+    dYd = torch.as_tensor(dY).cuda()
+    ref = oracle_grads(w, dY)
+    outs = {}
+    for un in (1, 2, 4):
+        say(f"[tuning] T={T} unroll={un}")
+        sched.set_tuning(KNOB, un)
+        rb = RenderBuffers(sched, T, "cuda", with_backward=True)
+        rb.forward(S, P)
+        dP = {t: torch.empty_like(p) for t, p in P.items()}
+        dS = torch.zeros_like(S)
+        rb.backward(S, P, dYd, dP, dS=dS)
+        torch.cuda.synchronize()
+        # outputs within 1e-5 of their peak; internal nodes within 1e-4 of theirs: a tanh with up
+        # to 24 dB of drive multiplies the float32 rounding of its input by up to 16
+        check_render(w, sched, rb.Y, rb.U, node_tol=1e-4)
+        for t, g in dP.items():
+            e = grad_err(g.cpu().numpy(), ref[t])
+            assert e <= GRAD_TOL, (un, t, e)
+        # the rows the library writes: U of processed nodes, dU of processed non-output nodes
+        K, ob = sched.num_inputs, sched.out_begin
+        outs[un] = (rb.U[K:].cpu().numpy(), rb.dU[K:ob].cpu().numpy(), dS.cpu().numpy())
+    for un in (2, 4):
+        for a, b in zip(outs[1], outs[un]):
+            assert np.array_equal(a, b), un
+
+
+def test_merged_graphs_keep_their_bits_under_tuning():
+    from test_gpu_batch import _alone, _check_merged  # noqa: F401
+    ws = [synth.random_workload(1600 + i, 12, T, types=TYPES) for i, T in
+          enumerate((6699, 9220, 3001))]
+    import test_gpu_batch as B
+    orig = B.Schedule
+
+    class Tuned(orig):  # every schedule the check builds runs with unroll 4
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.set_tuning(KNOB, 4)
+
+    B.Schedule = Tuned
+    try:
+        B._check_merged(ws, "unroll 4")
+    finally:
+        B.Schedule = orig
+
+
+def test_autotuner_sets_a_candidate():
+    w = synth.tiny_console(T=2 ** 15)
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    S, P = device_inputs(w)
+    times = tune_pointwise(sched, S, P, reps=2)
+    say(f"   autotune ms: {times}")
+    assert set(times) == {1, 2, 4} and all(v > 0 for v in times.values())
+    assert sched.get_tuning(KNOB) == min(times, key=times.get)

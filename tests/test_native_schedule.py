@@ -129,3 +129,18 @@ def test_workspace_bytes_grow_with_T():
     lib = load()
     n = ctypes.c_size_t()
     assert lib.grafx_workspace_bytes(s._h, 0, 0, ctypes.byref(n)) == 5  # T < 1: E_SHAPE
+
+
+def test_tuning_settings():
+    w = synth.tiny_console(T=8)
+    s = Schedule(w.graph.node_type, w.graph.edges)
+    assert s.get_tuning(Schedule.TUNE_POINTWISE_UNROLL) == 1
+    before = s.workspace_bytes(3 * 2048 + 5, True)
+    for v in (2, 4, 1):
+        s.set_tuning(Schedule.TUNE_POINTWISE_UNROLL, v)
+        assert s.get_tuning(Schedule.TUNE_POINTWISE_UNROLL) == v
+        assert s.workspace_bytes(3 * 2048 + 5, True) == before  # sized for every setting
+    for knob, v in ((0, 3), (0, 0), (7, 1)):
+        with pytest.raises(GrafxError) as e:
+            s.set_tuning(knob, v)
+        assert e.value.status == "GRAFX_E_ARG"
