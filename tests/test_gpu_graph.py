@@ -74,3 +74,34 @@ def test_graph_replay_matches_eager(T):
         gs.replay()
         _same(_snapshot(gs), eager2)
     say(f"   loss {eager[0]:.6f} -> {eager2[0]:.6f}; replays bitwise equal to eager")
+
+
+def test_graph_replay_with_dynamics_variants():
+    """A console whose compressors have attack/release ballistics, plus noisegates on the tracks:
+    their chunk state is reset by kernels, not memsets, so a captured step replays bit for bit
+    (the attack/release forward's branch-pattern passes included)."""
+    T = 2 ** 15 + 1234
+    w = synth.mixing_console(T=T, attack_release=True)
+    g = w.graph
+    # every imager becomes a noisegate (same position in the graph, gate parameters drawn)
+    nt = np.where(g.node_type == synth.IMAGER, synth.GATE, g.node_type).astype(np.int32)
+    g2 = synth.Graph(nt, g.edges)
+    params = synth.draw_params(synth.rng_for(77, 2), g2)
+    dev = torch.device("cuda")
+    sched = Schedule(g2.node_type, g2.edges, "beam")
+    S = torch.as_tensor(w.sources, device=dev)
+    P = {t: torch.as_tensor(p, device=dev) for t, p in params.items() if p.shape[0] > 0}
+    assert synth.GATE in P and synth.COMP_AR in P
+    with torch.no_grad():
+        tgt = (0.5 * render(sched, S, P)).contiguous()
+    say(f"[graph dynamics] {g2.num_nodes} nodes, gates {int((nt == synth.GATE).sum())}, "
+        f"attack/release {int((nt == synth.COMP_AR).sum())}")
+    gs = GradStep(sched, S, P, tgt)
+    gs.run()
+    eager = _snapshot(gs)
+    gs.capture()
+    for rep in range(3):
+        gs.replay()
+        _same(_snapshot(gs), eager)
+        gs.run()
+        _same(_snapshot(gs), eager)
