@@ -230,7 +230,9 @@ def setup_console(args, dev):
         maker = functools.partial(maker, attack_release=True)
     w = maker(T=args.T) if args.T else maker()
     g = w.graph
+    t_s = time.perf_counter()
     sched = Schedule(g.node_type, g.edges, args.method)
+    schedule_ms = (time.perf_counter() - t_s) * 1e3
     S = torch.as_tensor(w.sources, device=dev)
     P = {t: torch.as_tensor(p, device=dev).requires_grad_(True)
          for t, p in w.params.items() if p.shape[0] > 0}
@@ -255,7 +257,8 @@ def setup_console(args, dev):
     config = {"workload": w.name, "nodes": g.num_nodes, "processed_nodes": w.processed_nodes,
               "edges": g.num_edges, "T": w.T, "schedule": args.method,
               "steps_in_schedule": sched.num_steps, "loss": "mrstft 512/1024/2048",
-              "step": "render+loss+adjoint", **tuning}
+              "step": "render+loss+adjoint", "host_schedule_ms": round(schedule_ms, 2),
+              **tuning}
     return {"sched": sched, "S": S, "P": {t: p.detach() for t, p in P.items()}, "T": w.T,
             "rb": None, "node_samples": w.processed_nodes * w.T, "steps": steps,
             "config": config, "key": args.workload,
@@ -283,7 +286,9 @@ def setup_batch(args, dev):
     node_samples = sum(w.processed_nodes * w.T for w in ws)
     n_out = [(m["output_offset"][i], w.graph.count(synth.OUT), w.T) for i, w in enumerate(ws)]
     del ws
+    t_s = time.perf_counter()
     sched = Schedule(m["node_type"], m["edges"], args.method, lengths=m["lengths"])
+    schedule_ms = (time.perf_counter() - t_s) * 1e3
     T = m["T"]
     S = torch.as_tensor(S_h, device=dev)
     del S_h
@@ -321,7 +326,8 @@ def setup_batch(args, dev):
               "nodes": int(counts.sum()), "processed_nodes": int(counts.sum() - counts[0]),
               "edges": int(m["edges"].shape[1]), "T": "per graph U{2^16, 2^17, 2^18}",
               "row_stride": T, "schedule": args.method, "steps_in_schedule": sched.num_steps,
-              "step": "render+adjoint (seeded output adjoint)", **tuning}
+              "step": "render+adjoint (seeded output adjoint)",
+              "host_schedule_ms": round(schedule_ms, 2), **tuning}
     return {"sched": sched, "S": S, "P": P, "T": T, "rb": rb, "dY": dY,
             "node_samples": node_samples, "steps": steps, "config": config, "key": "batch",
             "cpu": (lambda: cpu_baseline_graph(sample))}
@@ -452,6 +458,24 @@ def main():
     ms = timed(steps[args.mode])  # the reported mode is timed last
     modes[args.mode] = ms
     value = ctx["node_samples"] / (ms * 1e-3)
+    # the same step timed one by one: spread of the step time
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        steps[args.mode]()
+        b.record()
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in evs)
+    spread = {q: round(float(np.percentile(per, q)), 4) for q in (10, 50, 90)}
+    # the forward render alone (the paper's render call), eager issue
+    rbf = ctx["rb"] or RenderBuffers(sched, T, dev, with_backward=False)
+    fwd_ms = timed(lambda: rbf.forward(S, ctx["P"]))
+    fwd_bytes = sum(step_bytes(sched, n, T, False) for n in range(1, sched.num_steps + 1))
+    forward = {"ms": round(fwd_ms, 4), "node_samples_per_s": round(ctx["node_samples"] /
+                                                                     (fwd_ms * 1e-3), 1),
+               "algorithmic_GBps": round(fwd_bytes / (fwd_ms * 1e6), 1),
+               "hbm_frac": round(fwd_bytes / (fwd_ms * 1e6) / HBM_PEAK_GBS, 4)}
 
     # ---- per-step breakdown: every render / adjoint step timed with events on its stream ------
     roofline, table, steps_hbm = None, [], None
@@ -528,6 +552,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": dict(ctx["config"], issue=args.mode),
            "ms_per_step_by_issue": {m: round(v, 4) for m, v in modes.items()},
+           "ms_per_step_p10_p50_p90": [spread[10], spread[50], spread[90]],
+           "forward_only": forward,
            "roofline": roofline, "render_adjoint_steps": steps_hbm, "cpu_baseline": cpu}
     print(json.dumps(out))
 
