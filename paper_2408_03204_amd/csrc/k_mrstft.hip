@@ -203,15 +203,25 @@ __device__ __forceinline__ void for_half_bins(int j, F&& fn) {
   if (j == 0) fn(N / 2);
 }
 
+// LDS of one block of the statistics and gradient passes: FPB frames x (output, target) spectra
 template <int N>
-__global__ __launch_bounds__(kBlock) void stats_kernel(int rows, int64_t T, int frames,
-                                                       const float* Y, const float* tgt,
-                                                       double* part) {
+constexpr int lds_entries() {
+  return (kBlock / Grp<N>::G) * 2 * (lpad(N - 1) + 1);
+}
+constexpr int kLdsMax = lds_entries<2048>() > lds_entries<1024>()
+                            ? (lds_entries<2048>() > lds_entries<512>() ? lds_entries<2048>()
+                                                                        : lds_entries<512>())
+                            : (lds_entries<1024>() > lds_entries<512>() ? lds_entries<1024>()
+                                                                        : lds_entries<512>());
+
+// Statistics of the frames of block bx of resolution N (one of the fused launch's ranges).
+template <int N>
+__device__ __forceinline__ void stats_body(int bx, int rows, int64_t T, int frames, const float* Y,
+                                           const float* tgt, double* part, float2* lds,
+                                           double (*red)[3]) {
   constexpr int G = Grp<N>::G, FPB = kBlock / G, S = lpad(N - 1) + 1;
-  __shared__ float2 lds[FPB * 2 * S];
-  __shared__ double red[kWaves][3];
   const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
-  const int f = blockIdx.x * FPB + grp, row = blockIdx.y;
+  const int f = bx * FPB + grp, row = blockIdx.y;
   const bool live = f < frames;  // uniform over the group
   double acc[3] = {0.0, 0.0, 0.0};  // sum (S_y - S_t)^2, sum S_t^2, sum |ln S_y - ln S_t|
   if (G == 64 ? live : true) {  // multi-wave groups keep every barrier convergent
@@ -252,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(int rows, int64_t T, int 
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) v += red[q][threadIdx.x];
-    part[((int64_t)blockIdx.x * rows + row) * 3 + threadIdx.x] = v;
+    part[((int64_t)bx * rows + row) * 3 + threadIdx.x] = v;
   }
 }
 
@@ -304,15 +314,14 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(int rows, Frames fr, dou
   *loss = (float)(L / 3.0);
 }
 
+// Frame gradients of block bx of resolution N (one of the fused launch's ranges).
 template <int N>
-__global__ __launch_bounds__(kBlock) void grad_kernel(int rows, int64_t T, int frames,
-                                                      const float* Y, const float* tgt,
-                                                      const double* consts, int res,
-                                                      const float* dloss, float* fb) {
+__device__ __forceinline__ void grad_body(int bx, int rows, int64_t T, int frames, const float* Y,
+                                          const float* tgt, const double* consts, int res,
+                                          const float* dloss, float* fb, float2* lds) {
   constexpr int G = Grp<N>::G, FPB = kBlock / G, P = N / G, S = lpad(N - 1) + 1;
-  __shared__ float2 lds[FPB * 2 * S];
   const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
-  const int f = blockIdx.x * FPB + grp, row = blockIdx.y;
+  const int f = bx * FPB + grp, row = blockIdx.y;
   const bool live = f < frames;  // uniform over the group
   if (G == 64 && !live) return;  // one-wave groups need no block-wide barrier
   float2* sy = lds + grp * 2 * S;
@@ -370,6 +379,48 @@ struct FrameBufs {
   int F[3];
   const float* fb[3];
 };
+
+// One launch for the three resolutions: block ranges [2048 | 1024 | 512] (the heaviest first),
+// each block running the code of its range with the largest range's LDS.
+__global__ __launch_bounds__(kBlock) void stats_all_kernel(int rows, int64_t T, Frames fr,
+                                                           const float* Y, const float* tgt) {
+  __shared__ float2 lds[kLdsMax];
+  __shared__ double red[kWaves][3];
+  int bx = blockIdx.x;
+  if (bx < fr.B[2]) {
+    stats_body<2048>(bx, rows, T, fr.F[2], Y, tgt, fr.part[2], lds, red);
+    return;
+  }
+  bx -= fr.B[2];
+  if (bx < fr.B[1]) {
+    stats_body<1024>(bx, rows, T, fr.F[1], Y, tgt, fr.part[1], lds, red);
+    return;
+  }
+  stats_body<512>(bx - fr.B[1], rows, T, fr.F[0], Y, tgt, fr.part[0], lds, red);
+}
+
+struct GradArgs {
+  int F[3], B[3];
+  float* fb[3];
+};
+
+__global__ __launch_bounds__(kBlock) void grad_all_kernel(int rows, int64_t T, GradArgs ga,
+                                                          const float* Y, const float* tgt,
+                                                          const double* consts,
+                                                          const float* dloss) {
+  __shared__ float2 lds[kLdsMax];
+  int bx = blockIdx.x;
+  if (bx < ga.B[2]) {
+    grad_body<2048>(bx, rows, T, ga.F[2], Y, tgt, consts, 2, dloss, ga.fb[2], lds);
+    return;
+  }
+  bx -= ga.B[2];
+  if (bx < ga.B[1]) {
+    grad_body<1024>(bx, rows, T, ga.F[1], Y, tgt, consts, 1, dloss, ga.fb[1], lds);
+    return;
+  }
+  grad_body<512>(bx - ga.B[1], rows, T, ga.F[0], Y, tgt, consts, 0, dloss, ga.fb[0], lds);
+}
 
 __global__ __launch_bounds__(kBlock) void ola_kernel(int rows, int64_t T, FrameBufs fbs,
                                                      float* dY) {
@@ -460,12 +511,12 @@ hipError_t launch_mrstft_loss(int rows, int64_t T, const float* Y, const float* 
     fr.B[i] = blocks_of(T, kRes[i]);
     fr.part[i] = reinterpret_cast<double*>(base + L.part[i]);
   }
-  if (fr.F[0] > 0)
-    stats_kernel<512><<<dim3(fr.B[0], rows), kBlock, 0, s>>>(rows, T, fr.F[0], Y, tgt, fr.part[0]);
-  if (fr.F[1] > 0)
-    stats_kernel<1024><<<dim3(fr.B[1], rows), kBlock, 0, s>>>(rows, T, fr.F[1], Y, tgt, fr.part[1]);
-  if (fr.F[2] > 0)
-    stats_kernel<2048><<<dim3(fr.B[2], rows), kBlock, 0, s>>>(rows, T, fr.F[2], Y, tgt, fr.part[2]);
+  Frames run = fr;  // block ranges of the fused launch: none for a resolution without frames
+  for (int i = 0; i < 3; ++i)
+    if (run.F[i] <= 0) run.B[i] = 0;
+  const int nb = run.B[0] + run.B[1] + run.B[2];
+  if (nb > 0)
+    stats_all_kernel<<<dim3(nb, rows), kBlock, 0, s>>>(rows, T, run, Y, tgt);
   reduce_kernel<<<1, kBlock, 0, s>>>(rows, fr, reinterpret_cast<double*>(base + L.consts), loss);
   return hipGetLastError();
 }
@@ -483,16 +534,16 @@ hipError_t launch_mrstft_bwd(int rows, int64_t T, const float* Y, const float* t
   float* fb0 = reinterpret_cast<float*>(base + L.fb[0]);
   float* fb1 = reinterpret_cast<float*>(base + L.fb[1]);
   float* fb2 = reinterpret_cast<float*>(base + L.fb[2]);
-  const int B[3] = {blocks_of(T, 512), blocks_of(T, 1024), blocks_of(T, 2048)};
-  if (fbs.F[0] > 0)
-    grad_kernel<512><<<dim3(B[0], rows), kBlock, 0, s>>>(rows, T, fbs.F[0], Y, tgt, consts, 0,
-                                                         dloss, fb0);
-  if (fbs.F[1] > 0)
-    grad_kernel<1024><<<dim3(B[1], rows), kBlock, 0, s>>>(rows, T, fbs.F[1], Y, tgt, consts, 1,
-                                                          dloss, fb1);
-  if (fbs.F[2] > 0)
-    grad_kernel<2048><<<dim3(B[2], rows), kBlock, 0, s>>>(rows, T, fbs.F[2], Y, tgt, consts, 2,
-                                                          dloss, fb2);
+  GradArgs ga;
+  float* fbw[3] = {fb0, fb1, fb2};
+  for (int i = 0; i < 3; ++i) {
+    ga.F[i] = fbs.F[i];
+    ga.B[i] = fbs.F[i] > 0 ? blocks_of(T, kRes[i]) : 0;
+    ga.fb[i] = fbw[i];
+  }
+  const int nb = ga.B[0] + ga.B[1] + ga.B[2];
+  if (nb > 0)
+    grad_all_kernel<<<dim3(nb, rows), kBlock, 0, s>>>(rows, T, ga, Y, tgt, consts, dloss);
   const int64_t n = (int64_t)rows * 2 * T;
   ola_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(rows, T, fbs, dY);
   return hipGetLastError();
