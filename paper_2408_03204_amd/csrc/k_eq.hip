@@ -12,8 +12,9 @@
 // samples before its first output, so the 2047-tap kernel never wraps. The FFT is a radix-16
 // Stockham transform with 256 threads x 16 points held in registers: the forward transform ends
 // and the inverse begins in the same register layout, so only the two inner passes of each
-// transform touch LDS; each thread keeps its 30 twiddles in registers for all transforms of the
-// block. Window gathers use raw buffer loads whose range check supplies the zero padding. Tiles
+// transform touch LDS; each thread keeps the 15 twiddles of the last pass in registers for all
+// transforms of the block and reads those of the middle pass, which take only 16 x 16 values,
+// from LDS. Window gathers use raw buffer loads whose range check supplies the zero padding. Tiles
 // of one node are mapped onto one XCD (neighbouring tiles share the halo through its L2).
 //
 // Adjoint: the input adjoint is the same filter applied to the output adjoint (h is even). The
@@ -40,20 +41,27 @@ constexpr int kLds = kN + kN / 16;  // one pad slot per 16 entries
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-// Twiddles of the two twiddled passes for thread j, loaded once per block and reused by every
-// transform of the block (the inverse uses their conjugates):
-// w1[r] = exp(-2 pi i r (j mod 16) / 256), w2[r] = exp(-2 pi i r j / 4096).
+// Twiddles of the two twiddled passes for thread j (the inverse uses their conjugates):
+// w1[r] = exp(-2 pi i r (j mod 16) / 256) comes from a 16 x 16 table in LDS, row (j mod 16)
+// padded to 17 entries so that the 16 rows read at one r fall in distinct banks; w2[r] =
+// exp(-2 pi i r j / 4096) differs in every thread and is kept in registers for all transforms
+// of the block.
+constexpr int kW1Row = 17;
+constexpr int kW1Lds = 16 * kW1Row;
+
 struct Twiddles {
-  float2 w1[16], w2[16];
+  float2 w2[16];
+  const float2* w1;  // LDS table, entry (m, r) at m * kW1Row + r
 };
 
-__device__ __forceinline__ void load_twiddles(Twiddles& tw) {
+// Fills the LDS table (thread j writes entry (j / 16, j mod 16)) and loads w2; the table is read
+// only after the first barrier of the first transform.
+__device__ __forceinline__ void load_twiddles(Twiddles& tw, float2* w1lds) {
   const int j = threadIdx.x;
+  w1lds[(j >> 4) * kW1Row + (j & 15)] = kTw4096[(j & 15) * (j >> 4) * 16];
 #pragma unroll
-  for (int r = 1; r < 16; ++r) {
-    tw.w1[r] = kTw4096[r * (j & 15) * 16];
-    tw.w2[r] = kTw4096[r * j];
-  }
+  for (int r = 1; r < 16; ++r) tw.w2[r] = kTw4096[r * j];
+  tw.w1 = w1lds;
 }
 
 // In-place 4096-point DFT (forward: exp(-2 pi i nk/N); inverse: exp(+...), unnormalised).
@@ -69,8 +77,9 @@ __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds, const Twid
   // pass 1 (sub-transform size 16)
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[pad(j + 256 * r)];
+  const float2* w1 = tw.w1 + (j & 15) * kW1Row;
 #pragma unroll
-  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], INV ? cconj(tw.w1[r]) : tw.w1[r]);
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], INV ? cconj(w1[r]) : w1[r]);
   dft16<INV>(v);
   __syncthreads();
   {
@@ -186,6 +195,7 @@ __global__ __launch_bounds__(kBlock) void eq_design_H_kernel(const double* h, fl
 __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, const float* H,
                                                         int node_begin, int tiles) {
   __shared__ float2 lds[kLds];
+  __shared__ float2 w1lds[kW1Lds];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % tiles, node = node_begin + lb / tiles;
   const int j = threadIdx.x;
@@ -193,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
   const int t0 = tile * kEqHop;
   if (t0 >= Tn) return;  // tile past the node's length
   Twiddles tw;
-  load_twiddles(tw);
+  load_twiddles(tw, w1lds);
   float2 v[16];
   gather_window<false>(g, node, t0 - kN / 4, v, 0, 16);  // window: 1024 samples of history
   fft4096<false>(v, lds, tw);
@@ -217,12 +227,13 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
 }
 
 // ---- adjoint ----------------------------------------------------------------------------------
-// Per tile: FFT of the output-adjoint window (kept in LDS), times H and inverse FFT for the input
-// adjoint, FFT of the zero-padded input tile, cross-spectrum folded and written per tile.
+// Per tile: FFT of the output-adjoint window (its spectrum kept in registers), times H and
+// inverse FFT for the input adjoint, FFT of the zero-padded input tile, real part of the
+// cross-spectrum through LDS, folded and written per tile.
 __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, const float* H,
                                                         int node_begin, int tiles, float* Fpart) {
   __shared__ float2 lds[kLds];
-  __shared__ float2 keep[kN];
+  __shared__ float2 w1lds[kW1Lds];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % tiles, i_node = lb / tiles, node = node_begin + i_node;
   const int j = threadIdx.x;
@@ -237,13 +248,13 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
     return;
   }
   Twiddles tw;
-  load_twiddles(tw);
-  float2 v[16];
+  load_twiddles(tw, w1lds);
+  float2 v[16], keep[16];
   gather_window<true>(g, node, t0 - kN / 4, v, 0, 16);
   fft4096<false>(v, lds, tw);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    keep[j + 256 * r] = v[r];
+    keep[r] = v[r];
     const float hk = Hn[j + 256 * r];
     v[r].x *= hk;
     v[r].y *= hk;
@@ -259,11 +270,13 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   }
   gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded
   fft4096<false>(v, lds, tw);
+  // Re C[k] = Re(W'[k] conj(U[k])); fold F[k] = Re C[k] + Re C[N - k], k = 0..N/2 (bins of other
+  // threads: through the transform's LDS, free again after its last barrier)
+  float* cre = reinterpret_cast<float*>(lds);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) keep[j + 256 * r] = cmulc(keep[j + 256 * r], v[r]);
-  // fold F[k] = Re C[k] + Re C[N - k], k = 0..N/2 (bins of other threads: through LDS)
+  for (int r = 0; r < 16; ++r) cre[j + 256 * r] = keep[r].x * v[r].x + keep[r].y * v[r].y;
   __syncthreads();
-  for (int k = j; k <= kN / 2; k += kBlock) out[k] = keep[k].x + keep[(kN - k) & (kN - 1)].x;
+  for (int k = j; k <= kN / 2; k += kBlock) out[k] = cre[k] + cre[(kN - k) & (kN - 1)];
 }
 
 // Sum the folded cross-spectra of the tiles of one step's nodes per bin, in double and in a fixed
@@ -297,10 +310,11 @@ __global__ __launch_bounds__(kBlock) void eq_fold_reduce_kernel(const int32_t* p
 __global__ __launch_bounds__(kBlock) void eq_grad_ifft_kernel(const float* F, double* sbuf) {
   __shared__ float2 lds[kLds];
   __shared__ float hb[kN];
+  __shared__ float2 w1lds[kW1Lds];
   const int slot = blockIdx.x;
   const int j = threadIdx.x;
   Twiddles tw;
-  load_twiddles(tw);
+  load_twiddles(tw, w1lds);
   float2 v[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
