@@ -148,6 +148,20 @@ grafx_status grafx_schedule_with_lengths(int32_t num_nodes, const int32_t* node_
                                          int32_t beam_width, int64_t state_limit,
                                          grafx_schedule_t** out);
 
+/*
+ * grafx_set_schedule_threads -- host threads that the beam and optimal searches of later
+ * grafx_schedule / grafx_schedule_with_lengths calls (on any thread) may use. The preprocessing
+ * runs on the CPU off the GPU's path, in several threads (paper Sec. 2, "Implementation
+ * details"): a search depth with enough work (states x processing nodes >= 65536) is split into
+ * contiguous slices of states, one per thread, and the children are merged in the serial order,
+ * so every thread count gives the same schedule bit for bit.
+ *   n >= 1   use at most n threads per search
+ *   n == 0   restore the default: the host's hardware concurrency, at most 16
+ *   n < 0    leave the setting unchanged (a query)
+ * Returns the setting before the call (0 for the default). Never fails.
+ */
+int32_t grafx_set_schedule_threads(int32_t n);
+
 void grafx_schedule_free(grafx_schedule_t* sched);
 
 /* Sizes of a schedule (host only). */

@@ -24,7 +24,7 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_mrstft_backward", "grafx_logmel", "grafx_encoder_gather",
            "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
            "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
-           "grafx_last_error")
+           "grafx_set_schedule_threads", "grafx_last_error")
 
 
 class GrafxError(RuntimeError):
@@ -63,6 +63,7 @@ def load() -> ctypes.CDLL:
         "grafx_schedule_with_lengths": (i32, [i32, c_i32p, i32, c_i32p, c_i32p, c_i32p, c_i32p,
                                               i32, i32, i64, ctypes.POINTER(vp)]),
         "grafx_schedule_free": (None, [vp]),
+        "grafx_set_schedule_threads": (i32, [i32]),
         "grafx_schedule_query": (i32, [vp, ctypes.POINTER(ScheduleSizes)]),
         "grafx_schedule_export": (i32, [vp] + [c_i32p] * 8),
         "grafx_plan_upload": (i32, [vp, vp, sz, vp]),

@@ -118,6 +118,32 @@ class Schedule:
         return int(n.value)
 
 
+def set_schedule_threads(n: int) -> int:
+    """Host threads a beam or optimal search may use (0: the default, the host's concurrency up
+    to 16); returns the previous setting. The schedule is the same for every count."""
+    if n < 0:
+        raise ValueError("thread count must be >= 0")
+    return int(load().grafx_set_schedule_threads(int(n)))
+
+
+def schedule_many(graphs, method: str | int = "beam", beam_width: int = 32, workers: int = 8):
+    """Schedules of several graphs, computed concurrently on host threads (each call into the
+    library releases the interpreter lock), in the order given. `graphs`: (node_type, edges) or
+    (node_type, edges, lengths) per graph. Concurrent or not, each schedule is the one
+    `Schedule` computes alone."""
+    import concurrent.futures
+
+    def one(g):
+        lengths = g[2] if len(g) > 2 else None
+        return Schedule(g[0], g[1], method, beam_width, lengths=lengths)
+
+    graphs = list(graphs)
+    if workers <= 1 or len(graphs) <= 1:
+        return [one(g) for g in graphs]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
+        return list(pool.map(one, graphs))
+
+
 def _param_list(sched: Schedule, P) -> list:
     out = [None] * NUM_TYPES
     for k, v in (P or {}).items():

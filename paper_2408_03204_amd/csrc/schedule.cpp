@@ -5,8 +5,19 @@
 // Computed-node sets are dense bitsets; the beam and optimal searches deduplicate children by set
 // (keeping the lexicographically smallest type string) and rank them by (more nodes computed,
 // smaller string). Every tie-break is fixed, so the schedule is a pure function of the graph.
+//
+// The preprocessing runs on the CPU, off the GPU's path (Sec. 2, "Implementation details"), and
+// a large search uses several host threads: the states of one search depth are split into
+// contiguous slices, each thread expands its slice, and the children are merged in the serial
+// order (state by state, types ascending), so the result does not depend on the thread count.
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "grafx_internal.h"
@@ -82,6 +93,95 @@ struct State {
   int pop = 0;
 };
 
+std::atomic<int> g_threads{0};  // 0: default
+
+int search_threads() {
+  const int n = g_threads.load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  const int hw = static_cast<int>(std::thread::hardware_concurrency());
+  return std::max(1, std::min(hw, 16));
+}
+
+// Every child of states[a, b): for each state in order, one child per non-empty type in
+// ascending type order.
+void expand(const Graph& g, const std::vector<State>& states, size_t a, size_t b,
+            std::vector<State>& out) {
+  std::vector<std::vector<int32_t>> by(kNumTypes);
+  for (size_t i = a; i < b; ++i) {
+    const State& st = states[i];
+    ready_by_type(g, st.C, by);
+    for (int t = 0; t < kNumTypes; ++t) {
+      if (by[t].empty()) continue;
+      State ch;
+      ch.C = st.C;
+      for (int32_t v : by[t]) ch.C.set(v);
+      ch.s = st.s;
+      ch.s.push_back(static_cast<int8_t>(t));
+      ch.pop = st.pop + static_cast<int>(by[t].size());
+      out.push_back(std::move(ch));
+    }
+  }
+}
+
+// Work (states x processing nodes) below which one depth is expanded on the calling thread.
+constexpr size_t kParallelWork = size_t(1) << 16;
+
+// Threads kept for one search: run(f) calls f(0) on the calling thread and f(1..n-1) on the
+// pool's threads, and returns when every call has returned.
+class SearchPool {
+ public:
+  explicit SearchPool(int n) : n_(n) {
+    for (int k = 1; k < n; ++k) threads_.emplace_back([this, k] { work(k); });
+  }
+  ~SearchPool() {
+    {
+      std::lock_guard<std::mutex> lock(m_);
+      stop_ = true;
+    }
+    go_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  int size() const { return n_; }
+  void run(const std::function<void(int)>& f) {
+    {
+      std::lock_guard<std::mutex> lock(m_);
+      job_ = f;
+      pending_ = n_ - 1;
+      ++generation_;
+    }
+    go_.notify_all();
+    f(0);
+    std::unique_lock<std::mutex> lock(m_);
+    done_.wait(lock, [&] { return pending_ == 0; });
+  }
+
+ private:
+  void work(int k) {
+    uint64_t seen = 0;
+    for (;;) {
+      std::function<void(int)> job;
+      {
+        std::unique_lock<std::mutex> lock(m_);
+        go_.wait(lock, [&] { return stop_ || generation_ != seen; });
+        if (stop_) return;
+        seen = generation_;
+        job = job_;
+      }
+      job(k);
+      std::lock_guard<std::mutex> lock(m_);
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  const int n_;
+  std::vector<std::thread> threads_;
+  std::mutex m_;
+  std::condition_variable go_, done_;
+  std::function<void(int)> job_;
+  int pending_ = 0;
+  uint64_t generation_ = 0;
+  bool stop_ = false;
+};
+
 grafx_status search_one_by_one(const Graph& g, std::vector<std::vector<int32_t>>& steps) {
   Bits C = g.start;
   std::vector<std::vector<int32_t>> by(kNumTypes);
@@ -120,7 +220,7 @@ grafx_status search_beam(const Graph& g, int64_t width, int64_t state_limit,
   states[0].C = g.start;
   states[0].pop = g.start.count();
   const int full_pop = g.full.count();
-  std::vector<std::vector<int32_t>> by(kNumTypes);
+  std::unique_ptr<SearchPool> pool;  // created at the first depth large enough to split
   for (;;) {
     const State* best_done = nullptr;
     for (const State& st : states)
@@ -130,18 +230,26 @@ grafx_status search_beam(const Graph& g, int64_t width, int64_t state_limit,
       types = best_done->s;
       return GRAFX_OK;
     }
+    // expansion (in slices on several threads when the depth is large), then the merge in the
+    // serial order with deduplication by computed set
+    const size_t ns = states.size();
+    if (!pool && ns > 1 && ns * g.proc.size() >= kParallelWork && search_threads() > 1)
+      pool = std::make_unique<SearchPool>(search_threads());
+    const int nt = pool && ns * g.proc.size() >= kParallelWork
+                       ? static_cast<int>(std::min<size_t>(ns, pool->size()))
+                       : 1;
+    std::vector<std::vector<State>> part(nt);
+    if (nt == 1) {
+      expand(g, states, 0, ns, part[0]);
+    } else {
+      pool->run([&](int k) {
+        if (k < nt) expand(g, states, ns * k / nt, ns * (k + 1) / nt, part[k]);
+      });
+    }
     std::vector<State> children;
     std::unordered_map<Bits, size_t, BitsHash> index;
-    for (const State& st : states) {
-      ready_by_type(g, st.C, by);
-      for (int t = 0; t < kNumTypes; ++t) {
-        if (by[t].empty()) continue;
-        State ch;
-        ch.C = st.C;
-        for (int32_t v : by[t]) ch.C.set(v);
-        ch.s = st.s;
-        ch.s.push_back(static_cast<int8_t>(t));
-        ch.pop = st.pop + static_cast<int>(by[t].size());
+    for (auto& pk : part)
+      for (State& ch : pk) {
         auto it = index.find(ch.C);
         if (it == index.end()) {
           index.emplace(ch.C, children.size());
@@ -150,7 +258,6 @@ grafx_status search_beam(const Graph& g, int64_t width, int64_t state_limit,
           children[it->second].s = std::move(ch.s);
         }
       }
-    }
     if (children.empty()) return fail(GRAFX_E_GRAPH, "schedule search stalled (internal)");
     std::sort(children.begin(), children.end(), [](const State& a, const State& b) {
       if (a.pop != b.pop) return a.pop > b.pop;
@@ -215,6 +322,11 @@ using namespace grafx;
 extern "C" {
 
 const char* grafx_last_error(void) { return g_error.c_str(); }
+
+int32_t grafx_set_schedule_threads(int32_t n) {
+  if (n < 0) return g_threads.load();
+  return g_threads.exchange(n);
+}
 
 grafx_status grafx_schedule(int32_t num_nodes, const int32_t* node_type, int32_t num_edges,
                             const int32_t* edge_src, const int32_t* edge_dst,
@@ -290,6 +402,7 @@ grafx_status grafx_schedule(int32_t num_nodes, const int32_t* node_type, int32_t
     if (g.type[v] == GRAFX_IN) { g.start.set(v); g.full.set(v); }
     else if (g.type[v] != GRAFX_OUT) { g.proc.push_back(v); g.full.set(v); }
   }
+
 
   std::vector<std::vector<int32_t>> steps;
   {

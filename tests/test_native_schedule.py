@@ -11,7 +11,8 @@ import pytest
 
 import synth
 from oracle import schedule as osch
-from paper_2408_03204_amd import EXPORTS, GrafxError, Schedule, load
+from paper_2408_03204_amd import (EXPORTS, GrafxError, Schedule, load, merge_graphs,
+                                  schedule_many, set_schedule_threads)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 METHODS = [(osch.ONE_BY_ONE, "one_by_one"), (osch.GREEDY, "greedy"), (osch.BEAM, "beam"),
@@ -31,7 +32,8 @@ def assert_same(g, method_code, name, beam=32, limit=1 << 20):
 
 def test_header_symbols_exported():
     header = open(os.path.join(ROOT, "include", "grafx.h")).read()
-    declared = set(re.findall(r"^(?:grafx_status|void|const char\*)\s+(grafx_\w+)\(", header, re.M))
+    declared = set(re.findall(r"^(?:grafx_status|void|int32_t|const char\*)\s+(grafx_\w+)\(", header,
+                              re.M))
     assert declared == set(EXPORTS)
     lib = load()
     for name in declared:
@@ -144,3 +146,61 @@ def test_tuning_settings():
         with pytest.raises(GrafxError) as e:
             s.set_tuning(knob, v)
         assert e.value.status == "GRAFX_E_ARG"
+
+
+FIELDS = ("step_type", "step_ptr", "perm", "in_ptr", "in_src", "out_ptr", "out_dst", "param_row")
+
+
+def _arrays(s):
+    return [np.array(getattr(s, f)) for f in FIELDS]
+
+
+def test_threaded_search_gives_the_serial_schedule():
+    """A merged batch large enough for the beam search to split its depths over host threads
+    (3,000+ processing nodes, 32 states): 1, 2, 3 and 8 threads give the same schedule bit for
+    bit, at two beam widths (the children are merged in the serial order)."""
+    ws = [synth.batched_graph(3, i, T_choices=(64,)) for i in range(24)]
+    m = merge_graphs([(w.graph.node_type, w.graph.edges, w.T) for w in ws])
+    assert sum(int(t) not in (synth.IN, synth.OUT) for t in m["node_type"]) >= 3000
+    prev = set_schedule_threads(1)
+    try:
+        for width in (32, 5):
+            set_schedule_threads(1)
+            ref = _arrays(Schedule(m["node_type"], m["edges"], "beam", beam_width=width))
+            for n in (2, 3, 8):
+                set_schedule_threads(n)
+                got = _arrays(Schedule(m["node_type"], m["edges"], "beam", beam_width=width))
+                for f, a, b in zip(FIELDS, ref, got):
+                    assert np.array_equal(a, b), (width, n, f)
+    finally:
+        set_schedule_threads(prev)
+
+
+def test_schedule_threads_setting():
+    prev = set_schedule_threads(3)
+    try:
+        assert set_schedule_threads(5) == 3
+        assert load().grafx_set_schedule_threads(-1) == 5  # a query leaves it unchanged
+        assert set_schedule_threads(0) == 5
+        assert load().grafx_set_schedule_threads(-1) == 0
+        with pytest.raises(ValueError):
+            set_schedule_threads(-2)
+    finally:
+        set_schedule_threads(prev)
+
+
+def test_schedule_many_matches_one_by_one():
+    """Schedules computed concurrently on host threads equal the ones computed alone, in order,
+    for graphs with and without per-node lengths."""
+    graphs = []
+    for i in range(6):
+        w = synth.batched_graph(11, i, T_choices=(64,))
+        graphs.append((w.graph.node_type, w.graph.edges))
+    m = merge_graphs([(g[0], g[1], 32 + 8 * i) for i, g in enumerate(graphs[:3])])
+    graphs.append((m["node_type"], m["edges"], m["lengths"]))
+    many = schedule_many(graphs, "beam", workers=4)
+    assert len(many) == len(graphs)
+    for g, s in zip(graphs, many):
+        alone = Schedule(g[0], g[1], "beam", lengths=g[2] if len(g) > 2 else None)
+        for f, a, b in zip(FIELDS, _arrays(alone), _arrays(s)):
+            assert np.array_equal(a, b), f
