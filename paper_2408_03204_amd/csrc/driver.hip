@@ -77,13 +77,8 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.part_tanh = take(h->type_count[GRAFX_TANH] * tiles * sizeof(double));
     L.comp_ragg = take(n_comp * chunks * sizeof(uint64_t));
     L.comp_part = take(n_comp * chunks * 4 * sizeof(double));
-    size_t fold = 0;  // EQ adjoint partials of the largest step (reused step after step)
-    for (int n = 1; n <= h->N; ++n) {
-      if (h->step_type[n] != GRAFX_EQ) continue;
-      const int cnt = h->step_ptr[n + 1] - h->step_ptr[n];
-      fold = std::max(fold, (size_t)cnt * eq_tiles(T));
-    }
-    L.eq_C = take(fold * kEqFoldStride * sizeof(float));
+    // EQ adjoint partials: a region per EQ node (parameter row), summed once after the last step
+    L.eq_C = take(n_eq * (size_t)eq_tiles(T) * kEqFoldStride * sizeof(float));
     L.eq_spec = take(n_eq * kEqFoldStride * sizeof(float));
     L.eq_s = take(n_eq * 1024 * sizeof(double));
     L.delay_part = take(n_del * delay_groups(T) * kDelayCoef * sizeof(float));
@@ -234,8 +229,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_TANH:
       return launch_pointwise_bwd(t, g, dU, p, b, cnt, at<double>(ws, L.part_tanh), stream);
     case GRAFX_EQ:
-      return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float>(ws, L.eq_C),
-                           at<float>(ws, L.eq_spec), stream);
+      return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float>(ws, L.eq_C), stream);
     case GRAFX_COMPRESSOR:
     case GRAFX_NOISEGATE:
       return launch_comp_bwd(g, dU, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
@@ -337,24 +331,25 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
   if (e == hipSuccess && dS && h->K > 0)  // adjoint of the input step: sum over output edges
     e = launch_pointwise_bwd(GRAFX_IN, g, dS, nullptr, 0, h->K, nullptr, stream);
   const int tiles = pointwise_tiles(T, h->pw_unroll), chunks = comp_chunks(T);
-  if (e == hipSuccess && dpar(GRAFX_GAIN_PAN))
-    e = launch_reduce_partials(at<double>(ws, L.part_gp), h->type_count[GRAFX_GAIN_PAN], tiles, 2,
-                               dpar(GRAFX_GAIN_PAN), stream);
-  if (e == hipSuccess && dpar(GRAFX_IMAGER))
-    e = launch_reduce_partials(at<double>(ws, L.part_im), h->type_count[GRAFX_IMAGER], tiles, 1,
-                               dpar(GRAFX_IMAGER), stream);
-  if (e == hipSuccess && dpar(GRAFX_TANH))
-    e = launch_reduce_partials(at<double>(ws, L.part_tanh), h->type_count[GRAFX_TANH], tiles, 1,
-                               dpar(GRAFX_TANH), stream);
+  ReduceJobs jobs;
+  if (dpar(GRAFX_GAIN_PAN))
+    jobs.add(at<double>(ws, L.part_gp), h->type_count[GRAFX_GAIN_PAN], tiles, 2,
+             dpar(GRAFX_GAIN_PAN));
+  if (dpar(GRAFX_IMAGER))
+    jobs.add(at<double>(ws, L.part_im), h->type_count[GRAFX_IMAGER], tiles, 1, dpar(GRAFX_IMAGER));
+  if (dpar(GRAFX_TANH))
+    jobs.add(at<double>(ws, L.part_tanh), h->type_count[GRAFX_TANH], tiles, 1, dpar(GRAFX_TANH));
   for (int t : {GRAFX_COMPRESSOR, GRAFX_NOISEGATE})
-    if (e == hipSuccess && dpar(t) && h->type_count[t] > 0)
-      e = launch_reduce_partials(at<double>(ws, L.comp_part) + (size_t)dyn_row(h, t) * chunks * 4,
-                                 h->type_count[t], chunks, 4, dpar(t), stream);
-  if (e == hipSuccess && dpar(GRAFX_COMPRESSOR_AR))
-    e = launch_reduce_partials(at<double>(ws, L.ar_part), h->type_count[GRAFX_COMPRESSOR_AR],
-                               chunks, kArParams, dpar(GRAFX_COMPRESSOR_AR), stream);
+    if (dpar(t))
+      jobs.add(at<double>(ws, L.comp_part) + (size_t)dyn_row(h, t) * chunks * 4, h->type_count[t],
+               chunks, 4, dpar(t));
+  if (dpar(GRAFX_COMPRESSOR_AR))
+    jobs.add(at<double>(ws, L.ar_part), h->type_count[GRAFX_COMPRESSOR_AR], chunks, kArParams,
+             dpar(GRAFX_COMPRESSOR_AR));
+  if (e == hipSuccess) e = launch_reduce_partials(jobs, stream);
   if (e == hipSuccess && dpar(GRAFX_EQ))
-    e = launch_eq_grad(par(GRAFX_EQ), at<float>(ws, L.eq_spec), h->type_count[GRAFX_EQ],
+    e = launch_eq_grad(par(GRAFX_EQ), at<float>(ws, L.eq_C), eq_tiles(T),
+                       at<float>(ws, L.eq_spec), h->type_count[GRAFX_EQ],
                        at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
   if (e == hipSuccess && dpar(GRAFX_DELAY))
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),

@@ -23,11 +23,11 @@
 // the conjugate spectrum of the zero-padded input tile). The design is even in n, so only
 // hbar[n] + hbar[-n] matters: the inverse transform of the real, even sequence
 // F[k] = Re C[k] + Re C[N - k], of which N/2 + 1 values are kept. Each block handles one tile
-// and writes its folded F; right after the step the tiles' F are summed per node in a fixed
-// order, which does not depend on how nodes are grouped into steps, so results do not depend on
-// the schedule. After the last step one inverse FFT per node gives hbar[n] + hbar[-n], and the
-// chain rule through the design gives dL/dp_k = (kappa_k / 2047) A_k sum_n hbar[n] v[n]
-// cos(2 pi k n / 2047).
+// and writes its folded F into its node's own region; after the last step one launch sums the
+// tiles' F per node in a fixed order, which does not depend on how nodes are grouped into steps,
+// so results do not depend on the schedule. Then one inverse FFT per node gives
+// hbar[n] + hbar[-n], and the chain rule through the design gives
+// dL/dp_k = (kappa_k / 2047) A_k sum_n hbar[n] v[n] cos(2 pi k n / 2047).
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
@@ -235,13 +235,13 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tile = lb % tiles, i_node = lb / tiles, node = node_begin + i_node;
+  const int tile = lb % tiles, node = node_begin + lb / tiles;
   const int j = threadIdx.x;
   const int64_t T = g.T, Tn = node_len(g, node);
   const int slot = g.param_row[node];
   const float* Hn = H + (int64_t)slot * kN;
   float* d = dU + (int64_t)node * 2 * T;
-  float* out = Fpart + ((int64_t)i_node * tiles + tile) * kEqFoldStride;
+  float* out = Fpart + ((int64_t)slot * tiles + tile) * kEqFoldStride;
   const int t0 = tile * kEqHop;
   if (t0 >= Tn) {  // tile past the node's length: contributes nothing to the gradient
     for (int k = j; k <= kN / 2; k += kBlock) out[k] = 0.f;
@@ -279,30 +279,28 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
   for (int k = j; k <= kN / 2; k += kBlock) out[k] = cre[k] + cre[(kN - k) & (kN - 1)];
 }
 
-// Sum the folded cross-spectra of the tiles of one step's nodes per bin, in double and in a fixed
+// Sum the folded cross-spectra of the tiles of every EQ node per bin, in double and in a fixed
 // order: wave w of a block sums tiles w, w + 4, w + 8, ... of 64 bins, then the four wave sums
-// are added in order.
-__global__ __launch_bounds__(kBlock) void eq_fold_reduce_kernel(const int32_t* param_row,
-                                                                int node_begin, const float* Fpart,
-                                                                int tiles, float* F) {
+// are added in order. Each node has its own region of partials, so one launch after the last
+// adjoint step serves every step, and the order does not depend on how nodes form steps.
+__global__ __launch_bounds__(kBlock) void eq_fold_reduce_kernel(const float* Fpart, int tiles,
+                                                                float* F) {
   __shared__ double part[4][64];
-  const int i_node = blockIdx.x;
+  const int slot = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int k = blockIdx.y * 64 + lane;
   const bool live = k <= kN / 2;
   double s = 0.0;
   if (live) {
-    const float* p = Fpart + (int64_t)i_node * tiles * kEqFoldStride + k;
+    const float* p = Fpart + (int64_t)slot * tiles * kEqFoldStride + k;
 #pragma unroll 8
     for (int t = w; t < tiles; t += 4) s += p[(int64_t)t * kEqFoldStride];
   }
   part[w][lane] = s;
   __syncthreads();
-  if (w == 0 && live) {
-    const int slot = param_row[node_begin + i_node];
+  if (w == 0 && live)
     F[(int64_t)slot * kEqFoldStride + k] =
         (float)(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
-  }
 }
 
 // The inverse FFT of the folded cross-spectrum gives hbar[n] + hbar[-n]; with the window,
@@ -371,18 +369,17 @@ hipError_t launch_eq_fwd(const GraphView& g, float* U, const float* H, int node_
 }
 
 hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node_begin,
-                         int n_nodes, float* Fpart, float* F, hipStream_t s) {
+                         int n_nodes, float* Fpart, hipStream_t s) {
   const int tiles = eq_tiles(g.T);
   eq_bwd_kernel<<<(unsigned)(tiles * n_nodes), kBlock, 0, s>>>(g, dU, H, node_begin, tiles,
                                                                Fpart);
-  eq_fold_reduce_kernel<<<dim3(n_nodes, (kN / 2 + 64) / 64), kBlock, 0, s>>>(
-      g.param_row, node_begin, Fpart, tiles, F);
   return hipGetLastError();
 }
 
-hipError_t launch_eq_grad(const float* P, const float* F, int n_eq, double* sbuf, float* dP,
-                          hipStream_t s) {
+hipError_t launch_eq_grad(const float* P, const float* Fpart, int tiles, float* F, int n_eq,
+                          double* sbuf, float* dP, hipStream_t s) {
   if (n_eq <= 0) return hipSuccess;
+  eq_fold_reduce_kernel<<<dim3(n_eq, (kN / 2 + 64) / 64), kBlock, 0, s>>>(Fpart, tiles, F);
   eq_grad_ifft_kernel<<<n_eq, kBlock, 0, s>>>(F, sbuf);
   eq_grad_p_kernel<<<dim3(n_eq, 1024 / kCosOut), kBlock, 0, s>>>(P, sbuf, dP);
   return hipGetLastError();

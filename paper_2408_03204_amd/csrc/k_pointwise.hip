@@ -258,16 +258,19 @@ __global__ __launch_bounds__(kBlock) void pointwise_bwd_kernel(GraphView g, floa
   }
 }
 
-// dP[slot][j] = sum over tiles of part[slot][tile][j], fixed order.
-__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const double* part, int tiles,
-                                                                 int np, float* dP) {
+// dP[slot][j] = sum over tiles of part[slot][tile][j], fixed order; one launch for every job of
+// the list, block b serving slot b of the concatenated slot ranges.
+__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(ReduceJobs J) {
   __shared__ double red[4];
-  const int slot = blockIdx.x;
+  int slot = blockIdx.x, q = 0;
+  while (q + 1 < J.n && slot >= J.slots[q]) slot -= J.slots[q++];  // uniform over the block
+  const double* part = J.part[q];
+  const int tiles = J.tiles[q], np = J.np[q];
   for (int j = 0; j < np; ++j) {
     double s = 0.0;
     for (int i = threadIdx.x; i < tiles; i += kBlock) s += part[((int64_t)slot * tiles + i) * np + j];
     s = block_sum<double>(s, red);
-    if (threadIdx.x == 0) dP[(int64_t)slot * np + j] = (float)s;
+    if (threadIdx.x == 0) J.dP[q][(int64_t)slot * np + j] = (float)s;
   }
 }
 
@@ -347,10 +350,11 @@ hipError_t launch_pointwise_bwd(int type, const GraphView& g, float* dst, const 
   }
 }
 
-hipError_t launch_reduce_partials(const double* part, int n_slots, int tiles, int np, float* dP,
-                                  hipStream_t s) {
-  if (n_slots <= 0) return hipSuccess;
-  reduce_partials_kernel<<<n_slots, kBlock, 0, s>>>(part, tiles, np, dP);
+hipError_t launch_reduce_partials(const ReduceJobs& jobs, hipStream_t s) {
+  int blocks = 0;
+  for (int q = 0; q < jobs.n; ++q) blocks += jobs.slots[q];
+  if (blocks <= 0) return hipSuccess;
+  reduce_partials_kernel<<<blocks, kBlock, 0, s>>>(jobs);
   return hipGetLastError();
 }
 

@@ -18,8 +18,25 @@ hipError_t launch_pointwise_fwd(int type, const GraphView& g, float* U, const fl
 // dst: dU (or dS for the input step); part: double [slots][tiles][NP] (NP = 2, 1, 1, 0)
 hipError_t launch_pointwise_bwd(int type, const GraphView& g, float* dst, const float* P,
                                 int node_begin, int n_nodes, double* part, hipStream_t s);
-hipError_t launch_reduce_partials(const double* part, int n_slots, int tiles, int np, float* dP,
-                                  hipStream_t s);
+// Fixed-order sums of per-tile parameter-gradient partials, several parameter types in one
+// launch: job q reduces part[q] [slots][tiles][np] (double) into dP[q] [slots][np] (float).
+struct ReduceJobs {
+  static constexpr int kMax = 8;
+  const double* part[kMax];
+  float* dP[kMax];
+  int slots[kMax], tiles[kMax], np[kMax];
+  int n = 0;
+  void add(const double* p, int n_slots, int n_tiles, int n_par, float* out) {
+    if (n_slots <= 0) return;
+    part[n] = p;
+    dP[n] = out;
+    slots[n] = n_slots;
+    tiles[n] = n_tiles;
+    np[n] = n_par;
+    ++n;
+  }
+};
+hipError_t launch_reduce_partials(const ReduceJobs& jobs, hipStream_t s);
 
 // ---- EQ (k_eq.hip) ---------------------------------------------------------------------------
 constexpr int kEqFFT = 4096;  // overlap-save FFT size
@@ -30,13 +47,15 @@ constexpr int kEqFoldStride = 2112;  // N/2 + 1 = 2049 folded bins, padded to 25
 hipError_t launch_eq_design(const float* P, int n_eq, double* h, float* H, hipStream_t s);
 hipError_t launch_eq_fwd(const GraphView& g, float* U, const float* H, int node_begin,
                          int n_nodes, hipStream_t s);
-// Adjoint of one step. Fpart: float [n_nodes][tiles][kEqFoldStride] scratch; F: float
-// [n_eq][kEqFoldStride]: the rows (by parameter slot) of the step's nodes are written.
+// Adjoint of one step. Fpart: float [n_eq][tiles][kEqFoldStride]: the regions (by parameter
+// slot) of the step's nodes are written, one folded cross-spectrum per tile.
 hipError_t launch_eq_bwd(const GraphView& g, float* dU, const float* H, int node_begin,
-                         int n_nodes, float* Fpart, float* F, hipStream_t s);
-// F as written by the adjoint steps; sbuf: double [n_eq][1024] scratch; dP: float [n_eq][1024]
-hipError_t launch_eq_grad(const float* P, const float* F, int n_eq, double* sbuf, float* dP,
-                          hipStream_t s);
+                         int n_nodes, float* Fpart, hipStream_t s);
+// After the last adjoint step: the tiles of Fpart summed per slot into F (float
+// [n_eq][kEqFoldStride]), then the FIR and parameter gradients; sbuf: double [n_eq][1024]
+// scratch; dP: float [n_eq][1024]
+hipError_t launch_eq_grad(const float* P, const float* Fpart, int tiles, float* F, int n_eq,
+                          double* sbuf, float* dP, hipStream_t s);
 
 // ---- compressor (k_comp.hip) ---------------------------------------------------------------
 constexpr int kCompChunk = 3072;  // 256 threads x 12 samples
