@@ -135,15 +135,18 @@ __device__ __forceinline__ void gather_window(const GraphView& g, int node, int 
 // Cosine sums in double, eight lanes per output: lane q sums the terms m = q, q + 8, ... with the
 // stride-8 Chebyshev recurrence c_{m+8} = 2 cos(8 theta) c_m - c_{m-8}, so each lane's dependent
 // chain is 128 FMAs long; the eight partial sums are combined by a fixed xor butterfly (addition
-// is commutative, so all eight lanes end with the same value).
+// is commutative, so all eight lanes end with the same value). Every angle is theta = 2 pi s / M
+// for an integer s, so the starting cosines of each lane are read from the table
+// tab[i] = cos(2 pi i / M) (correctly rounded) instead of being evaluated.
 
 constexpr int kCosLanes = 8;
 
-__device__ __forceinline__ double cos_sum(const double* w, double theta_over_pi) {
-  // sum_{m=1}^{1023} w[m] cos(m theta)
+template <int M>
+__device__ __forceinline__ double cos_sum(const double* w, int s, const double* tab) {
+  // sum_{m=1}^{1023} w[m] cos(2 pi m s / M), 0 <= s < 2 M
   const int q = (int)threadIdx.x & (kCosLanes - 1);
-  const double two_c8 = 2.0 * cospi(kCosLanes * theta_over_pi);
-  double cm = cospi((q - kCosLanes) * theta_over_pi), c = cospi(q * theta_over_pi);
+  const double two_c8 = 2.0 * tab[(kCosLanes * s) % M];
+  double cm = tab[((q - kCosLanes) * s % M + M) % M], c = tab[(q * s) % M];
   double acc = q > 0 ? w[q] * c : 0.0;  // the m = 0 term is not part of the sum
   {
     const double cn = fma(two_c8, c, -cm);
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void eq_design_h_kernel(const float* P, dou
   for (int i = threadIdx.x; i < 1024; i += kBlock) A[i] = exp((double)P[(int64_t)slot * 1024 + i]);
   __syncthreads();
   const int n = blockIdx.y * kCosOut + (int)threadIdx.x / kCosLanes;  // 0..1023
-  const double h0 = (A[0] + 2.0 * cos_sum(A, 2.0 * n / 2047.0)) / 2047.0;
+  const double h0 = (A[0] + 2.0 * cos_sum<2047>(A, n, kCos2047)) / 2047.0;
   const double win = 0.5 + 0.5 * cospi((double)n / 1023.0);
   if ((threadIdx.x & (kCosLanes - 1)) == 0) h[(int64_t)slot * 1024 + n] = win * h0;
 }
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void eq_design_H_kernel(const double* h, fl
   __syncthreads();
   const int k = blockIdx.y * kCosOut + (int)threadIdx.x / kCosLanes;
   if (k > kN / 2) return;  // whole groups of kCosLanes lanes leave together
-  const float Hk = (float)((hs[0] + 2.0 * cos_sum(hs, k / (double)(kN / 2))) / (double)kN);
+  const float Hk = (float)((hs[0] + 2.0 * cos_sum<kN>(hs, k, kCos4096)) / (double)kN);
   if ((threadIdx.x & (kCosLanes - 1)) != 0) return;
   float* Hn = H + (int64_t)slot * kN;
   Hn[k] = Hk;
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void eq_grad_p_kernel(const float* P, const
   for (int i = threadIdx.x; i < 1024; i += kBlock) s[i] = sbuf[(int64_t)slot * 1024 + i];
   __syncthreads();
   const int k = blockIdx.y * kCosOut + (int)threadIdx.x / kCosLanes;  // 0..1023
-  const double acc = cos_sum(s, 2.0 * k / 2047.0);
+  const double acc = cos_sum<2047>(s, k, kCos2047);
   if ((threadIdx.x & (kCosLanes - 1)) != 0) return;
   const double A = exp((double)P[(int64_t)slot * 1024 + k]);
   const double kappa = k == 0 ? 1.0 : 2.0;
