@@ -204,3 +204,23 @@ def test_schedule_many_matches_one_by_one():
         alone = Schedule(g[0], g[1], "beam", lengths=g[2] if len(g) > 2 else None)
         for f, a, b in zip(FIELDS, _arrays(alone), _arrays(s)):
             assert np.array_equal(a, b), f
+
+
+def test_concurrent_threaded_searches():
+    """Several large searches at once, each splitting its depths over its own thread pool (four
+    threads each, three searches on three host threads): every schedule equals the one computed
+    alone on one thread."""
+    merged = []
+    for seed in (5, 6, 7):
+        ws = [synth.batched_graph(seed, i, T_choices=(64,)) for i in range(20)]
+        merged.append(merge_graphs([(w.graph.node_type, w.graph.edges, w.T) for w in ws]))
+    prev = set_schedule_threads(1)
+    try:
+        alone = [_arrays(Schedule(m["node_type"], m["edges"], "beam")) for m in merged]
+        set_schedule_threads(4)
+        many = schedule_many([(m["node_type"], m["edges"]) for m in merged], "beam", workers=3)
+        for ref, s in zip(alone, many):
+            for f, a, b in zip(FIELDS, ref, _arrays(s)):
+                assert np.array_equal(a, b), f
+    finally:
+        set_schedule_threads(prev)
