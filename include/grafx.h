@@ -32,7 +32,9 @@
  *   2 mix        --   sum of inputs
  *   3 gain_pan   2    y_c = exp(p_c) u_c                                  (paper Eq. 2)
  *   4 eq         1024 zero-phase 2047-tap FIR from 1024 log-magnitudes    (Eqs. 4-5)
- *   5 compressor 4    (alpha, T, W, R): one-pole energy envelope, quadratic knee (Eqs. 8-12)
+ *   5 compressor 4    (alpha, T, W, R): one-pole energy envelope, quadratic knee (Eqs. 8-12);
+ *                     alpha in [0, 1) (the envelope of a negative alpha can go negative and
+ *                     its log is NaN, as in Eq. 11); W <= 0 is a hard knee; R > 0
  *   6 imager     1    mid/side width                                     (Eq. 3)
  *   7 delay      220  [channel 2][slot 5][re z, im z, 20 log-magnitudes]  (Eq. 14, <= 500 ms)
  *   8 tanh       1    y = tanh(exp(p) u)                                  (not in the paper)
@@ -108,7 +110,7 @@ typedef struct grafx_schedule_sizes {
  * a width cap. Nodes are then reordered by (step, original id) ("sigma"), and the read/write
  * index lists are built as CSR arrays in that order.
  *
- *   num_nodes, node_type    host int32[num_nodes], codes 0..8
+ *   num_nodes, node_type    host int32[num_nodes], codes 0..10 (the node types above)
  *   num_edges, edge_src/dst host int32[num_edges] each (may be NULL when num_edges == 0)
  *   edge_type               host int32[2*num_edges] or NULL; must be all zero (SISO graphs)
  *   method                  grafx_sched_method
@@ -162,13 +164,32 @@ grafx_status grafx_schedule_with_lengths(int32_t num_nodes, const int32_t* node_
  */
 int32_t grafx_set_schedule_threads(int32_t n);
 
+/*
+ * grafx_schedule_free -- release a handle made by grafx_schedule or grafx_schedule_with_lengths
+ * (the host copy of the preprocessing results of Algorithm 1: the type string, the reordering
+ * sigma and the read/write indices). NULL is ignored. The caller must not free a handle that a
+ * call on another thread still uses, nor before a grafx_plan_upload copy from it has completed.
+ */
 void grafx_schedule_free(grafx_schedule_t* sched);
 
-/* Sizes of a schedule (host only). */
+/*
+ * grafx_schedule_query -- sizes of a schedule (host only): |V|, |E|, the number N of processing
+ * steps after the input step (the length of the type string minus one, paper Sec. 2 "Type
+ * scheduling": steps V_0..V_N), the input count K (Sec. 2 "Graph representations": the k-th
+ * source feeds the k-th input node), the output count |V_N| (the rows of Y, Algorithm 1 Ensure),
+ * the nodes per type (the rows each P[t] must have, Algorithm 1 Require), the device bytes of
+ * the plan and the largest per-node length.
+ * Errors: GRAFX_E_ARG for a NULL argument. Never touches the device.
+ */
 grafx_status grafx_schedule_query(const grafx_schedule_t* sched, grafx_schedule_sizes* out);
 
 /*
- * Host copies of the schedule arrays (every pointer may be NULL to skip that array):
+ * grafx_schedule_export -- host copies of the outputs of ScheduleBatchedProcessing,
+ * OptimizeNodeOrder and GetReadWriteIndex of Algorithm 1 (paper Sec. 2, "Implementation
+ * details"): the type string, the reordering sigma, and the gather (I^G), aggregate (I^A),
+ * parameter (I^P) and store (I^S) indices, here in CSR form over sigma positions. Every pointer
+ * may be NULL to skip that array; the caller owns the arrays, sized as below from
+ * grafx_schedule_query. Errors: GRAFX_E_ARG for a NULL schedule.
  *   step_type int32[N+1]  type of each step (step 0 = in, step N = out)
  *   step_ptr  int32[N+2]  step n holds reordered positions [step_ptr[n], step_ptr[n+1])
  *   perm      int32[V]    perm[i] = original id of the node at reordered position i
@@ -184,15 +205,27 @@ grafx_status grafx_schedule_export(const grafx_schedule_t* sched, int32_t* step_
                                    int32_t* param_row);
 
 /*
- * Copy the index lists to caller-owned device memory `dev_plan` (>= plan_bytes bytes, 256-byte
- * aligned) with an asynchronous host-to-device copy on `stream`. The host arrays belong to the
- * handle, which must outlive the copy.
+ * grafx_plan_upload -- copy the read/write indices of GetReadWriteIndex (Algorithm 1; I^G and
+ * I^A as the in-CSR, its mirror for the adjoint, I^P as param_row, and per-node lengths if any)
+ * to caller-owned device memory `dev_plan` (>= plan_bytes bytes, 256-byte aligned) with an
+ * asynchronous host-to-device copy on `stream`; the main loop of Algorithm 1 reads them there.
+ * The host arrays belong to the handle, which must outlive the copy.
+ * Errors: GRAFX_E_ARG (NULL schedule or plan), GRAFX_E_WORKSPACE (bytes < plan_bytes),
+ * GRAFX_E_SHAPE (misaligned plan), GRAFX_E_HIP (the copy could not be enqueued).
  */
 grafx_status grafx_plan_upload(const grafx_schedule_t* sched, void* dev_plan, size_t bytes,
                                hipStream_t stream);
 
-/* Workspace bytes for grafx_render (with_backward = 0) or for a render followed by
- * grafx_render_backward on the same workspace (with_backward = 1), for signals of length T. */
+/*
+ * grafx_workspace_bytes -- device workspace bytes for grafx_render (with_backward = 0) or for a
+ * render followed by grafx_render_backward on the same workspace (with_backward = 1), for
+ * signals of length (row stride) T. The workspace holds what the Process step of Algorithm 1
+ * derives from the parameters P (EQ and delay filter designs, Eqs. 4 and 14), the compressor
+ * chunk states of Eq. 8, and, for the adjoint, the per-tile parameter-gradient partials. Its
+ * size depends only on the schedule's node counts and on T; the caller allocates it (the
+ * library never allocates device memory). Errors: GRAFX_E_ARG (NULL argument), GRAFX_E_SHAPE
+ * (T < 1).
+ */
 grafx_status grafx_workspace_bytes(const grafx_schedule_t* sched, int64_t T,
                                    int32_t with_backward, size_t* bytes);
 
@@ -267,20 +300,50 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* sched, const voi
                                         size_t ws_bytes, int32_t step, hipStream_t stream);
 
 /*
- * Tuning settings of a schedule (chosen by a caller-side autotuner from measured step times).
- * They change which threads and blocks share the work, hence the grouping of the per-block
- * parameter-gradient partial sums (results stay within the parity tolerances; each setting is
- * deterministic), never the per-sample arithmetic or the workspace size.
+ * Settings of a schedule. The tuning knobs are chosen by a caller-side autotuner from measured
+ * step times (the paper picks its batching per graph on the host, Sec. 2 "Implementation
+ * details"; these settings pick launch shapes the same way). A tuning knob changes which threads
+ * and blocks share the work, hence the grouping of the per-block parameter-gradient partial sums
+ * (results stay within the parity tolerances; each setting is deterministic), never the
+ * per-sample arithmetic or the workspace size.
  *   GRAFX_TUNE_POINTWISE_UNROLL: 1024-sample parts per block of the pointwise kernels (mix, out,
- *   gain_pan, imager, tanh): 1 (default), 2 or 4.
- * grafx_schedule_set_tuning: E_ARG for a NULL schedule, an unknown knob or a value not listed.
+ *     gain_pan, imager, tanh): 1 (default), 2 or 4.
+ * Two settings bound the iterative parts of the dynamics kernels instead:
+ *   GRAFX_TUNE_AR_MAX_PASSES: branch-pattern passes of the attack/release compressor's forward
+ *     (Eq. 8 with distinct coefficients) before a chunk that has not settled falls back to the
+ *     serial recursion, 1..16 (default 16). Every value gives the exact recursion; a small value
+ *     sends more chunks to the fallback.
+ *   GRAFX_TUNE_WAIT_POLLS: polls of a published chunk state that a dynamics block makes before
+ *     it gives up waiting, 0..2^30 (default 2^24, far beyond any wait a completing launch
+ *     needs). A wait that gives up sets bit 0 of the workspace's error word
+ *     (grafx_workspace_error) and poisons its result with NaN; the kernel still exits normally.
+ *     0 makes every wait give up at once (a test of that path from the host).
+ * grafx_schedule_set_tuning: E_ARG for a NULL schedule, an unknown knob or a value out of range.
  * A setting applies to every later call with the schedule; calls that overlap with a change on
- * another thread are not synchronised with it.
+ * another thread are not synchronised with it. A HIP graph captured from render calls keeps the
+ * settings in force at capture time.
  */
-enum { GRAFX_TUNE_POINTWISE_UNROLL = 0 };
+enum { GRAFX_TUNE_POINTWISE_UNROLL = 0, GRAFX_TUNE_AR_MAX_PASSES = 1, GRAFX_TUNE_WAIT_POLLS = 2 };
 grafx_status grafx_schedule_set_tuning(grafx_schedule_t* sched, int32_t knob, int32_t value);
 grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* sched, int32_t knob,
                                        int32_t* value);
+
+/*
+ * grafx_workspace_error -- the error word of the dynamics kernels (compressor, noisegate,
+ * compressor_ar; the chunked scan of Eq. 8) in a render workspace: enqueues on `stream` a copy of
+ * the 32-bit word into `word` (host or device memory; read it after the stream has completed).
+ *   bit 0  a chunk wait gave up (GRAFX_TUNE_WAIT_POLLS): the affected outputs are NaN
+ *   bit 1  a dynamics kernel found its chunk tickets not reset and did nothing (only possible if
+ *          a caller ran kernels on a workspace outside the render calls' order)
+ * grafx_render and grafx_render_step clear the word before their first dynamics launch;
+ * grafx_render_backward and grafx_render_backward_step add their own bits to it, so after a
+ * render and its adjoint the word reports both. A schedule without dynamics nodes reports 0.
+ *   T, ws, ws_bytes   as passed to the render calls (ws_bytes >= the forward workspace size)
+ * Errors: GRAFX_E_ARG (NULL argument), GRAFX_E_SHAPE (T out of range, misaligned workspace),
+ * GRAFX_E_WORKSPACE (workspace too small), GRAFX_E_HIP (the copy could not be enqueued).
+ */
+grafx_status grafx_workspace_error(const grafx_schedule_t* sched, int64_t T, const void* ws,
+                                   size_t ws_bytes, uint32_t* word, hipStream_t stream);
 
 /*
  * Multi-resolution STFT loss between two sets of stereo signals (the loss of the paper's
@@ -361,7 +424,12 @@ grafx_status grafx_adam(int64_t n, float* p, const float* g, float* m, float* v,
 grafx_status grafx_encoder_params(int32_t batch, const float* out, float* gain_pan, float* eq,
                                   float* comp, hipStream_t stream);
 
-/* Message of the last failed call on this thread ("" if none). */
+/*
+ * grafx_last_error -- message of the last failed call on the calling thread ("" if the last
+ * call succeeded). Every entry point clears it on entry and sets it with the status it returns,
+ * so the message always names the check that failed (the error model of the boundary; the paper
+ * has no error model of its own). The string stays valid until the thread's next call.
+ */
 const char* grafx_last_error(void);
 
 #ifdef __cplusplus

@@ -24,7 +24,7 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_mrstft_backward", "grafx_logmel", "grafx_encoder_gather",
            "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
            "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
-           "grafx_set_schedule_threads", "grafx_last_error")
+           "grafx_set_schedule_threads", "grafx_workspace_error", "grafx_last_error")
 
 
 class GrafxError(RuntimeError):
@@ -88,6 +88,7 @@ def load() -> ctypes.CDLL:
         "grafx_encoder_params": (i32, [i32, vp, vp, vp, vp, vp]),
         "grafx_schedule_set_tuning": (i32, [vp, i32, i32]),
         "grafx_schedule_get_tuning": (i32, [vp, i32, c_i32p]),
+        "grafx_workspace_error": (i32, [vp, i64, vp, sz, vp, vp]),
         "grafx_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -102,6 +102,8 @@ class Schedule:
         return self._plans[device]
 
     TUNE_POINTWISE_UNROLL = 0
+    TUNE_AR_MAX_PASSES = 1
+    TUNE_WAIT_POLLS = 2
 
     def set_tuning(self, knob: int, value: int) -> None:
         """A tuning setting of the schedule (see include/grafx.h, grafx_schedule_set_tuning)."""
@@ -288,6 +290,14 @@ class RenderBuffers:
                                        _ptrs(_param_list(self.sched, P)), self.U.data_ptr(),
                                        self.ws.data_ptr(), self.ws.numel(), n,
                                        _stream(self.device)))
+
+    def error_word(self) -> int:
+        """The dynamics kernels' error word of this workspace (bit 0: a chunk wait gave up, bit 1:
+        tickets were not reset); waits for the current stream."""
+        w = torch.zeros((), dtype=torch.int32, device=self.device)
+        check(load().grafx_workspace_error(self.sched._h, self.T, self.ws.data_ptr(),
+                                           self.ws.numel(), w.data_ptr(), _stream(self.device)))
+        return int(w.item()) & 0xFFFFFFFF
 
     def backward_step(self, S, P, dY, n: int):
         check(load().grafx_render_backward_step(

@@ -27,6 +27,7 @@ struct GraphView {
   int32_t out_begin;         // sigma position of the first output node
   int32_t vec4;              // T and every node length are multiples of 4 (16-byte vectors)
   int32_t pw_unroll;         // pointwise kernels: 1024-sample parts per block (1, 2 or 4)
+  int32_t wait_polls;        // dynamics kernels: reads of a published chunk state before giving up
 };
 
 // Length of the signal of the node at sigma position v (its row holds valid samples [0, len)).

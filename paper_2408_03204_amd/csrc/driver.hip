@@ -2,7 +2,6 @@
 // of its adjoint, the plan upload and the workspace layout. Every argument is checked before the
 // first launch; the drivers only enqueue kernels on the caller's stream.
 #include <algorithm>
-#include <cstdlib>
 #include <cstring>
 
 #include "device_common.h"
@@ -37,14 +36,6 @@ int dyn_row(const grafx_schedule_t* h, int t) {
 // (A, B) of every chunk.
 size_t ar_slot_words(size_t chunks) { return (size_t)kArPasses * chunks * 3 + chunks * 2; }
 
-// Most branch-pattern passes of the attack/release forward before the serial fallback
-// (GRAFX_AR_MAX_PASSES, 1..kArPasses; a small value exercises the fallback).
-int ar_max_pass() {
-  const char* e = std::getenv("GRAFX_AR_MAX_PASSES");
-  const int v = e ? std::atoi(e) : kArPasses;
-  return std::min(std::max(v, 1), kArPasses);
-}
-
 WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   WsLayout L{};
   size_t off = 0;
@@ -57,9 +48,9 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   L.eq_H = take(n_eq * kEqFFT * sizeof(float));
   L.comp_agg = take(n_comp * chunks * sizeof(uint64_t));
   L.comp_carry = take(n_comp * chunks * sizeof(double));
-  // one ticket counter per dynamics node (forward), one per node (adjoint), each on its own
-  // cache line, then the error word
-  L.comp_tickets = take((2 * n_comp * kCompTicketStride + 1) * sizeof(unsigned));
+  // the error word on a cache line of its own, then one ticket counter per dynamics node
+  // (forward) and one per node (adjoint), each on its own cache line
+  L.comp_tickets = take((1 + 2 * n_comp) * kCompTicketStride * sizeof(unsigned));
   L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
   L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
   // attack/release compressors: per-pass and final chunk maps (reset), entering states and final
@@ -113,6 +104,7 @@ GraphView make_view(const grafx_schedule_t* h, const void* dev_plan, int64_t T, 
   g.out_begin = h->step_ptr[h->N];
   g.vec4 = (T % 4 == 0) && h->len4;
   g.pw_unroll = h->pw_unroll;
+  g.wait_polls = h->wait_polls;
   return g;
 }
 
@@ -142,24 +134,31 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
   return GRAFX_OK;
 }
 
-unsigned* tickets(void* ws, const WsLayout& L, const grafx_schedule_t* h, bool bwd) {
-  return at<unsigned>(ws, L.comp_tickets) + (bwd ? (size_t)n_dynamics(h) * kCompTicketStride : 0);
-}
+unsigned* error_word(void* ws, const WsLayout& L) { return at<unsigned>(ws, L.comp_tickets); }
 
-unsigned* error_word(void* ws, const WsLayout& L, const grafx_schedule_t* h) {
-  return at<unsigned>(ws, L.comp_tickets) + (size_t)2 * n_dynamics(h) * kCompTicketStride;
+unsigned* tickets(void* ws, const WsLayout& L, const grafx_schedule_t* h, bool bwd) {
+  return error_word(ws, L) +
+         (size_t)(1 + (bwd ? n_dynamics(h) : 0)) * kCompTicketStride;
 }
 
 bool is_dynamics(int t) { return t == GRAFX_COMPRESSOR || t == GRAFX_NOISEGATE; }
+bool has_dynamics(const grafx_schedule_t* h) {
+  return n_dynamics(h) + h->type_count[GRAFX_COMPRESSOR_AR] > 0;
+}
 
 // Reset the dynamics chaining state of one pass (all compressor and noisegate nodes, all steps).
+// The forward reset also clears the error word, which sits just before the forward tickets; it
+// runs whenever the graph has any dynamics node (attack/release compressors included).
 hipError_t reset_comp(const grafx_schedule_t* h, void* ws, const WsLayout& L, bool bwd,
                       int64_t T, hipStream_t stream) {
   const int n_comp = n_dynamics(h);
-  if (n_comp == 0) return hipSuccess;
+  if (!has_dynamics(h) || (bwd && n_comp == 0)) return hipSuccess;
   uint64_t* tot = at<uint64_t>(ws, bwd ? L.comp_ragg : L.comp_agg);
-  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, bwd),
-                           n_comp * kCompTicketStride, stream);
+  if (bwd)
+    return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), tickets(ws, L, h, true),
+                             n_comp * kCompTicketStride, stream);
+  return launch_comp_reset(tot, (int64_t)n_comp * comp_chunks(T), error_word(ws, L),
+                           (1 + n_comp) * kCompTicketStride, stream);
 }
 
 // Reset the attack/release chaining state of one pass.
@@ -196,17 +195,17 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_comp_fwd(g, U, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
                              at<uint64_t>(ws, L.comp_agg),
                              at<double>(ws, L.comp_carry), tickets(ws, L, h, false),
-                             error_word(ws, L, h), stream);
+                             error_word(ws, L), stream);
     case GRAFX_DELAY:
       return launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
                               cnt, stream);
     case GRAFX_COMPRESSOR_AR: {
       const size_t n_ar = h->type_count[GRAFX_COMPRESSOR_AR], chunks = comp_chunks(g.T);
       uint64_t* slots = at<uint64_t>(ws, L.ar_slots);
-      return launch_comp_ar_fwd(g, U, p, b, cnt, ar_max_pass(), slots,
+      return launch_comp_ar_fwd(g, U, p, b, cnt, h->ar_max_pass, slots,
                                 slots + n_ar * (size_t)kArPasses * chunks * 3,
                                 at<double>(ws, L.ar_carry), at<uint16_t>(ws, L.ar_pat),
-                                at<unsigned>(ws, L.ar_tickets), error_word(ws, L, h), stream);
+                                at<unsigned>(ws, L.ar_tickets), error_word(ws, L), stream);
     }
     default:
       return hipErrorInvalidValue;
@@ -235,7 +234,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_comp_bwd(g, dU, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
                              at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
-                             tickets(ws, L, h, true), error_word(ws, L, h), stream);
+                             tickets(ws, L, h, true), error_word(ws, L), stream);
     case GRAFX_DELAY:
       return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
                               b, cnt, at<float>(ws, L.delay_part), stream);
@@ -245,7 +244,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
                                 at<double>(ws, L.ar_part),
                                 at<unsigned>(ws, L.ar_tickets) +
                                     (size_t)h->type_count[GRAFX_COMPRESSOR_AR] * kCompTicketStride,
-                                error_word(ws, L, h), stream);
+                                error_word(ws, L), stream);
     default:
       return hipErrorInvalidValue;
   }
@@ -367,8 +366,9 @@ grafx_status grafx_render_step(const grafx_schedule_t* h, const void* dev_plan, 
   const WsLayout L = ws_layout(h, T, false);
   const GraphView g = make_view(h, dev_plan, T, S, U);
   hipError_t e = hipSuccess;
-  if (is_dynamics(h->step_type[step])) e = reset_comp(h, ws, L, false, T, stream);
-  if (h->step_type[step] == GRAFX_COMPRESSOR_AR) e = reset_ar(h, ws, L, false, T, stream);
+  const bool ar = h->step_type[step] == GRAFX_COMPRESSOR_AR;
+  if (is_dynamics(h->step_type[step]) || ar) e = reset_comp(h, ws, L, false, T, stream);
+  if (e == hipSuccess && ar) e = reset_ar(h, ws, L, false, T, stream);
   if (e == hipSuccess) e = enqueue_fwd_step(h, g, P, U, ws, L, step, stream);
   return hip_status(e, "render_step launch");
 }
@@ -388,7 +388,8 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* d
   g.dU = dU;
   hipError_t e = hipSuccess;
   if (is_dynamics(h->step_type[step])) e = reset_comp(h, ws, L, true, T, stream);
-  if (h->step_type[step] == GRAFX_COMPRESSOR_AR) e = reset_ar(h, ws, L, true, T, stream);
+  if (e == hipSuccess && h->step_type[step] == GRAFX_COMPRESSOR_AR)
+    e = reset_ar(h, ws, L, true, T, stream);
   if (e == hipSuccess) e = enqueue_bwd_step(h, g, P, dU, ws, L, step, stream);
   return hip_status(e, "render_backward_step launch");
 }
@@ -396,19 +397,53 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* h, const void* d
 grafx_status grafx_schedule_set_tuning(grafx_schedule_t* h, int32_t knob, int32_t value) {
   clear_error();
   if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
-  if (knob != GRAFX_TUNE_POINTWISE_UNROLL) return fail(GRAFX_E_ARG, "unknown tuning knob");
-  if (value != 1 && value != 2 && value != 4)
-    return fail(GRAFX_E_ARG, "pointwise unroll must be 1, 2 or 4");
-  h->pw_unroll = value;
-  return GRAFX_OK;
+  switch (knob) {
+    case GRAFX_TUNE_POINTWISE_UNROLL:
+      if (value != 1 && value != 2 && value != 4)
+        return fail(GRAFX_E_ARG, "pointwise unroll must be 1, 2 or 4");
+      h->pw_unroll = value;
+      return GRAFX_OK;
+    case GRAFX_TUNE_AR_MAX_PASSES:
+      if (value < 1 || value > kArPasses)
+        return fail(GRAFX_E_ARG, "attack/release passes must be in 1.." + std::to_string(kArPasses));
+      h->ar_max_pass = value;
+      return GRAFX_OK;
+    case GRAFX_TUNE_WAIT_POLLS:
+      if (value < 0 || value > (1 << 30)) return fail(GRAFX_E_ARG, "wait polls must be in 0..2^30");
+      h->wait_polls = value;
+      return GRAFX_OK;
+    default:
+      return fail(GRAFX_E_ARG, "unknown tuning knob");
+  }
 }
 
 grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* h, int32_t knob, int32_t* value) {
   clear_error();
   if (!h || !value) return fail(GRAFX_E_ARG, "NULL argument");
-  if (knob != GRAFX_TUNE_POINTWISE_UNROLL) return fail(GRAFX_E_ARG, "unknown tuning knob");
-  *value = h->pw_unroll;
-  return GRAFX_OK;
+  switch (knob) {
+    case GRAFX_TUNE_POINTWISE_UNROLL: *value = h->pw_unroll; return GRAFX_OK;
+    case GRAFX_TUNE_AR_MAX_PASSES: *value = h->ar_max_pass; return GRAFX_OK;
+    case GRAFX_TUNE_WAIT_POLLS: *value = h->wait_polls; return GRAFX_OK;
+    default: return fail(GRAFX_E_ARG, "unknown tuning knob");
+  }
+}
+
+grafx_status grafx_workspace_error(const grafx_schedule_t* h, int64_t T, const void* ws,
+                                   size_t ws_bytes, uint32_t* word, hipStream_t stream) {
+  clear_error();
+  if (!h || !ws || !word) return fail(GRAFX_E_ARG, "NULL argument");
+  if (T < 1 || T >= ((int64_t)1 << 29)) return fail(GRAFX_E_SHAPE, "T must be in [1, 2^29)");
+  if (!aligned(ws, 256)) return fail(GRAFX_E_SHAPE, "workspace must be 256-byte aligned");
+  const WsLayout L = ws_layout(h, T, false);
+  if (ws_bytes < L.fwd_end)
+    return fail(GRAFX_E_WORKSPACE, "workspace too small: need " + std::to_string(L.fwd_end) +
+                                       " bytes, got " + std::to_string(ws_bytes));
+  static const uint32_t kZero = 0;
+  const void* src = has_dynamics(h) ? static_cast<const void*>(
+                                          error_word(const_cast<void*>(ws), L))
+                                    : static_cast<const void*>(&kZero);
+  return hip_status(hipMemcpyAsync(word, src, sizeof(uint32_t), hipMemcpyDefault, stream),
+                    "error word copy");
 }
 
 grafx_status grafx_mrstft_workspace_bytes(int32_t rows, int64_t T, size_t* bytes) {

@@ -14,7 +14,6 @@ constexpr int kPer = 12;
 constexpr int kChunk = kCompChunk;  // 256 x kPer
 constexpr double kEps = 1e-8;
 constexpr uint64_t kNotReady = ~0ull;
-constexpr int kMaxSpin = 1 << 24;
 
 // Coefficient structs passed to the curves provide thr (T), knee (W), c = 1/R - 1 and
 // g1 = 1 - R, inv2w = 1/(2W), inv4w = 1/(4W) (0 for a hard knee) and invR2 = 1/R^2.
@@ -101,16 +100,16 @@ __device__ __forceinline__ void publish(uint64_t* slot, double v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double await_total(uint64_t* slot, unsigned* err) {
-  for (int spin = 0;; ++spin) {
+// Wait for a published total: at most `polls` reads of the slot (0: give up at once). A wait
+// that gives up sets bit 0 of the error word and returns NaN, so the kernel still ends normally.
+__device__ __forceinline__ double await_total(uint64_t* slot, unsigned* err, int polls) {
+  for (int spin = 0; spin < polls; ++spin) {
     const uint64_t x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (x != kNotReady) return __longlong_as_double((long long)x);
-    if (spin >= kMaxSpin) {  // never expected: poison the result instead of spinning on
-      atomicOr(err, 1u);
-      return __longlong_as_double(0x7FF8000000000001ll);
-    }
     __builtin_amdgcn_s_sleep(1);
   }
+  atomicOr(err, 1u);
+  return __longlong_as_double(0x7FF8000000000001ll);
 }
 
 // ---- staging -----------------------------------------------------------------------------------

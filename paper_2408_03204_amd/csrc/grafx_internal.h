@@ -30,7 +30,7 @@ struct PlanLayout {
 }  // namespace grafx
 
 // The schedule handle (host memory only). Its graph and plan are immutable after creation; only
-// the tuning settings (grafx_schedule_set_tuning) change.
+// the settings (grafx_schedule_set_tuning) change.
 struct grafx_schedule_t {
   int32_t V = 0, E = 0, N = 0, K = 0, n_out = 0;
   int32_t type_count[grafx::kNumTypes] = {0};
@@ -47,6 +47,8 @@ struct grafx_schedule_t {
   int32_t max_len = 0;             // largest node length (0 when uniform)
   bool len4 = true;                // every node length is a multiple of 4
   int32_t pw_unroll = 1;           // tuning: pointwise 1024-sample parts per block
+  int32_t ar_max_pass = 16;        // attack/release forward: branch-pattern passes (1..16)
+  int32_t wait_polls = 1 << 24;    // dynamics kernels: polls of a chunk wait before giving up
   grafx::PlanLayout layout{};
   std::vector<int32_t> plan;       // packed host image of the device plan
 };

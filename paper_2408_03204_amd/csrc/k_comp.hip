@@ -53,7 +53,7 @@ struct Coef {
   float inv2w, inv4w; // 1/(2W), 1/(4W)
   float invR2;        // 1/R^2
   double pw[9];       // pw[d] = (a^kPer)^(2^d); pw[8] = a^kChunk
-  double logA;        // ln(a^kChunk)
+  double logA;        // ln(a^kChunk), -inf for a = 0
 };
 
 __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ Coef load_coef(const float* P, int slot) {
   k.inv2w = k.knee > 0.f ? 1.0f / (2.f * k.knee) : 0.f;
   k.inv4w = k.knee > 0.f ? 1.0f / (4.f * k.knee) : 0.f;
   k.invR2 = 1.0f / (R * R);
-  k.logA = (double)kChunk * log(k.a);
+  k.logA = (double)kChunk * log(fabs(k.a));  // a^kChunk = |a|^kChunk: kChunk is even
   double q = 1.0, b = k.a;  // a^kPer by binary powering
   for (int e = kPer; e > 0; e >>= 1) {
     if (e & 1) q *= b;
@@ -132,17 +132,22 @@ __device__ __forceinline__ int scan_index(bool rev) {
 }
 
 // Entering state of chunk k: fixed-order block-wide sum over the published totals of the
-// chunks before it (REV: after it), weighted by A^(distance - 1).
+// chunks before it (REV: after it), weighted by A^(distance - 1). The adjacent chunk's weight is
+// exactly 1, so a = 0 (A = 0, logA = -inf) gives the plain recursion's carry without 0 * inf.
+__device__ __forceinline__ double carry_weight(int dist, const Coef& c) {
+  return dist == 0 ? 1.0 : exp((double)dist * c.logA);
+}
+
 template <bool REV>
 __device__ __forceinline__ double chunk_carry(uint64_t* tot, int k, int chunks, const Coef& c,
-                                              unsigned* err, double* red) {
+                                              unsigned* err, int polls, double* red) {
   double s = 0.0;
   if (!REV) {
     for (int j = threadIdx.x; j < k; j += kBlock)
-      s += await_total(tot + j, err) * exp((double)(k - 1 - j) * c.logA);
+      s += await_total(tot + j, err, polls) * carry_weight(k - 1 - j, c);
   } else {
     for (int j = k + 1 + threadIdx.x; j < chunks; j += kBlock)
-      s += await_total(tot + j, err) * exp((double)(j - k - 1) * c.logA);
+      s += await_total(tot + j, err, polls) * carry_weight(j - k - 1, c);
   }
   return block_sum<double>(s, red);
 }
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
   const double E0 = chunk_scan<false>(B, k, wtot, total);
   uint64_t* tots = agg + (int64_t)ws * chunks;
   if (threadIdx.x == 0) publish(tots + chunk, total);
-  const double cin = chunk_carry<false>(tots, chunk, chunks, k, err, red);
+  const double cin = chunk_carry<false>(tots, chunk, chunks, k, err, g.wait_polls, red);
   if (threadIdx.x == 0) carry[(int64_t)ws * chunks + chunk] = cin;
   double s = fma(pow_a8(k, scan_index(false)), cin, E0);
 #pragma unroll
@@ -271,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   const double L0 = chunk_scan<true>(R, k, wtot, rtotal);
   uint64_t* rtots = ragg + (int64_t)ws * chunks;
   if (threadIdx.x == 0) publish(rtots + chunk, rtotal);
-  const double rin = chunk_carry<true>(rtots, chunk, chunks_n, k, err, red);  // own chunks
+  const double rin = chunk_carry<true>(rtots, chunk, chunks_n, k, err, g.wait_polls, red);  // own chunks
   double lam = fma(pow_a8(k, scan_index(true)), rin, L0);
   double accA = 0.0;
 #pragma unroll

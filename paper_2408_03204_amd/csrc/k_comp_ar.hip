@@ -132,13 +132,13 @@ __device__ __forceinline__ Aff aff_scan(Aff f, Aff* wtot, Aff& total) {
 // the state it gives from a zero start.
 template <bool FWD>
 __device__ __forceinline__ double fold_maps(uint64_t* base, int stride, int n, unsigned* err,
-                                            Aff* wtot) {
+                                            int polls, Aff* wtot) {
   const int per = (n + kBlock - 1) / kBlock;
   const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
   Aff m = {1.0, 0.0};
   for (int r = lo; r < hi; ++r) {
     uint64_t* w = base + (int64_t)(FWD ? r : n - 1 - r) * stride;
-    const Aff o = {await_total(w, err), await_total(w + 1, err)};
+    const Aff o = {await_total(w, err, polls), await_total(w + 1, err, polls)};
     m = after(o, m);
   }
   Aff total;
@@ -149,15 +149,15 @@ __device__ __forceinline__ double fold_maps(uint64_t* base, int stride, int n, u
 // fold_maps<true> over the pass rows (A, B, flag) of the chunks before `chunk`, which also
 // returns in `all` whether `own` and every earlier chunk's flag are set (block-uniform).
 __device__ __forceinline__ double fold_maps_flags(uint64_t* row, int chunk, unsigned* err,
-                                                  Aff* wtot, bool own, bool& all) {
+                                                  int polls, Aff* wtot, bool own, bool& all) {
   const int per = (chunk + kBlock - 1) / kBlock;
   const int lo = min(chunk, (int)threadIdx.x * per), hi = min(chunk, lo + per);
   Aff m = {1.0, 0.0};
   bool ok = own;
   for (int r = lo; r < hi; ++r) {
     uint64_t* w = row + (int64_t)r * 3;
-    const Aff o = {await_total(w, err), await_total(w + 1, err)};
-    ok = ok && await_total(w + 2, err) == 1.0;
+    const Aff o = {await_total(w, err, polls), await_total(w + 1, err, polls)};
+    ok = ok && await_total(w + 2, err, polls) == 1.0;
     m = after(o, m);
   }
   all = __syncthreads_and(ok) != 0;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
       publish(row + (int64_t)chunk * 3 + 2, same ? 1.0 : 0.0);
     }
     bool all_same;
-    cin = fold_maps_flags(row, chunk, err, wtot, same, all_same);
+    cin = fold_maps_flags(row, chunk, err, g.wait_polls, wtot, same, all_same);
     if (all_same) {  // the pattern of this pass is exact up to the chunk's end, and so is cin
       done = true;
       for (int q = pass + 1 + (int)threadIdx.x; q < max_pass; q += kBlock) {
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
     }
   }
   if (!done) {  // serial fallback from the exact entering state
-    cin = fold_maps<true>(fn, 2, chunk, err, wtot);
+    cin = fold_maps<true>(fn, 2, chunk, err, g.wait_polls, wtot);
     if (threadIdx.x == 0) {
       double s = cin;
       for (int j = 0; j < kBlock; ++j) {
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_bwd_kernel(
   }
   // maps of the later chunks of this node, the last one first
   const double rin = fold_maps<false>(rn + (int64_t)(chunk + 1) * 2, 2, chunks_n - 1 - chunk, err,
-                                      wtot);
+                                      g.wait_polls, wtot);
   double mu = fma(rex.A, rin, rex.B);
   double accAa = 0.0, accAr = 0.0;
 #pragma unroll

@@ -2,7 +2,7 @@
 
 Kernel durations (from a `--kernel-trace --stats` run):
 
-    python -m paper_2408_03204_amd.rocprof_summary trace <run_results.db> <command...>
+    python rocprof_summary.py trace <run_results.db> <command...>
 
 HBM traffic per kernel from two PMC runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`) of a
 program that first copies `copy_mib` MiB device-to-device: each counter is scaled by
@@ -10,7 +10,7 @@ program that first copies `copy_mib` MiB device-to-device: each counter is scale
 step-kernel type to a JSON file keyed "<dir>:<type>:<workload>", with the SHA-256 of the kernel's
 source so the figure is only used while that source is unchanged:
 
-    python -m paper_2408_03204_amd.rocprof_summary pmc <fetch.db> <write.db> <copy_mib> \\
+    python rocprof_summary.py pmc <fetch.db> <write.db> <copy_mib> \\
         <steps> <kernel substring> <key> <source file> <json out> <command...>
 """
 from __future__ import annotations

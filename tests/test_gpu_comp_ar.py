@@ -2,9 +2,8 @@
 against the FP64 oracle's literal per-sample loop, forward and adjoint. The kernel iterates on
 the attack/release branch pattern and falls back to a serial recursion for any chunk that has
 not settled after a given number of passes; GRAFX_AR_MAX_PASSES lowers that number so that the
-fallback runs (1 pass: almost every chunk falls back; 2-3: some do)."""
-import os
-
+fallback runs (1 pass: almost every chunk falls back; 2-3: some do). That number is the
+schedule's GRAFX_TUNE_AR_MAX_PASSES setting, set here through the C ABI."""
 import numpy as np
 import pytest
 import torch
@@ -40,26 +39,15 @@ def ar_workload(T, seed, attack_ms, release_ms):
                           P, None, T, seed)
 
 
-class max_passes:
-    """Set GRAFX_AR_MAX_PASSES for the calls inside the block (read by the library per call)."""
-
-    def __init__(self, n):
-        self.n = n
-
-    def __enter__(self):
-        self.old = os.environ.get("GRAFX_AR_MAX_PASSES")
-        if self.n is not None:
-            os.environ["GRAFX_AR_MAX_PASSES"] = str(self.n)
-
-    def __exit__(self, *a):
-        if self.old is None:
-            os.environ.pop("GRAFX_AR_MAX_PASSES", None)
-        else:
-            os.environ["GRAFX_AR_MAX_PASSES"] = self.old
-
-
-def run_forward(w):
+def make_schedule(w, passes=None):
     sched = Schedule(w.graph.node_type, w.graph.edges)
+    if passes is not None:
+        sched.set_tuning(Schedule.TUNE_AR_MAX_PASSES, passes)
+    return sched
+
+
+def run_forward(w, passes=None):
+    sched = make_schedule(w, passes)
     S, P = device_inputs(w)
     Y, U = render(sched, S, P, return_U=True)
     torch.cuda.synchronize()
@@ -67,8 +55,8 @@ def run_forward(w):
     return Y
 
 
-def run_backward(w, seed):
-    sched = Schedule(w.graph.node_type, w.graph.edges)
+def run_backward(w, seed, passes=None):
+    sched = make_schedule(w, passes)
     S, P = device_inputs(w)
     S.requires_grad_(True)
     for p in P.values():
@@ -110,9 +98,8 @@ def test_comp_ar_serial_fallback(passes):
     within tolerance of the oracle, forward and adjoint."""
     T = T_RAGGED[1]
     say(f"[comp_ar fallback] max passes {passes} T={T}")
-    with max_passes(passes):
-        run_forward(ar_workload(T, 55, 2.0, 60.0))
-        errs = run_backward(ar_workload(T, 57, 70.0, 2.0), 9)
+    run_forward(ar_workload(T, 55, 2.0, 60.0), passes)
+    errs = run_backward(ar_workload(T, 57, 70.0, 2.0), 9, passes)
     say("   grad errs", errs)
     for k, e in errs.items():
         assert e <= GRAD_TOL, (k, e)

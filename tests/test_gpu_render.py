@@ -146,3 +146,24 @@ def test_tiny_console_backward():
     say("   grad errs", errs)
     for k, e in errs.items():
         assert e <= GRAD_TOL, (k, e)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.999999])
+def test_compressor_alpha_edge_values(a):
+    """alpha at the ends of its domain [0, 1): 0 (no smoothing, g = x) and a time constant of
+    about 23 s, across several 3072-sample chunks, forward and adjoint against the oracle. With
+    a = 0 the chunk carry weights A^d (A = a^3072) must be 1 for the adjacent chunk and 0 beyond;
+    near 1 every earlier chunk's total reaches the carry."""
+    T = 5 * 3072 + 77
+    say(f"[compressor alpha={a}] T={T}")
+    w = single_node_workload(synth.COMP, T, 41)
+    w.params[synth.COMP][:, 0] = a
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    S, P = device_inputs(w)
+    Y, U = render(sched, S, P, return_U=True)
+    torch.cuda.synchronize()
+    check_render(w, sched, Y, U)
+    errs = run_backward(w, 5)
+    say("   grad errs", errs)
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)

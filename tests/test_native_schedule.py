@@ -137,15 +137,27 @@ def test_tuning_settings():
     w = synth.tiny_console(T=8)
     s = Schedule(w.graph.node_type, w.graph.edges)
     assert s.get_tuning(Schedule.TUNE_POINTWISE_UNROLL) == 1
+    assert s.get_tuning(Schedule.TUNE_AR_MAX_PASSES) == 16
+    assert s.get_tuning(Schedule.TUNE_WAIT_POLLS) == 1 << 24
     before = s.workspace_bytes(3 * 2048 + 5, True)
     for v in (2, 4, 1):
         s.set_tuning(Schedule.TUNE_POINTWISE_UNROLL, v)
         assert s.get_tuning(Schedule.TUNE_POINTWISE_UNROLL) == v
         assert s.workspace_bytes(3 * 2048 + 5, True) == before  # sized for every setting
-    for knob, v in ((0, 3), (0, 0), (7, 1)):
+    for v in (1, 7, 16):
+        s.set_tuning(Schedule.TUNE_AR_MAX_PASSES, v)
+        assert s.get_tuning(Schedule.TUNE_AR_MAX_PASSES) == v
+    for v in (0, 1, 1 << 30):
+        s.set_tuning(Schedule.TUNE_WAIT_POLLS, v)
+        assert s.get_tuning(Schedule.TUNE_WAIT_POLLS) == v
+    assert s.workspace_bytes(3 * 2048 + 5, True) == before
+    for knob, v in ((0, 3), (0, 0), (7, 1), (1, 0), (1, 17), (2, -1), (2, (1 << 30) + 1)):
         with pytest.raises(GrafxError) as e:
             s.set_tuning(knob, v)
         assert e.value.status == "GRAFX_E_ARG"
+    # a refused setting leaves the previous one in force
+    assert s.get_tuning(Schedule.TUNE_AR_MAX_PASSES) == 16
+    assert s.get_tuning(Schedule.TUNE_WAIT_POLLS) == 1 << 30
 
 
 FIELDS = ("step_type", "step_ptr", "perm", "in_ptr", "in_src", "out_ptr", "out_dst", "param_row")
