@@ -1,14 +1,18 @@
-"""Benchmark: node-samples/s of one gradient step of the mixing-console graph on one MI355X.
+"""Benchmark: node-samples/s of one gradient step of a mixing-console graph on one MI355X.
 
-A step is the whole hot path on one batch: the batched forward render of the graph (64 stereo
-tracks, T = 2^18, ~220 nodes), the 3-resolution STFT loss against a target mix rendered with
-hidden parameters, the loss adjoint and the render adjoint down to every processor parameter.
-Throughput = processed (non-input) nodes x T / step time, with every input already resident in
-HBM. All inputs are seeded synthetic stand-ins for the paper's consoles.
+A step is the whole hot path on one batch: the batched forward render of the graph, the
+3-resolution STFT loss against a target mix rendered with hidden parameters, the loss adjoint
+and the render adjoint down to every processor parameter. The default workload is the largest
+single-GPU one, the 256-track console (bus tree 32 -> 8 -> 2 -> master, 904 nodes, T = 2^20);
+`--workload console` is the 64-track console at T = 2^18. Throughput = processed (non-input)
+nodes x T / step time, with every input already resident in HBM. All inputs are seeded
+synthetic stand-ins for the paper's consoles.
 
 Prints one JSON line with, besides the metric, the HBM roofline of the dominant step kernel
-(algorithmic bytes / its event-timed duration, measured here) and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+(its algorithmic bytes per launch / its event-timed launch duration, measured here, against
+8 TB/s; for the FFT- and FIR-bound kernels also their flop rate against the FP32 vector issue
+rate as a second view) and the FP64 CPU oracle timed on a bounded sample of the same workload
+with one thread and with every host thread.
 
 The timed step is issued as one HIP-graph replay of the whole step (default: `--mode graph`,
 captured once from the same C-ABI calls); `--mode eager` issues those calls one by one and
@@ -34,7 +38,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32; unpacked issue is half of it)
+# MI355X FP32 vector rate without packed-FP32 instructions (which this build does not emit):
+# 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz; the published 157.3 TFLOP/s counts packed issue
+FP32_VALU_TFLOPS = 78.6
 EQ_FFT = 4096
 WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
              "batch": "batched_graphs", "console_ar": "mixing_console",
@@ -53,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="console", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="beam")
     ap.add_argument("--graphs", type=int, default=128, help="graphs in the batch workload")
     ap.add_argument("--mode", default="graph", choices=("graph", "eager", "autograd"),
@@ -147,13 +153,36 @@ def stored_traffic(kernel_type: str, direction: str, workload: str):
     return None
 
 
-def cpu_baseline(maker, T_full: int, seed_T: int, min_seconds: float = 10.0, max_reps: int = 6):
+CPU_SAMPLE_T = 2 ** 15  # oracle sample length: a few seconds of CPU work per step on any graph
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _timed_reps(fn, min_seconds: float, max_reps: int):
+    reps, t0 = 0, time.perf_counter()
+    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+        fn()
+        reps += 1
+    return reps, time.perf_counter() - t0
+
+
+def cpu_baseline(maker, T_full: int, seed_T: int, min_seconds: float = 8.0, max_reps: int = 6):
     """The FP64 oracle (forward render, MRSTFT loss, autograd backward) on the same graph, as it
-    stands, repeated until about `min_seconds` of CPU work: a bounded sample of the workload."""
+    stands, on a bounded sample of the workload (the graph at length `seed_T`), repeated until
+    about `min_seconds` of CPU work, once with one thread and once with every host thread."""
     import torch
 
     from oracle import mrstft as OM
     from oracle import render as OR
+    threads = len(os.sched_getaffinity(0))
     # one untimed pass on a short signal first (thread pool and FFT plan set-up)
     wu = maker(T=4096)
     Pu = OR.as_params64(wu.params, requires_grad=True)
@@ -162,48 +191,63 @@ def cpu_baseline(maker, T_full: int, seed_T: int, min_seconds: float = 10.0, max
     torch.autograd.grad(Lu, [Pu[t] for t in Pu if Pu[t].shape[0] > 0])
     w = maker(T=seed_T)
     g = w.graph
-    cores = torch.get_num_threads()
     P = OR.as_params64(w.params, requires_grad=True)
     with torch.no_grad():
         tgt = OR.render(g.node_type, g.edges, w.sources, OR.as_params64(w.target_params))
     keys = [t for t in P if P[t].shape[0] > 0]
-    reps, t0 = 0, time.perf_counter()
-    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+
+    def step():
         Y = OR.render(g.node_type, g.edges, w.sources, P)
         L = OM.mrstft(Y, tgt)
         torch.autograd.grad(L, [P[t] for t in keys])
-        reps += 1
-    dt = time.perf_counter() - t0
-    ns = w.processed_nodes * seed_T * reps
+
+    before = torch.get_num_threads()
+    rates = {}
+    for n in (1, threads):
+        torch.set_num_threads(n)
+        reps, dt = _timed_reps(step, min_seconds, max_reps)
+        rates[n] = (w.processed_nodes * seed_T * reps / dt, reps, dt)
+    torch.set_num_threads(before)
     frac = "" if seed_T == T_full else f" (1/{T_full // seed_T} of the benchmark length)"
-    return {"value": ns / dt, "unit": "node-samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{w.name} graph at T={seed_T}{frac}, forward+MRSTFT+backward in float64, "
-                      f"{reps} step(s) in {dt:.1f} s"}
+    v, reps, dt = rates[threads]
+    v1, reps1, dt1 = rates[1]
+    return {"value": round(v, 1), "unit": "node-samples/s", "cores": threads, "kind": "oracle",
+            "single_thread": round(v1, 1), "cpu_model": _cpu_model(),
+            "sample": f"{w.name} graph at T={seed_T}{frac}: forward+MRSTFT+backward in float64 "
+                      f"(torch autograd), {reps} step(s) in {dt:.1f} s on {threads} threads, "
+                      f"{reps1} in {dt1:.1f} s on 1 thread"}
 
 
-
-def cpu_baseline_graph(w, min_seconds: float = 10.0, max_reps: int = 6):
+def cpu_baseline_graph(w, min_seconds: float = 8.0, max_reps: int = 6):
     """The FP64 oracle (forward render and the adjoint of a seeded output adjoint, by autograd) on
-    one graph of the batch at its own T, repeated until about `min_seconds` of CPU work."""
+    one graph of the batch at its own T, repeated until about `min_seconds` of CPU work, with one
+    thread and with every host thread."""
     import torch
 
     from oracle import render as OR
     g = w.graph
-    cores = torch.get_num_threads()
+    threads = len(os.sched_getaffinity(0))
     P = OR.as_params64(w.params, requires_grad=True)
     keys = [t for t in P if P[t].shape[0] > 0]
     dY = torch.as_tensor(np.random.default_rng(1).standard_normal(
         (g.count(1), 2, w.T)), dtype=torch.float64)
-    reps, t0 = 0, time.perf_counter()
-    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+
+    def step():
         Y = OR.render(g.node_type, g.edges, w.sources, P)
         torch.autograd.grad((Y * dY).sum(), [P[t] for t in keys])
-        reps += 1
-    dt = time.perf_counter() - t0
-    return {"value": w.processed_nodes * w.T * reps / dt, "unit": "node-samples/s",
-            "cores": cores, "kind": "oracle",
+
+    before = torch.get_num_threads()
+    rates = {}
+    for n in (1, threads):
+        torch.set_num_threads(n)
+        reps, dt = _timed_reps(step, min_seconds, max_reps)
+        rates[n] = (w.processed_nodes * w.T * reps / dt, reps, dt)
+    torch.set_num_threads(before)
+    v, reps, dt = rates[threads]
+    return {"value": round(v, 1), "unit": "node-samples/s", "cores": threads, "kind": "oracle",
+            "single_thread": round(rates[1][0], 1), "cpu_model": _cpu_model(),
             "sample": f"graph 0 of the batch ({g.num_nodes} nodes, T={w.T}), forward+backward in "
-                      f"float64, {reps} step(s) in {dt:.1f} s"}
+                      f"float64, {reps} step(s) in {dt:.1f} s on {threads} threads"}
 
 
 def _tune(args, sched, S, P) -> dict:
@@ -262,7 +306,7 @@ def setup_console(args, dev):
     return {"sched": sched, "S": S, "P": {t: p.detach() for t, p in P.items()}, "T": w.T,
             "rb": None, "node_samples": w.processed_nodes * w.T, "steps": steps,
             "config": config, "key": args.workload,
-            "cpu": (lambda: cpu_baseline(maker, w.T, w.T))}
+            "cpu": (lambda: cpu_baseline(maker, w.T, min(w.T, CPU_SAMPLE_T)))}
 
 
 def setup_batch(args, dev):
@@ -518,20 +562,24 @@ def main():
             tb[1] += nbytes
             tb[2] += 1
         (d, tname), (t_tot, b_tot, cnt) = max(agg.items(), key=lambda kv: kv[1][0])
-        if tname in ("eq", "delay"):  # FFT / FIR bound: priced against the FP32 vector peak
+        # the dominant step kernel: algorithmic bytes per launch over its average launch time
+        achieved = b_tot / (t_tot * 1e6)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": stored_traffic(tname, d, ctx["key"]),
+                    "kernel": f"{tname} {d}", "launches": cnt,
+                    "algorithmic_bytes_per_launch": round(b_tot / cnt),
+                    "ms_per_launch": round(t_tot / cnt, 5)}
+        if tname in ("eq", "delay"):  # FFT / FIR arithmetic: also its flop rate
             flops = sum(step_flops(sched, r["step"], T, d == "bwd") for r in table
                         if r["dir"] == d and r["type"] == tname)
-            achieved = flops / (t_tot * 1e-3) / 1e12
-            roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4)}
-        else:
-            achieved = b_tot / (t_tot * 1e6)
-            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-        roofline.update({"traffic": stored_traffic(tname, d, ctx["key"]),
-                         "kernel": f"{tname} {d}", "launches": cnt,
-                         "algorithmic_bytes": b_tot, "ms_total": round(t_tot, 4),
-                         "hbm_GBps_at_algorithmic_bytes": round(b_tot / (t_tot * 1e6), 1)})
+            tf = flops / (t_tot * 1e-3) / 1e12
+            roofline["alu_view"] = {
+                "achieved": round(tf, 2), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP32_VALU_TFLOPS, 4),
+                "count": "5 N log2 N flops per 4096-point complex FFT plus the spectral products"
+                         if tname == "eq" else "2 flops per FIR multiply-add",
+                "peak_basis": "FP32 vector issue without packed-FP32 instructions"}
         all_t = sum(v[0] for v in agg.values())
         all_b = sum(v[1] for v in agg.values())
         steps_hbm = {"ms": round(all_t, 4), "GB/s": round(all_b / (all_t * 1e6), 1),

@@ -38,7 +38,7 @@ DELAY_SLOT = 4410  # 100 ms at 44.1 kHz
 DELAY_BINS = 20
 
 # random streams
-S_STRUCT, S_SOURCE, S_PARAM, S_TARGET = 0, 1, 2, 3
+S_STRUCT, S_SOURCE, S_PARAM, S_TARGET, S_ADJOINT = 0, 1, 2, 3, 4
 
 
 def rng_for(seed: int, stream: int, index: int = 0) -> np.random.Generator:
@@ -402,6 +402,12 @@ def large_console(seed=5, T=2 ** 20, n_tracks=256) -> Workload:
                     make_sources(rng_for(seed, S_SOURCE), K, T),
                     draw_params(rng_for(seed, S_PARAM), graph),
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
+
+
+def output_adjoint(seed: int, n_out: int, T: int) -> np.ndarray:
+    """Seeded output adjoint dY [n_out, 2, T] (standard normal, float32) for parity of the
+    render's adjoint: the gradient of sum(dY * Y)."""
+    return rng_for(seed, S_ADJOINT).standard_normal((n_out, 2, T), dtype=np.float32)
 
 
 def batched_graph(seed: int, index: int, T_choices=(2 ** 16, 2 ** 17, 2 ** 18),
