@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import synth
-from gpu_common import GRAD_TOL, RENDER_TOL, grad_err, rel_err, row_grad_err, say
+from gpu_common import GRAD_TOL, RENDER_TOL, rel_err, row_grad_err, say
 from oracle import render as OR
 from paper_2408_03204_amd import RenderBuffers, Schedule
 
@@ -81,6 +81,7 @@ def test_large_console_sampled_nodes_forward_and_adjoint():
     P64 = OR.as_params64(w.params)
     worst = {}
     rows_p = []  # (v, type, gpu row, oracle row) of the parameter gradients, judged per column
+    bad = []
     for v in picked:
         t = int(g.node_type[v])
         u = sum(out_row(s) for s in ins[v]).clone().requires_grad_(True)
@@ -90,15 +91,19 @@ def test_large_console_sampled_nodes_forward_and_adjoint():
         ybar = adj_in(v)
         wrt = [u] + ([p] if p is not None else [])
         grads = torch.autograd.grad(y, wrt, ybar, allow_unused=True)
-        e_u = grad_err(rb.dU[pos[v]].cpu().numpy(), grads[0].numpy())
+        # a signal row [2, T]: judged against its own largest entry (not per time sample)
+        e_u = rel_err(rb.dU[pos[v]].double().cpu().numpy(), grads[0].numpy())
         if p is not None:
             gp = grads[1] if grads[1] is not None else torch.zeros_like(p)
             rows_p.append((v, t, dP[t][rows[v]].cpu().numpy(), gp.numpy()))
         name = synth.TYPE_NAMES[t]
         worst[name] = tuple(max(a, b) for a, b in zip(worst.get(name, (0.0, 0.0, 0.0)),
                                                        (e_y, e_u, 0.0)))
-        assert e_y <= RENDER_TOL, (v, name, "y", e_y)
-        assert e_u <= GRAD_TOL, (v, name, "ubar", e_u)
+        if e_y > RENDER_TOL or e_u > GRAD_TOL:
+            bad.append((v, name, f"y {e_y:.2e}", f"ubar {e_u:.2e}"))
+            say("   failed:", bad[-1])
+    assert rb.error_word() == 0
+    assert not bad, bad
     scale = {}
     for _, t, _, ref in rows_p:
         scale[t] = np.maximum(scale.get(t, 0.0), np.abs(ref))
