@@ -17,7 +17,8 @@
  *   calling thread, and the call has had no side effect: all arguments are checked before any
  *   device work is enqueued.
  * - Ownership: the caller owns all device memory (plan, signal buffers, workspaces, gradients);
- *   the library never allocates or frees device memory and never synchronises a stream. A
+ *   the library never allocates or frees device memory and never synchronises a stream (its one
+ *   device array, the scratch of grafx_render_noalloc, is part of its code object). A
  *   schedule handle owns host memory only; it is immutable after creation and may be shared by
  *   threads and streams.
  * - Device work is enqueued on the caller's stream and runs asynchronously. Two calls that share
@@ -253,6 +254,35 @@ grafx_status grafx_workspace_bytes(const grafx_schedule_t* sched, int64_t T,
 grafx_status grafx_render(const grafx_schedule_t* sched, const void* dev_plan, int64_t T,
                           const float* S, const float* const* P, float* U, void* ws,
                           size_t ws_bytes, hipStream_t stream);
+
+/*
+ * grafx_render_noalloc -- grafx_render for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. The same render
+ * (same kernels, same bits) with the workspace taken from a static scratch array inside the
+ * library instead of a caller buffer.
+ *
+ *   dev_plan, T, S, P, U, stream   exactly as for grafx_render
+ * Scratch: one array of GRAFX_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU, in the library's code
+ * object; each GPU the library runs on holds it until the process ends. The first call on a
+ * device (the device current on the calling thread, which must own `stream`) looks up the
+ * array's address there; no call allocates or frees memory. A render whose forward workspace
+ * (grafx_workspace_bytes with with_backward = 0) exceeds the scratch fails with
+ * GRAFX_E_WORKSPACE before any device work: use grafx_render then. The call clears what must
+ * start at zero (the dynamics chunk states and the error word) itself; everything else it
+ * writes before reading.
+ * Every call on a GPU shares that GPU's scratch, which keeps the last call's contents: two calls
+ * whose device work overlaps on one GPU (different streams, or different threads without
+ * ordering) race and give undefined results. The scratch is not a render workspace for
+ * grafx_render_backward or grafx_workspace_error; a caller that needs the adjoint renders with
+ * grafx_render into its own workspace. A caller that captures should make its first call on each
+ * device outside capture (the address lookup is a runtime query, not stream work).
+ * Errors: those of grafx_render (the workspace checks replaced by the size check above), and
+ * GRAFX_E_HIP if the current device or the scratch address cannot be determined.
+ */
+#define GRAFX_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+grafx_status grafx_render_noalloc(const grafx_schedule_t* sched, const void* dev_plan, int64_t T,
+                                  const float* S, const float* const* P, float* U,
+                                  hipStream_t stream);
 
 /*
  * grafx_render_backward -- adjoint of grafx_render (the backpropagation through the render that

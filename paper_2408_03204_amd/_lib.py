@@ -24,7 +24,8 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_mrstft_backward", "grafx_logmel", "grafx_encoder_gather",
            "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
            "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
-           "grafx_set_schedule_threads", "grafx_workspace_error", "grafx_last_error")
+           "grafx_set_schedule_threads", "grafx_workspace_error", "grafx_last_error",
+           "grafx_render_noalloc")
 
 
 class GrafxError(RuntimeError):
@@ -69,6 +70,7 @@ def load() -> ctypes.CDLL:
         "grafx_plan_upload": (i32, [vp, vp, sz, vp]),
         "grafx_workspace_bytes": (i32, [vp, i64, i32, ctypes.POINTER(sz)]),
         "grafx_render": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, sz, vp]),
+        "grafx_render_noalloc": (i32, [vp, vp, i64, vp, ptr_array, vp, vp]),
         "grafx_render_backward": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, vp, vp, ptr_array,
                                         vp, sz, vp]),
         "grafx_render_step": (i32, [vp, vp, i64, vp, ptr_array, vp, vp, sz, i32, vp]),

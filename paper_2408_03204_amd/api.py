@@ -216,6 +216,22 @@ def render(sched: Schedule, S: torch.Tensor, P: dict, return_U: bool = False):
     return (Y, holder[0]) if return_U else Y
 
 
+def render_noalloc(sched: Schedule, plan: torch.Tensor, S: torch.Tensor, P: dict,
+                   U: torch.Tensor) -> torch.Tensor:
+    """grafx_render_noalloc: the render of `render` into the caller's U [|V|, 2, T] (float32,
+    sigma order) with the library's static scratch as workspace, so the call allocates no device
+    memory. `plan` is the schedule's device plan (`sched.plan(device)`, uploaded beforehand).
+    Returns the output rows of U. Calls that overlap on one GPU share the scratch and race."""
+    T = int(S.shape[-1])
+    if tuple(U.shape) != (sched.num_nodes, 2, T) or U.dtype != torch.float32 or \
+            not U.is_contiguous():
+        raise ValueError(f"U must be contiguous float32 [{sched.num_nodes}, 2, {T}]")
+    check(load().grafx_render_noalloc(sched._h, plan.data_ptr(), T, S.data_ptr(),
+                                      _ptrs(_param_list(sched, P)), U.data_ptr(),
+                                      _stream(U.device)))
+    return U[sched.out_begin:]
+
+
 class _MRSTFT(torch.autograd.Function):
     @staticmethod
     def forward(ctx, Y, target):

@@ -3,10 +3,17 @@
 // first launch; the drivers only enqueue kernels on the caller's stream.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
+
+// Workspace of grafx_render_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends. In host code its name is not a device address: the address comes from
+// hipGetSymbolAddress, looked up once per device (with that device current) by noalloc_scratch.
+static constexpr size_t kNoallocScratchBytes = GRAFX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 namespace grafx {
 namespace {
@@ -255,6 +262,52 @@ grafx_status hip_status(hipError_t e, const char* what) {
   return fail(GRAFX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// The forward loop of grafx_render on a workspace that has passed the checks: per-render
+// parameter preprocessing, reset of the dynamics chaining state, then steps 1..N.
+grafx_status enqueue_render(const grafx_schedule_t* h, const void* dev_plan, int64_t T,
+                            const float* S, const float* const* P, float* U, void* ws,
+                            hipStream_t stream) {
+  const WsLayout L = ws_layout(h, T, false);
+  const GraphView g = make_view(h, dev_plan, T, S, U);
+  auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
+  hipError_t e = hipSuccess;
+  // per-render parameter preprocessing
+  if (h->type_count[GRAFX_EQ] > 0)
+    e = launch_eq_design(par(GRAFX_EQ), h->type_count[GRAFX_EQ], at<double>(ws, L.eq_h),
+                         at<float>(ws, L.eq_H), stream);
+  if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
+    e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
+                            at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
+  if (e == hipSuccess) e = reset_comp(h, ws, L, false, T, stream);
+  if (e == hipSuccess) e = reset_ar(h, ws, L, false, T, stream);
+  for (int n = 1; n <= h->N && e == hipSuccess; ++n)
+    e = enqueue_fwd_step(h, g, P, U, ws, L, n, stream);
+  return hip_status(e, "render launch");
+}
+
+// Host-side table of the scratch array's device address per GPU (see the array's comment at the
+// top of this file).
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || !aligned(p, 256)) return hipErrorInvalidSymbol;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 }  // namespace grafx
 
@@ -289,22 +342,27 @@ grafx_status grafx_render(const grafx_schedule_t* h, const void* dev_plan, int64
   clear_error();
   grafx_status st = check_common(h, dev_plan, T, S, P, U, ws, ws_bytes, false);
   if (st != GRAFX_OK) return st;
-  const WsLayout L = ws_layout(h, T, false);
-  const GraphView g = make_view(h, dev_plan, T, S, U);
-  auto par = [&](int t) -> const float* { return P ? P[t] : nullptr; };
-  hipError_t e = hipSuccess;
-  // per-render parameter preprocessing
-  if (h->type_count[GRAFX_EQ] > 0)
-    e = launch_eq_design(par(GRAFX_EQ), h->type_count[GRAFX_EQ], at<double>(ws, L.eq_h),
-                         at<float>(ws, L.eq_H), stream);
-  if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
-    e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
-                            at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
-  if (e == hipSuccess) e = reset_comp(h, ws, L, false, T, stream);
-  if (e == hipSuccess) e = reset_ar(h, ws, L, false, T, stream);
-  for (int n = 1; n <= h->N && e == hipSuccess; ++n)
-    e = enqueue_fwd_step(h, g, P, U, ws, L, n, stream);
-  return hip_status(e, "render launch");
+  return enqueue_render(h, dev_plan, T, S, P, U, ws, stream);
+}
+
+grafx_status grafx_render_noalloc(const grafx_schedule_t* h, const void* dev_plan, int64_t T,
+                                  const float* S, const float* const* P, float* U,
+                                  hipStream_t stream) {
+  clear_error();
+  // the same checks as grafx_render with a stand-in workspace of the scratch's size (aligned, not
+  // dereferenced), so that a request beyond the scratch fails before any HIP call
+  void* const stand_in = reinterpret_cast<void*>(uintptr_t{256});
+  grafx_status st = check_common(h, dev_plan, T, S, P, U, stand_in, kNoallocScratchBytes, false);
+  if (st == GRAFX_E_WORKSPACE)
+    return fail(GRAFX_E_WORKSPACE,
+                "grafx_render_noalloc needs " + std::to_string(ws_layout(h, T, false).total) +
+                    " bytes of scratch; its static scratch holds " +
+                    std::to_string(kNoallocScratchBytes) + " bytes (use grafx_render)");
+  if (st != GRAFX_OK) return st;
+  void* ws = nullptr;
+  st = hip_status(noalloc_scratch(&ws), "scratch address");
+  if (st != GRAFX_OK) return st;
+  return enqueue_render(h, dev_plan, T, S, P, U, ws, stream);
 }
 
 grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_plan, int64_t T,

@@ -136,3 +136,51 @@ def test_plan_upload_rejects_bad_arguments(console):
     assert lib.grafx_plan_upload(s._h, None, s.plan_bytes, None) == E_ARG
     assert lib.grafx_plan_upload(s._h, addr(1), s.plan_bytes - 1, None) == E_WORKSPACE
     assert lib.grafx_plan_upload(s._h, addr(1, 4), s.plan_bytes, None) == E_SHAPE
+
+
+def noalloc(sched, T=4096, plan=None, S=None, P=None, U=None, h=True):
+    return load().grafx_render_noalloc(
+        sched._h if h else None, addr(1) if plan is None else plan, T,
+        addr(2) if S is None else S, params(sched) if P is None else P,
+        addr(3) if U is None else U, None)
+
+
+def test_noalloc_render_rejects_bad_arguments(console):
+    assert noalloc(console, h=False) == E_ARG
+    assert noalloc(console, plan=0) == E_ARG
+    assert noalloc(console, U=0) == E_ARG
+    assert noalloc(console, T=0) == E_SHAPE
+    assert noalloc(console, T=1 << 29) == E_SHAPE
+    assert noalloc(console, plan=addr(1, 128)) == E_SHAPE
+    assert noalloc(console, U=addr(3, 4)) == E_SHAPE
+    assert noalloc(console, P=params(console, skip=4)) == E_SHAPE
+
+
+def test_noalloc_render_refuses_a_workspace_beyond_its_scratch():
+    """A render whose forward workspace exceeds the static scratch (32 MiB) fails with
+    GRAFX_E_WORKSPACE during validation, before any HIP call."""
+    b = synth.GraphBuilder()
+    i0, m = b.add(synth.IN), b.add(synth.MIX)
+    for _ in range(48):
+        c = b.add(synth.COMP)
+        b.connect(i0, c)
+        b.connect(c, m)
+    b.connect(m, b.add(synth.OUT))
+    g = b.build()
+    sched = Schedule(g.node_type, g.edges)
+    T = 1 << 28
+    assert sched.workspace_bytes(T, False) > (32 << 20)
+    assert noalloc(sched, T=T) == E_WORKSPACE
+    assert b"static scratch" in load().grafx_last_error()
+    # within the scratch the same graph passes validation and only then needs a device: on a host
+    # without one the call fails at the scratch lookup (GRAFX_E_HIP), having launched nothing
+    small = 1 << 16
+    assert sched.workspace_bytes(small, False) <= (32 << 20)
+    if not _has_device():
+        assert noalloc(sched, T=small) == 8  # GRAFX_E_HIP
+        assert b"scratch address" in load().grafx_last_error()
+
+
+def _has_device() -> bool:
+    import torch
+    return torch.cuda.device_count() > 0
