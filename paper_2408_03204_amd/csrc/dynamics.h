@@ -12,6 +12,16 @@ namespace dyn {
 
 constexpr int kPer = 12;
 constexpr int kChunk = kCompChunk;  // 256 x kPer
+
+// LDS layout of a chunk: element x sits at x + x / 96, one padding word after every 8 threads'
+// segments of kPer samples. Thread j's segment is then contiguous from seg_base(j), and the 32
+// lanes that one LDS cycle serves, reading element i of their own segments (a 12-word stride
+// that would put 4 lanes on each of 8 banks), fall on 32 distinct banks; the coalesced staging
+// writes and the stores stay conflict-free.
+constexpr int kLdsChunk = kChunk + kChunk / 96;
+__device__ __forceinline__ int lpos(int x) { return x + x / 96; }
+__device__ __forceinline__ int seg_base(int j) { return kPer * j + (j >> 3); }
+static_assert(kPer * 8 == 96, "one padding word per 8 segments");
 constexpr double kEps = 1e-8;
 constexpr uint64_t kNotReady = ~0ull;
 
@@ -114,8 +124,8 @@ __device__ __forceinline__ double await_total(uint64_t* slot, unsigned* err, int
 
 // ---- staging -----------------------------------------------------------------------------------
 
-// Gather-sum of a chunk (both channels) into LDS: ADJ = false sums the input edges over U/S,
-// ADJ = true the output edges over dU/dY. Zero beyond T.
+// Gather-sum of a chunk (both channels) into LDS (padded layout): ADJ = false sums the input
+// edges over U/S, ADJ = true the output edges over dU/dY. Zero beyond T.
 template <bool ADJ, bool RAGGED>
 __device__ __forceinline__ void stage(const GraphView& g, int node, int t0, float* sl, float* sr) {
   const int64_t T = g.T;
@@ -144,26 +154,32 @@ __device__ __forceinline__ void stage(const GraphView& g, int node, int t0, floa
   }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    sl[threadIdx.x + kBlock * q] = l[q];
-    sr[threadIdx.x + kBlock * q] = r[q];
+    sl[lpos(threadIdx.x + kBlock * q)] = l[q];
+    sr[lpos(threadIdx.x + kBlock * q)] = r[q];
   }
 }
 
-// x = (u_l + u_r)^2, formed in float and fed to the double envelope recursion.
+// x = (u_l + u_r)^2 at LDS position idx, formed in float and fed to the double envelope
+// recursion.
 __device__ __forceinline__ double energy(const float* sl, const float* sr, int idx) {
   const float m = sl[idx] + sr[idx];
   return (double)(m * m);
 }
 
-// Chunk store into a row of stride T; samples at or beyond the node's length Tn are dropped.
+// Chunk store (from the padded layout) into a row of stride T; samples at or beyond the node's
+// length Tn are dropped.
 __device__ __forceinline__ void store_chunk(float* row, int64_t T, int64_t Tn, int t0,
                                             const float* sl, const float* sr) {
   const auto rl = row_rsrc(row, Tn), rr = row_rsrc(row + T, Tn);
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int idx = threadIdx.x + kBlock * q;
-    bstore(rl, t0 + idx, sl[idx]);
-    bstore(rr, t0 + idx, sr[idx]);
+    // an opaque copy of the thread index keeps the compiler from holding the staging
+    // addresses, which are the same, in registers from the staging to here
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int idx = tid + kBlock * q;
+    bstore(rl, t0 + idx, sl[lpos(idx)]);
+    bstore(rr, t0 + idx, sr[lpos(idx)]);
   }
 }
 

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
                                                           int node_begin, int n_nodes, int chunks,
                                                           int ws_off, uint64_t* agg, double* carry,
                                                           unsigned* ticket, unsigned* err) {
-  __shared__ float sl[kChunk], sr[kChunk];
+  __shared__ float sl[kLdsChunk], sr[kLdsChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
   const int node = node_begin + (int)blockIdx.x / chunks;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
   const int t0 = chunk * kChunk;
   stage<false, RAGGED>(g, node, t0, sl, sr);
   __syncthreads();
-  const int i0 = kPer * threadIdx.x;
+  const int i0 = seg_base(threadIdx.x);  // this thread's kPer samples
   double B = 0.0;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) B = fma(k.a, B, k.b * energy(sl, sr, i0 + i));
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
                                                           const double* carry, uint64_t* ragg,
                                                           double* part, unsigned* ticket,
                                                           unsigned* err) {
-  __shared__ float ul[kChunk], ur[kChunk], yl[kChunk], yr[kChunk];
+  __shared__ float ul[kLdsChunk], ur[kLdsChunk], yl[kLdsChunk], yr[kLdsChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
   const int node = node_begin + (int)blockIdx.x / chunks;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   stage<false, RAGGED>(g, node, t0, ul, ur);
   stage<true, RAGGED>(g, node, t0, yl, yr);
   __syncthreads();
-  const int i0 = kPer * threadIdx.x;
+  const int i0 = seg_base(threadIdx.x);  // this thread's kPer samples
   // envelope rebuilt from the forward carry
   double B = 0.0;
 #pragma unroll

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
     GraphView g, float* U, const float* P, int node_begin, int n_nodes, int chunks, int max_pass,
     uint64_t* pslot, uint64_t* fin, double* carry, uint16_t* pats, unsigned* ticket,
     unsigned* err) {
-  __shared__ float sl[kChunk], sr[kChunk];
+  __shared__ float sl[kLdsChunk], sr[kLdsChunk];
   __shared__ Aff wtot[4];
   __shared__ uint16_t sh_pat[kBlock];
   __shared__ int sh_ticket;
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
   const int t0 = chunk * kChunk;
   stage<false, RAGGED>(g, node, t0, sl, sr);
   __syncthreads();
-  const int i0 = kPer * threadIdx.x;
+  const int i0 = seg_base(threadIdx.x);  // this thread's kPer samples
   float x[kPer];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
       for (int j = 0; j < kBlock; ++j) {
         int p = 0;
         for (int i = 0; i < kPer; ++i) {
-          const float m = sl[j * kPer + i] + sr[j * kPer + i];
+          const float m = sl[seg_base(j) + i] + sr[seg_base(j) + i];
           const double xi = (double)(m * m);
           const bool up = xi > s;
           p |= (int)up << i;
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_bwd_kernel(
     GraphView g, float* dU, const float* P, int node_begin, int n_nodes, int chunks,
     const double* carry, const uint16_t* pats, uint64_t* ragg, double* part, unsigned* ticket,
     unsigned* err) {
-  __shared__ float ul[kChunk], ur[kChunk], yl[kChunk], yr[kChunk];
+  __shared__ float ul[kLdsChunk], ur[kLdsChunk], yl[kLdsChunk], yr[kLdsChunk];
   __shared__ Aff wtot[4];
   __shared__ double red[4];
   __shared__ int sh_ticket;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_bwd_kernel(
   stage<false, RAGGED>(g, node, t0, ul, ur);
   stage<true, RAGGED>(g, node, t0, yl, yr);
   __syncthreads();
-  const int i0 = kPer * threadIdx.x;
+  const int i0 = seg_base(threadIdx.x);  // this thread's kPer samples
   const int pat = pats[((int64_t)slot * chunks + chunk) * kBlock + threadIdx.x];
   float x[kPer];
 #pragma unroll
