@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--T", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-forward-only", action="store_true",
+                    help="skip timing the forward render alone (a trace then ends with the "
+                         "timed step issues)")
     ap.add_argument("--breakdown-json", default=None, help="write the per-step timing table here")
     ap.add_argument("--train-consoles", type=int, default=25000,
                     help="learned_init: labelled tiny consoles rendered for training (4 examples each)")
@@ -513,13 +516,15 @@ def main():
     per = sorted(a.elapsed_time(b) for a, b in evs)
     spread = {q: round(float(np.percentile(per, q)), 4) for q in (10, 50, 90)}
     # the forward render alone (the paper's render call), eager issue
-    rbf = ctx["rb"] or RenderBuffers(sched, T, dev, with_backward=False)
-    fwd_ms = timed(lambda: rbf.forward(S, ctx["P"]))
-    fwd_bytes = sum(step_bytes(sched, n, T, False) for n in range(1, sched.num_steps + 1))
-    forward = {"ms": round(fwd_ms, 4), "node_samples_per_s": round(ctx["node_samples"] /
-                                                                     (fwd_ms * 1e-3), 1),
-               "algorithmic_GBps": round(fwd_bytes / (fwd_ms * 1e6), 1),
-               "hbm_frac": round(fwd_bytes / (fwd_ms * 1e6) / HBM_PEAK_GBS, 4)}
+    forward = None
+    if not args.no_forward_only:
+        rbf = ctx["rb"] or RenderBuffers(sched, T, dev, with_backward=False)
+        fwd_ms = timed(lambda: rbf.forward(S, ctx["P"]))
+        fwd_bytes = sum(step_bytes(sched, n, T, False) for n in range(1, sched.num_steps + 1))
+        forward = {"ms": round(fwd_ms, 4),
+                   "node_samples_per_s": round(ctx["node_samples"] / (fwd_ms * 1e-3), 1),
+                   "algorithmic_GBps": round(fwd_bytes / (fwd_ms * 1e6), 1),
+                   "hbm_frac": round(fwd_bytes / (fwd_ms * 1e6) / HBM_PEAK_GBS, 4)}
 
     # ---- per-step breakdown: every render / adjoint step timed with events on its stream ------
     roofline, table, steps_hbm = None, [], None

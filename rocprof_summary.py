@@ -4,6 +4,13 @@ Kernel durations (from a `--kernel-trace --stats` run):
 
     python rocprof_summary.py trace <run_results.db> <command...>
 
+Gaps between kernels of HIP-graph replays (from a `--kernel-trace` run of a program whose last
+`replays` kernel issues are identical graph replays of one step; the kernels per replay are found
+as the period of the trace's kernel-name sequence): the time the GPU runs no kernel between a
+replay's first start and last end, as a fraction of that span, over all replays:
+
+    python rocprof_summary.py gaps <run_results.db> <replays> <command...>
+
 HBM traffic per kernel from two PMC runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`) of a
 program that first copies `copy_mib` MiB device-to-device: each counter is scaled by
 (true bytes of that copy) / (what the counter reads for it). Also writes the traffic of one
@@ -40,6 +47,40 @@ def trace(db: str, cmd: str) -> None:
         print(f"{short(name)[:60]:60s} {n:6d} {tot / 1e3:10.1f} {avg / 1e3:9.2f} "
               f"{100 * tot / total:5.1f}%")
     print(f"\n{'all kernels':60s} {sum(r[1] for r in rows):6d} {total / 1e3:10.1f}")
+
+
+def gaps(db: str, replays: int, cmd: str) -> None:
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select start, end, name from kernels order by start"))
+    n = len(rows)
+    names = [r[2] for r in rows]
+    per = next(p for p in range(8, n // replays + 1)
+               if all(names[n - (k + 1) * p:n - k * p] == names[n - p:]
+                      for k in range(1, replays)))  # kernels per replay: the trace's period
+    rows = rows[n - replays * per:]
+    print(f"# rocprofv3 kernel trace: gaps between kernels inside HIP-graph replays\n"
+          f"# command: {cmd}\n# {n} kernels traced; the last {replays} issues are graph "
+          f"replays of {per} kernels each\n")
+    print(f"{'replay':>6s} {'kernels':>8s} {'span_us':>10s} {'busy_us':>10s} {'gaps_us':>9s} "
+          f"{'gap_frac':>8s} {'max_gap_us':>10s}")
+    tot_span = tot_gap = 0.0
+    for r in range(replays):
+        seg = rows[r * per:(r + 1) * per]
+        span = (max(e for _, e, _ in seg) - seg[0][0]) / 1e3
+        busy, cur_s, cur_e, mx = 0.0, seg[0][0], seg[0][1], 0.0
+        for s, e, _ in seg[1:]:
+            if s > cur_e:
+                busy += cur_e - cur_s
+                mx = max(mx, (s - cur_e) / 1e3)
+                cur_s, cur_e = s, e
+            else:
+                cur_e = max(cur_e, e)
+        busy = (busy + cur_e - cur_s) / 1e3
+        tot_span += span
+        tot_gap += span - busy
+        print(f"{r:6d} {len(seg):8d} {span:10.1f} {busy:10.1f} {span - busy:9.1f} "
+              f"{(span - busy) / span:8.4f} {mx:10.2f}")
+    print(f"\nall replays: gaps {tot_gap:.1f} us of {tot_span:.1f} us = {tot_gap / tot_span:.4f}")
 
 
 def _counter(db: str, name: str):
@@ -87,6 +128,8 @@ def pmc(fetch_db: str, write_db: str, copy_mib: float, steps: int, kernel: str, 
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], " ".join(sys.argv[3:]))
+    elif sys.argv[1] == "gaps":
+        gaps(sys.argv[2], int(sys.argv[3]), " ".join(sys.argv[4:]))
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6],
             sys.argv[7], sys.argv[8], sys.argv[9], " ".join(sys.argv[10:]))
