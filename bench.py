@@ -255,13 +255,16 @@ def cpu_baseline_graph(w, min_seconds: float = 8.0, max_reps: int = 6):
 
 def _tune(args, sched, S, P) -> dict:
     """Optionally autotune the schedule; returns the settings in force for the config record."""
-    from paper_2408_03204_amd import Schedule
+    from paper_2408_03204_amd import autotune
+    times = None
     if args.autotune:
-        from paper_2408_03204_amd.autotune import tune_pointwise
-        times = tune_pointwise(sched, S, P)
-        print(f"autotune (pointwise unroll -> ms): {times}", file=sys.stderr)
-    return {"pointwise_unroll": sched.get_tuning(Schedule.TUNE_POINTWISE_UNROLL),
-            "autotuned": bool(args.autotune)}
+        times = autotune.tune_all(sched, S, P)
+        print(f"autotune (setting -> candidate -> ms): {times}", file=sys.stderr)
+    out = {**autotune.settings(sched), "autotuned": bool(args.autotune)}
+    if times:
+        out["autotune_ms"] = {k: {str(c): round(v, 4) for c, v in r.items()}
+                              for k, r in times.items()}
+    return out
 
 
 def setup_console(args, dev):

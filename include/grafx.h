@@ -338,6 +338,17 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* sched, const voi
  * per-sample arithmetic or the workspace size.
  *   GRAFX_TUNE_POINTWISE_UNROLL: 1024-sample parts per block of the pointwise kernels (mix, out,
  *     gain_pan, imager, tanh): 1 (default), 2 or 4.
+ *   GRAFX_TUNE_EQ_ORDER: order of the EQ kernels' blocks: 0 maps the tiles of one node onto one
+ *     XCD (neighbouring tiles share their halo through its L2), 1 (default) keeps the hardware's
+ *     round-robin order. Same bits either way.
+ *   GRAFX_TUNE_DYN_ORDER: order of the dynamics kernels' blocks (compressor, noisegate,
+ *     compressor_ar): 0 issues a node's chunks contiguously, 1 interleaves the step's nodes block
+ *     by block, so that a chunk's predecessors have usually published by the time it starts;
+ *     2 (default) interleaves a launch of at least 4096 blocks (several rounds of resident
+ *     blocks) and keeps a smaller one contiguous. Chunks are still taken in ticket order per
+ *     node: same bits.
+ *   GRAFX_TUNE_TAP_TILES: time tiles (2048 samples) per block of the delay's tap-gradient pass:
+ *     4, 8 or 16 (default); sets the grouping of the tap-gradient partial sums.
  * Two settings bound the iterative parts of the dynamics kernels instead:
  *   GRAFX_TUNE_AR_MAX_PASSES: branch-pattern passes of the attack/release compressor's forward
  *     (Eq. 8 with distinct coefficients) before a chunk that has not settled falls back to the
@@ -353,7 +364,10 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* sched, const voi
  * another thread are not synchronised with it. A HIP graph captured from render calls keeps the
  * settings in force at capture time.
  */
-enum { GRAFX_TUNE_POINTWISE_UNROLL = 0, GRAFX_TUNE_AR_MAX_PASSES = 1, GRAFX_TUNE_WAIT_POLLS = 2 };
+enum {
+  GRAFX_TUNE_POINTWISE_UNROLL = 0, GRAFX_TUNE_AR_MAX_PASSES = 1, GRAFX_TUNE_WAIT_POLLS = 2,
+  GRAFX_TUNE_EQ_ORDER = 3, GRAFX_TUNE_DYN_ORDER = 4, GRAFX_TUNE_TAP_TILES = 5
+};
 grafx_status grafx_schedule_set_tuning(grafx_schedule_t* sched, int32_t knob, int32_t value);
 grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* sched, int32_t knob,
                                        int32_t* value);

@@ -104,6 +104,9 @@ class Schedule:
     TUNE_POINTWISE_UNROLL = 0
     TUNE_AR_MAX_PASSES = 1
     TUNE_WAIT_POLLS = 2
+    TUNE_EQ_ORDER = 3
+    TUNE_DYN_ORDER = 4
+    TUNE_TAP_TILES = 5
 
     def set_tuning(self, knob: int, value: int) -> None:
         """A tuning setting of the schedule (see include/grafx.h, grafx_schedule_set_tuning)."""

@@ -28,6 +28,9 @@ struct GraphView {
   int32_t vec4;              // T and every node length are multiples of 4 (16-byte vectors)
   int32_t pw_unroll;         // pointwise kernels: 1024-sample parts per block (1, 2 or 4)
   int32_t wait_polls;        // dynamics kernels: reads of a published chunk state before giving up
+  int32_t eq_order;          // EQ kernels: 0 tiles of a node on one XCD, 1 hardware block order
+  int32_t dyn_order;         // dynamics kernels: 0 a node's blocks contiguous, 1 nodes interleaved
+  int32_t tap_tiles;         // delay tap gradients: tiles per block (4, 8 or 16)
 };
 
 // Length of the signal of the node at sigma position v (its row holds valid samples [0, len)).

@@ -79,7 +79,8 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.eq_C = take(n_eq * (size_t)eq_tiles(T) * kEqFoldStride * sizeof(float));
     L.eq_spec = take(n_eq * kEqFoldStride * sizeof(float));
     L.eq_s = take(n_eq * 1024 * sizeof(double));
-    L.delay_part = take(n_del * delay_groups(T) * kDelayCoef * sizeof(float));
+    // sized for the smallest tap-gradient group, so that the size does not depend on tuning
+    L.delay_part = take(n_del * delay_groups(T, kTapTilesMin) * kDelayCoef * sizeof(float));
     L.ar_ragg = take(n_ar * chunks * 2 * sizeof(uint64_t));
     L.ar_part = take(n_ar * chunks * kArParams * sizeof(double));
   }
@@ -112,6 +113,9 @@ GraphView make_view(const grafx_schedule_t* h, const void* dev_plan, int64_t T, 
   g.vec4 = (T % 4 == 0) && h->len4;
   g.pw_unroll = h->pw_unroll;
   g.wait_polls = h->wait_polls;
+  g.eq_order = h->eq_order;
+  g.dyn_order = h->dyn_order;
+  g.tap_tiles = h->tap_tiles;
   return g;
 }
 
@@ -182,6 +186,16 @@ hipError_t reset_ar(const grafx_schedule_t* h, void* ws, const WsLayout& L, bool
                            t, n_ar * kCompTicketStride, stream);
 }
 
+// The dynamics block order of one launch: the setting, or for "auto" (2) interleaved nodes once a
+// launch spans several rounds of resident blocks (then a chunk's predecessors have usually
+// published by the time it starts) and a node's chunks together for about one round.
+constexpr int kDynInterleaveBlocks = 4096;
+GraphView dyn_view(const GraphView& g, int n_nodes) {
+  GraphView d = g;
+  if (d.dyn_order == 2) d.dyn_order = (int64_t)n_nodes * comp_chunks(g.T) >= kDynInterleaveBlocks;
+  return d;
+}
+
 hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const float* const* P,
                             float* U, void* ws, const WsLayout& L, int n, hipStream_t stream) {
   const int t = h->step_type[n];
@@ -199,7 +213,7 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_eq_fwd(g, U, at<float>(ws, L.eq_H), b, cnt, stream);
     case GRAFX_COMPRESSOR:
     case GRAFX_NOISEGATE:
-      return launch_comp_fwd(g, U, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
+      return launch_comp_fwd(dyn_view(g, cnt), U, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
                              at<uint64_t>(ws, L.comp_agg),
                              at<double>(ws, L.comp_carry), tickets(ws, L, h, false),
                              error_word(ws, L), stream);
@@ -209,7 +223,7 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
     case GRAFX_COMPRESSOR_AR: {
       const size_t n_ar = h->type_count[GRAFX_COMPRESSOR_AR], chunks = comp_chunks(g.T);
       uint64_t* slots = at<uint64_t>(ws, L.ar_slots);
-      return launch_comp_ar_fwd(g, U, p, b, cnt, h->ar_max_pass, slots,
+      return launch_comp_ar_fwd(dyn_view(g, cnt), U, p, b, cnt, h->ar_max_pass, slots,
                                 slots + n_ar * (size_t)kArPasses * chunks * 3,
                                 at<double>(ws, L.ar_carry), at<uint16_t>(ws, L.ar_pat),
                                 at<unsigned>(ws, L.ar_tickets), error_word(ws, L), stream);
@@ -238,7 +252,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_eq_bwd(g, dU, at<float>(ws, L.eq_H), b, cnt, at<float>(ws, L.eq_C), stream);
     case GRAFX_COMPRESSOR:
     case GRAFX_NOISEGATE:
-      return launch_comp_bwd(g, dU, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
+      return launch_comp_bwd(dyn_view(g, cnt), dU, p, b, cnt, dyn_row(h, t), t == GRAFX_NOISEGATE,
                              at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
                              tickets(ws, L, h, true), error_word(ws, L), stream);
@@ -246,7 +260,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
       return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
                               b, cnt, at<float>(ws, L.delay_part), stream);
     case GRAFX_COMPRESSOR_AR:
-      return launch_comp_ar_bwd(g, dU, p, b, cnt, at<double>(ws, L.ar_carry),
+      return launch_comp_ar_bwd(dyn_view(g, cnt), dU, p, b, cnt, at<double>(ws, L.ar_carry),
                                 at<uint16_t>(ws, L.ar_pat), at<uint64_t>(ws, L.ar_ragg),
                                 at<double>(ws, L.ar_part),
                                 at<unsigned>(ws, L.ar_tickets) +
@@ -410,7 +424,8 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
                        at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
   if (e == hipSuccess && dpar(GRAFX_DELAY))
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
-                          h->type_count[GRAFX_DELAY], delay_groups(T), dpar(GRAFX_DELAY), stream);
+                          h->type_count[GRAFX_DELAY], delay_groups(T, h->tap_tiles),
+                          dpar(GRAFX_DELAY), stream);
   return hip_status(e, "render_backward launch");
 }
 
@@ -470,6 +485,20 @@ grafx_status grafx_schedule_set_tuning(grafx_schedule_t* h, int32_t knob, int32_
       if (value < 0 || value > (1 << 30)) return fail(GRAFX_E_ARG, "wait polls must be in 0..2^30");
       h->wait_polls = value;
       return GRAFX_OK;
+    case GRAFX_TUNE_EQ_ORDER:
+      if (value != 0 && value != 1) return fail(GRAFX_E_ARG, "EQ block order must be 0 or 1");
+      h->eq_order = value;
+      return GRAFX_OK;
+    case GRAFX_TUNE_DYN_ORDER:
+      if (value < 0 || value > 2)
+        return fail(GRAFX_E_ARG, "dynamics block order must be 0, 1 or 2");
+      h->dyn_order = value;
+      return GRAFX_OK;
+    case GRAFX_TUNE_TAP_TILES:
+      if (value != 4 && value != 8 && value != 16)
+        return fail(GRAFX_E_ARG, "delay tap-gradient tiles must be 4, 8 or 16");
+      h->tap_tiles = value;
+      return GRAFX_OK;
     default:
       return fail(GRAFX_E_ARG, "unknown tuning knob");
   }
@@ -482,6 +511,9 @@ grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* h, int32_t knob, 
     case GRAFX_TUNE_POINTWISE_UNROLL: *value = h->pw_unroll; return GRAFX_OK;
     case GRAFX_TUNE_AR_MAX_PASSES: *value = h->ar_max_pass; return GRAFX_OK;
     case GRAFX_TUNE_WAIT_POLLS: *value = h->wait_polls; return GRAFX_OK;
+    case GRAFX_TUNE_EQ_ORDER: *value = h->eq_order; return GRAFX_OK;
+    case GRAFX_TUNE_DYN_ORDER: *value = h->dyn_order; return GRAFX_OK;
+    case GRAFX_TUNE_TAP_TILES: *value = h->tap_tiles; return GRAFX_OK;
     default: return fail(GRAFX_E_ARG, "unknown tuning knob");
   }
 }

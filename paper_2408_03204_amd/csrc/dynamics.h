@@ -95,6 +95,13 @@ __device__ __forceinline__ float exp_f(float x) {
 
 __device__ __forceinline__ int comp_chunks_of(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 
+// Node of a block within its step: a node's `chunks` blocks contiguous (order 0) or the step's
+// nodes interleaved block by block (order 1). A block's chunk comes from its node's ticket, so
+// the order decides only when a node's chunks are issued, not what they compute.
+__device__ __forceinline__ int block_node(const GraphView& g, int n_nodes, int chunks) {
+  return g.dyn_order ? (int)blockIdx.x % n_nodes : (int)blockIdx.x / chunks;
+}
+
 // ---- chunk chaining ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int take_ticket(unsigned* counter, int* sh) {

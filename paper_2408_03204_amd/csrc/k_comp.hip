@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void comp_fwd_kernel(GraphView g, float* U,
   __shared__ float sl[kLdsChunk], sr[kLdsChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
-  const int node = node_begin + (int)blockIdx.x / chunks;
+  const int node = node_begin + block_node(g, n_nodes, chunks);
   const int slot = g.param_row[node];  // row in P
   const int ws = slot + ws_off;         // row of the dynamics workspace (compressors, then gates)
   const int chunk = take_ticket(ticket + (int64_t)ws * kCompTicketStride, &sh_ticket);
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void comp_bwd_kernel(GraphView g, float* dU
   __shared__ float ul[kLdsChunk], ur[kLdsChunk], yl[kLdsChunk], yr[kLdsChunk];
   __shared__ double wtot[4], red[4];
   __shared__ int sh_ticket;
-  const int node = node_begin + (int)blockIdx.x / chunks;
+  const int node = node_begin + block_node(g, n_nodes, chunks);
   const int slot = g.param_row[node];  // row in P
   const int ws = slot + ws_off;         // row of the dynamics workspace (compressors, then gates)
   const int tk = take_ticket(ticket + (int64_t)ws * kCompTicketStride, &sh_ticket);

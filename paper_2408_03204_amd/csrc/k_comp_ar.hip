@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_fwd_kernel(
   __shared__ Aff wtot[4];
   __shared__ uint16_t sh_pat[kBlock];
   __shared__ int sh_ticket;
-  const int node = node_begin + (int)blockIdx.x / chunks;
+  const int node = node_begin + block_node(g, n_nodes, chunks);
   const int slot = g.param_row[node];
   const int chunk = take_ticket(ticket + (int64_t)slot * kCompTicketStride, &sh_ticket);
   if (chunk >= chunks) {  // tickets not reset before the launch: do nothing
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void comp_ar_bwd_kernel(
   __shared__ Aff wtot[4];
   __shared__ double red[4];
   __shared__ int sh_ticket;
-  const int node = node_begin + (int)blockIdx.x / chunks;
+  const int node = node_begin + block_node(g, n_nodes, chunks);
   const int slot = g.param_row[node];
   const int tk = take_ticket(ticket + (int64_t)slot * kCompTicketStride, &sh_ticket);
   if (tk >= chunks) {  // tickets not reset before the launch: do nothing

@@ -134,10 +134,10 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
   (void)tiles;
 }
 
-// Tiles per tap-gradient block: a constant, so a node's partial sums are grouped the same way
-// whatever the row stride T (a graph merged with longer ones gets the same bits as alone). Eight
-// tiles amortise the block reduction of the 39 sums per channel-tap.
-constexpr int kTapTiles = 8;
+// Tiles per tap-gradient block: a setting of the schedule (4, 8 or 16; 16 by default), not a
+// function of T, so a node's partial sums are grouped the same way whatever the row stride (a
+// graph merged with longer ones gets the same bits as alone). More tiles amortise the block
+// reduction of the 39 sums per channel-tap; fewer give short steps more blocks.
 
 // Tap gradients: part[slot][group][c*5+m][j] = sum over the group's tiles of
 // sum_t ybar_c[t] u_c[t - d - j]. One block per (node, group, channel-slot): the ten sums of a
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, cons
   const int group = (lb % per_node) / kCM, cm = lb % kCM;
   const int slot = g.param_row[node];
   const int tiles_n = (int)((node_len(g, node) + kHop - 1) / kHop);  // the node's own tiles
-  const int tile_end = min(min(tiles, tiles_n), (group + 1) * kTapTiles);
+  const int tile_end = min(min(tiles, tiles_n), (group + 1) * g.tap_tiles);
   const int o0 = kPer * threadIdx.x;
   {
     const int c = cm / kDelayTaps;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, cons
     float acc[kDelayFir];
 #pragma unroll
     for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] = 0.f;
-    for (int tile = group * kTapTiles; tile < tile_end; ++tile) {
+    for (int tile = group * g.tap_tiles; tile < tile_end; ++tile) {
       const int64_t t0 = (int64_t)tile * kHop;
       __syncthreads();
       stage_window<false>(g, node, c, t0 - d - kHalf, kWin, w);
@@ -231,7 +231,9 @@ __global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, cons
 
 int delay_tiles(int64_t T) { return (int)((T + kHop - 1) / kHop); }
 
-int delay_groups(int64_t T) { return (delay_tiles(T) + kTapTiles - 1) / kTapTiles; }
+int delay_groups(int64_t T, int tap_tiles) {
+  return (delay_tiles(T) + tap_tiles - 1) / tap_tiles;
+}
 
 hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -253,7 +255,7 @@ hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
   const int tiles = delay_tiles(g.T);
   delay_conv_kernel<true><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, dU, taps, offs, node_begin,
                                                                   tiles);
-  const int groups = delay_groups(g.T);
+  const int groups = delay_groups(g.T, g.tap_tiles);
   delay_tapgrad_kernel<<<dim3(groups * 2 * kDelayTaps, n_nodes), kBlock, 0, s>>>(
       g, offs, node_begin, tiles, groups, part);
   return hipGetLastError();

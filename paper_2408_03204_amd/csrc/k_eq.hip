@@ -15,7 +15,8 @@
 // transform touch LDS; each thread keeps the 15 twiddles of the last pass in registers for all
 // transforms of the block and reads those of the middle pass, which take only 16 x 16 values,
 // from LDS. Window gathers use raw buffer loads whose range check supplies the zero padding. Tiles
-// of one node are mapped onto one XCD (neighbouring tiles share the halo through its L2).
+// of one node are mapped onto one XCD (neighbouring tiles share the halo through its L2); the
+// EQ block-order setting can keep the hardware order instead (same arithmetic).
 //
 // Adjoint: the input adjoint is the same filter applied to the output adjoint (h is even). The
 // FIR gradient hbar[n] = sum_{c,t} ybar_c[t] u_c[t - n] is the real part of a complex
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
                                                         int node_begin, int tiles) {
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int lb = g.eq_order ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % tiles, node = node_begin + lb / tiles;
   const int j = threadIdx.x;
   const int64_t T = g.T, Tn = node_len(g, node);
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
                                                         int node_begin, int tiles, float* Fpart) {
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int lb = g.eq_order ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % tiles, node = node_begin + lb / tiles;
   const int j = threadIdx.x;
   const int64_t T = g.T, Tn = node_len(g, node);

@@ -99,7 +99,8 @@ hipError_t launch_comp_ar_bwd(const GraphView& g, float* dU, const float* P, int
 constexpr int kDelayTaps = 5, kDelayFir = 39, kDelaySlot = 4410;
 constexpr int kDelayCoef = 2 * kDelayTaps * kDelayFir;  // 390 per node
 int delay_tiles(int64_t T);
-int delay_groups(int64_t T);  // tile groups per node in the tap-gradient pass
+constexpr int kTapTilesMin = 4;  // smallest tap-gradient group (sizes the partials)
+int delay_groups(int64_t T, int tap_tiles);  // tile groups per node in the tap-gradient pass
 // taps: float [n][390]; offs: int32 [n][10]
 hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s);
 hipError_t launch_delay_fwd(const GraphView& g, float* U, const float* taps, const int32_t* offs,

@@ -76,3 +76,97 @@ def test_autotuner_sets_a_candidate():
     say(f"   autotune ms: {times}")
     assert set(times) == {1, 2, 4} and all(v > 0 for v in times.values())
     assert sched.get_tuning(KNOB) == min(times, key=times.get)
+
+
+ALL_TYPES = (synth.MIX, synth.GAIN_PAN, synth.EQ, synth.COMP, synth.IMAGER, synth.DELAY,
+             synth.TANH, synth.GATE, synth.COMP_AR)
+
+
+def _render_adjoint(w, sched, dY):
+    S, P = device_inputs(w)
+    rb = RenderBuffers(sched, w.T, "cuda", with_backward=True)
+    rb.forward(S, P)
+    dP = {t: torch.empty_like(p) for t, p in P.items()}
+    dS = torch.zeros_like(S)
+    rb.backward(S, P, torch.as_tensor(dY).cuda(), dP, dS=dS)
+    torch.cuda.synchronize()
+    K, ob = sched.num_inputs, sched.out_begin
+    return (rb.U[K:].cpu().numpy(), rb.dU[K:ob].cpu().numpy(), dS.cpu().numpy(),
+            {t: g.cpu().numpy() for t, g in dP.items()})
+
+
+@pytest.mark.parametrize("knob", [Schedule.TUNE_EQ_ORDER, Schedule.TUNE_DYN_ORDER])
+def test_block_order_settings_keep_every_bit(knob):
+    """The EQ and dynamics block orders move launches only: renders, input adjoints and every
+    parameter gradient are bit-identical under both orders."""
+    T = 7 * 3072 + 1234  # several dynamics chunks and EQ tiles, ragged tail
+    w = synth.random_workload(1700 + knob, 18, T, types=ALL_TYPES, edge_p=0.3, n_out=2)
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    dY = np.random.default_rng(5).normal(size=(sched.num_outputs, 2, T)).astype(np.float32)
+    say(f"[tuning order] knob={knob} types={sorted(set(w.graph.node_type.tolist()))}")
+    sched.set_tuning(knob, 0)
+    ref = _render_adjoint(w, sched, dY)
+    sched.set_tuning(knob, 1)
+    got = _render_adjoint(w, sched, dY)
+    for a, b in zip(ref[:3], got[:3]):
+        assert np.array_equal(a, b)
+    for t in ref[3]:
+        assert np.array_equal(ref[3][t], got[3][t]), t
+
+
+def test_tap_tiles_settings_against_oracle():
+    """Tap-gradient tiles per block 4 / 8 / 16 at a length with 33 tiles (groups of 9, 5 and 3):
+    renders and input adjoints bit-identical; delay gradients within tolerance of the oracle."""
+    from test_gpu_fullsize_paths import delay_graph
+    T = 2 ** 16 + 1234
+    w = delay_graph(T, 93)
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    dY = np.random.default_rng(6).normal(size=(sched.num_outputs, 2, T)).astype(np.float32)
+    ref = oracle_grads(w, dY)
+    outs = {}
+    for v in (8, 4, 16):
+        sched.set_tuning(Schedule.TUNE_TAP_TILES, v)  # 16 is the default
+        outs[v] = _render_adjoint(w, sched, dY)
+        e = grad_err(outs[v][3][synth.DELAY], ref[synth.DELAY])
+        say(f"[tap tiles] {v}: delay grad err {e:.2e}")
+        assert e <= GRAD_TOL, (v, e)
+    for v in (4, 16):
+        for a, b in zip(outs[8][:3], outs[v][:3]):
+            assert np.array_equal(a, b), v
+
+
+def test_merged_graphs_keep_their_bits_under_tap_tiles():
+    ws = [synth.random_workload(1800 + i, 12, T, types=ALL_TYPES) for i, T in
+          enumerate((9 * 2048 + 77, 5 * 2048 + 3, 13 * 2048))]
+    import test_gpu_batch as B
+    orig = B.Schedule
+
+    class Tuned(orig):  # every schedule the check builds: 4 tiles per tap block, node-major
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.set_tuning(Schedule.TUNE_TAP_TILES, 4)
+            self.set_tuning(Schedule.TUNE_DYN_ORDER, 0)
+            self.set_tuning(Schedule.TUNE_EQ_ORDER, 0)
+
+    B.Schedule = Tuned
+    try:
+        B._check_merged(ws, "tap tiles 4, node-major dynamics, XCD-contiguous EQ")
+    finally:
+        B.Schedule = orig
+
+
+def test_autotuner_tunes_every_setting_with_steps():
+    from paper_2408_03204_amd import autotune
+    w = synth.random_workload(1900, 16, 5 * 3072, types=ALL_TYPES, edge_p=0.3)
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    S, P = device_inputs(w)
+    times = autotune.tune_all(sched, S, P, reps=2)
+    say(f"   autotune ms: {times}")
+    present = set(int(t) for t in sched.step_type)
+    for knob, (types, cands) in autotune.KNOBS.items():
+        name = autotune.KNOB_NAMES[knob]
+        if present & set(types):
+            assert set(times[name]) == set(cands)
+            assert sched.get_tuning(knob) == min(times[name], key=times[name].get)
+        else:
+            assert name not in times

@@ -150,8 +150,17 @@ def test_tuning_settings():
     for v in (0, 1, 1 << 30):
         s.set_tuning(Schedule.TUNE_WAIT_POLLS, v)
         assert s.get_tuning(Schedule.TUNE_WAIT_POLLS) == v
+    assert s.get_tuning(Schedule.TUNE_EQ_ORDER) == 1
+    assert s.get_tuning(Schedule.TUNE_DYN_ORDER) == 2
+    assert s.get_tuning(Schedule.TUNE_TAP_TILES) == 16
+    for knob, vals in ((Schedule.TUNE_EQ_ORDER, (0, 1)), (Schedule.TUNE_DYN_ORDER, (0, 1, 2)),
+                       (Schedule.TUNE_TAP_TILES, (4, 8, 16))):
+        for v in vals:
+            s.set_tuning(knob, v)
+            assert s.get_tuning(knob) == v
     assert s.workspace_bytes(3 * 2048 + 5, True) == before
-    for knob, v in ((0, 3), (0, 0), (7, 1), (1, 0), (1, 17), (2, -1), (2, (1 << 30) + 1)):
+    for knob, v in ((0, 3), (0, 0), (7, 1), (1, 0), (1, 17), (2, -1), (2, (1 << 30) + 1),
+                    (3, 2), (3, -1), (4, 3), (4, -1), (5, 0), (5, 2), (5, 32), (6, 0)):
         with pytest.raises(GrafxError) as e:
             s.set_tuning(knob, v)
         assert e.value.status == "GRAFX_E_ARG"
