@@ -9,6 +9,8 @@ written to be checked against the paper by eye:
                  read/write index lists.
 * `processors` -- each differentiable processor (Sec. 3, Eqs. 2-5, 8-12, 14) plus tanh
                  distortion, in torch float64.
+* `reverb`    -- the filtered-noise mid/side reverb (Sec. 3, Eqs. 6-7) and the delay-time
+                 surrogate with its straight-through gradient (Eq. 15).
 * `render`    -- the graph evaluated one node at a time in topological order (Sec. 2,
                  "Definitions", Eq. 1).
 * `mrstft`    -- the multi-resolution STFT loss used to drive gradient descent (Sec. 4).
@@ -19,4 +21,4 @@ Gradients come from torch autograd in float64. The oracle shares no code with th
 Parity status of every function is listed in the module that defines it; the only function
 without an independent pin is marked "parity unpinned" there.
 """
-from . import encoder, mrstft, processors, render, schedule  # noqa: F401
+from . import encoder, mrstft, processors, render, reverb, schedule  # noqa: F401

@@ -277,10 +277,41 @@ def delay_offsets(p: np.ndarray) -> np.ndarray:
     return d + DELAY_SLOT * np.arange(DELAY_TAPS)[None, :]
 
 
-def delay(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+def delay(u: torch.Tensor, p: torch.Tensor, surrogate: bool = False) -> torch.Tensor:
     """y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j]: per channel, five
-    integer delays, each followed by its own 39-tap zero-phase FIR. Delays are not
-    differentiable here (the surrogate gradient of Eq. 15 is not part of this path)."""
+    integer delays, each followed by its own 39-tap zero-phase FIR. The integer delays carry no
+    gradient; with `surrogate`, the phasors get the straight-through gradient of Eq. 15 (the
+    value is unchanged: see `_delay_surrogate_term`)."""
+    y = _delay_exact(u, p)
+    if surrogate:
+        s = _delay_surrogate_term(u.detach(), p)
+        y = y + (s - s.detach())
+    return y
+
+
+def _delay_surrogate_term(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """The delay with each slot's integer delay replaced by the real part of the surrogate
+    impulse of its phasor (oracle.reverb.surrogate; 4410 lags from the slot's start), filter
+    taps and input held constant: its gradient with respect to the phasors is the
+    straight-through gradient."""
+    from .reverb import surrogate as surr  # the surrogate lives with the other Eq. 15 helpers
+    q = p.reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
+    span = DELAY_TAPS * DELAY_SLOT + 38
+    ys = []
+    for c in range(2):
+        K = torch.zeros(span, dtype=F64)
+        for m in range(DELAY_TAPS):
+            z = torch.complex(q[c, m, 0], q[c, m, 1])
+            s = surr(z, DELAY_SLOT).real  # impulse at lag n within the slot, n = 0..4409
+            taps = zero_phase_fir(q[c, m, 2:].detach(), 39)
+            cs = torch.nn.functional.conv1d(s.view(1, 1, -1), taps.flip(0).view(1, 1, -1),
+                                            padding=38).view(-1)  # (taps * s)[0 .. 4410 + 37]
+            K = K + torch.nn.functional.pad(cs, (m * DELAY_SLOT, span - m * DELAY_SLOT - cs.shape[0]))
+        ys.append(linear_conv_centred(u[c:c + 1], K, -19)[0])  # index i at lag i - 19
+    return torch.stack(ys)
+
+
+def _delay_exact(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
     d = delay_offsets(p.detach().numpy())
     q = p.reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
     span = int(d.max()) + 39
@@ -308,4 +339,5 @@ def identity(u: torch.Tensor, p=None) -> torch.Tensor:
 
 PROCESS = {2: identity, 3: gain_pan, 4: eq, 5: compressor, 6: imager, 7: delay, 8: tanh_dist,
            9: noisegate, 10: compressor_ar, 1: identity}
-N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4, 10: 5}
+N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4, 10: 5, 11: 768}
+REVERB = 11  # the reverb takes its noise realisation besides u and p (oracle.reverb.reverb)

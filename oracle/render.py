@@ -23,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import processors
+from . import processors, reverb
 
 F64 = torch.float64
 IN, OUT = 0, 1
@@ -74,12 +74,21 @@ def as_params64(params: dict, requires_grad: bool = False) -> dict:
     return out
 
 
-def node_forward(t: int, u: torch.Tensor, p: torch.Tensor | None) -> torch.Tensor:
-    """One processor call on one node (Eq. 1a)."""
+def node_forward(t: int, u: torch.Tensor, p: torch.Tensor | None, reverb_noise=None,
+                 delay_surrogate: bool = False) -> torch.Tensor:
+    """One processor call on one node (Eq. 1a). A reverb needs the noise realisation
+    [2, L] (mid, side); `delay_surrogate` gives delay phasors their straight-through gradient."""
+    if t == processors.REVERB:
+        if reverb_noise is None:
+            raise ValueError("a reverb node needs the reverb noise realisation")
+        return reverb.reverb(u, p, reverb_noise)
+    if t == 7 and delay_surrogate:
+        return processors.delay(u, p, surrogate=True)
     return processors.PROCESS[t](u, p)
 
 
-def render(node_type, edges, sources, params: dict, order=None, keep_all: bool = False):
+def render(node_type, edges, sources, params: dict, order=None, keep_all: bool = False,
+           reverb_noise=None, delay_surrogate: bool = False):
     """Returns Y [n_out, 2, T] (output nodes in node order) and, if `keep_all`, the list of
     every node's output (None for unreachable entries is impossible: all nodes are visited).
 
@@ -110,7 +119,7 @@ def render(node_type, edges, sources, params: dict, order=None, keep_all: bool =
         if u is None:
             u = torch.zeros((2, T), dtype=F64)
         p = params[t][rows[v]] if processors.N_PARAMS[t] else None
-        y[v] = node_forward(t, u, p)
+        y[v] = node_forward(t, u, p, reverb_noise, delay_surrogate)
     outs = [v for v in range(V) if int(node_type[v]) == OUT]
     Y = torch.stack([y[v] for v in outs])
     return (Y, y) if keep_all else Y

@@ -24,13 +24,17 @@ import numpy as np
 
 FS = 44100
 
-IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE, COMP_AR = range(11)
+IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE, COMP_AR, REVERB = range(12)
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
-              "noisegate", "compressor_ar")
+              "noisegate", "compressor_ar", "reverb")
 NUM_TYPES = len(TYPE_NAMES)
 TYPE_CODES = {n: i for i, n in enumerate(TYPE_NAMES)}
 # parameters per node of each type (0 for in/out/mix)
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5)
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768)
+# reverb: noise realisation of 2 s (mid, side); parameters [mid, side][H0, HD][192 bins]
+REVERB_LEN = 2 * FS
+REVERB_BINS = 192
+REVERB_HOP = 192
 
 # delay layout: [channel 2][tap 5][re z, im z, 20 log-magnitudes]
 DELAY_TAPS = 5
@@ -38,7 +42,7 @@ DELAY_SLOT = 4410  # 100 ms at 44.1 kHz
 DELAY_BINS = 20
 
 # random streams
-S_STRUCT, S_SOURCE, S_PARAM, S_TARGET, S_ADJOINT = 0, 1, 2, 3, 4
+S_STRUCT, S_SOURCE, S_PARAM, S_TARGET, S_ADJOINT, S_NOISE = 0, 1, 2, 3, 4, 5
 
 
 def rng_for(seed: int, stream: int, index: int = 0) -> np.random.Generator:
@@ -194,9 +198,36 @@ def delay_params(rng, n, max_ms=500.0):
     return out.reshape(n, 2 * DELAY_TAPS * (2 + DELAY_BINS)).astype(np.float32)
 
 
+def reverb_params(rng, n):
+    """Mid and side masks of the filtered-noise reverb, per one-sided bin k (k fs / 384 Hz) of
+    the 384-point STFT: initial colouration H0 = a level U[-40, -30] dB (mid; side 3 to 9 dB
+    lower) plus +-3 dB per six log-spaced bands, interpolated like the EQ; decay per 192-sample
+    frame HD = -ln(1000) 192 / (fs RT60(f)) with RT60(f) = RT60_0 / (1 + f / 8 kHz) and
+    RT60_0 U[0.3, 1.5] s (60 dB of decay over RT60). Natural-log units."""
+    f = np.arange(REVERB_BINS) * FS / 384.0
+    centres = 20.0 * 1000.0 ** ((np.arange(6) + 0.5) / 6)
+    lf = np.log(np.maximum(f, 1e-3))
+    out = np.empty((n, 2, 2, REVERB_BINS), dtype=np.float64)
+    for i in range(n):
+        level = rng.uniform(-40.0, -30.0)
+        rt0 = rng.uniform(0.3, 1.5)
+        for x in range(2):
+            lv = level - (rng.uniform(3.0, 9.0) if x == 1 else 0.0)
+            ripple = np.interp(lf, np.log(centres), rng.uniform(-3.0, 3.0, size=6))
+            out[i, x, 0] = (lv + ripple) * LN10_20
+            rt = rt0 * rng.uniform(0.9, 1.1) / (1.0 + f / 8000.0)
+            out[i, x, 1] = -math.log(1000.0) * REVERB_HOP / (FS * rt)
+    return out.reshape(n, 4 * REVERB_BINS).astype(np.float32)
+
+
+def reverb_noise(seed: int, length: int = REVERB_LEN) -> np.ndarray:
+    """The reverb's noise realisation [2, length] (mid, side): uniform in [-1, 1)."""
+    return rng_for(seed, S_NOISE).uniform(-1.0, 1.0, size=(2, length)).astype(np.float32)
+
+
 PARAM_DRAW = {GAIN_PAN: gain_pan_params, EQ: eq_params, COMP: comp_params,
               IMAGER: imager_params, DELAY: delay_params, TANH: tanh_params, GATE: gate_params,
-              COMP_AR: comp_ar_params}
+              COMP_AR: comp_ar_params, REVERB: reverb_params}
 
 
 def draw_params(rng: np.random.Generator, graph: Graph) -> dict[int, np.ndarray]:
@@ -227,6 +258,9 @@ def default_params(graph: Graph) -> dict[int, np.ndarray]:
             p[:, 2] = -20.0 * LN10_10
             p[:, 3] = 3.0 * LN10_10
             p[:, 4] = 1.0
+        elif t == REVERB:  # -40 dB, about 1 s of decay (60 dB)
+            p.reshape(n, 2, 2, REVERB_BINS)[:, :, 0] = -40.0 * LN10_20
+            p.reshape(n, 2, 2, REVERB_BINS)[:, :, 1] = -math.log(1000.0) * REVERB_HOP / FS
         out[t] = p
     return out
 
