@@ -338,9 +338,9 @@ grafx_status grafx_render_backward_step(const grafx_schedule_t* sched, const voi
  * per-sample arithmetic or the workspace size.
  *   GRAFX_TUNE_POINTWISE_UNROLL: 1024-sample parts per block of the pointwise kernels (mix, out,
  *     gain_pan, imager, tanh): 1 (default), 2 or 4.
- *   GRAFX_TUNE_EQ_ORDER: order of the EQ kernels' blocks: 0 maps the tiles of one node onto one
- *     XCD (neighbouring tiles share their halo through its L2), 1 (default) keeps the hardware's
- *     round-robin order. Same bits either way.
+ *   GRAFX_TUNE_EQ_ORDER: order of the EQ kernels' blocks: 0 (default) maps the tiles of one node
+ *     onto one XCD (neighbouring tiles share their halo through its L2), 1 keeps the hardware's
+ *     round-robin order (another XCD then fetches the halo again). Same bits either way.
  *   GRAFX_TUNE_DYN_ORDER: order of the dynamics kernels' blocks (compressor, noisegate,
  *     compressor_ar): 0 issues a node's chunks contiguously, 1 interleaves the step's nodes block
  *     by block, so that a chunk's predecessors have usually published by the time it starts;

@@ -107,6 +107,7 @@ class Schedule:
     TUNE_EQ_ORDER = 3
     TUNE_DYN_ORDER = 4
     TUNE_TAP_TILES = 5
+    TUNE_EQ_GROUP = 6
 
     def set_tuning(self, knob: int, value: int) -> None:
         """A tuning setting of the schedule (see include/grafx.h, grafx_schedule_set_tuning)."""
@@ -153,6 +154,10 @@ def _param_list(sched: Schedule, P) -> list:
     out = [None] * NUM_TYPES
     for k, v in (P or {}).items():
         t = TYPE_CODES[k] if isinstance(k, str) else int(k)
+        if not 0 <= t < NUM_TYPES:
+            if v is not None and v.shape[0] == 0:
+                continue  # an empty tensor of a type the library has no node of
+            raise ValueError(f"unknown node type {t}")
         out[t] = v
     for t in range(NUM_TYPES):
         if N_PARAMS[t] and sched.type_count[t] > 0:

@@ -24,7 +24,7 @@ CANDIDATES = (1, 2, 4)
 # setting -> (node types whose steps it shapes, candidate values; the first is the default)
 KNOBS = {
     Schedule.TUNE_POINTWISE_UNROLL: (POINTWISE_TYPES, CANDIDATES),
-    Schedule.TUNE_EQ_ORDER: ((4,), (1, 0)),
+    Schedule.TUNE_EQ_ORDER: ((4,), (0, 1)),
     Schedule.TUNE_DYN_ORDER: ((5, 9, 10), (2, 1, 0)),
     Schedule.TUNE_TAP_TILES: ((7,), (16, 8, 4)),
 }

@@ -49,7 +49,7 @@ struct grafx_schedule_t {
   int32_t pw_unroll = 1;           // tuning: pointwise 1024-sample parts per block
   int32_t ar_max_pass = 16;        // attack/release forward: branch-pattern passes (1..16)
   int32_t wait_polls = 1 << 24;    // dynamics kernels: polls of a chunk wait before giving up
-  int32_t eq_order = 1;            // tuning: EQ block order (0 XCD-contiguous, 1 hardware order)
+  int32_t eq_order = 0;            // tuning: EQ block order (0 XCD-contiguous, 1 hardware order)
   int32_t dyn_order = 2;           // tuning: dynamics block order (0 node-major, 1 interleaved,
                                    // 2 interleaved only for launches of many blocks)
   int32_t tap_tiles = 16;          // tuning: delay tiles per tap-gradient block (4, 8 or 16)

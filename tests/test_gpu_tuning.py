@@ -146,11 +146,11 @@ def test_merged_graphs_keep_their_bits_under_tap_tiles():
             super().__init__(*a, **k)
             self.set_tuning(Schedule.TUNE_TAP_TILES, 4)
             self.set_tuning(Schedule.TUNE_DYN_ORDER, 0)
-            self.set_tuning(Schedule.TUNE_EQ_ORDER, 0)
+            self.set_tuning(Schedule.TUNE_EQ_ORDER, 1)
 
     B.Schedule = Tuned
     try:
-        B._check_merged(ws, "tap tiles 4, node-major dynamics, XCD-contiguous EQ")
+        B._check_merged(ws, "tap tiles 4, node-major dynamics, hardware EQ order")
     finally:
         B.Schedule = orig
 

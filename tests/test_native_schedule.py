@@ -150,10 +150,10 @@ def test_tuning_settings():
     for v in (0, 1, 1 << 30):
         s.set_tuning(Schedule.TUNE_WAIT_POLLS, v)
         assert s.get_tuning(Schedule.TUNE_WAIT_POLLS) == v
-    assert s.get_tuning(Schedule.TUNE_EQ_ORDER) == 1
+    assert s.get_tuning(Schedule.TUNE_EQ_ORDER) == 0
     assert s.get_tuning(Schedule.TUNE_DYN_ORDER) == 2
     assert s.get_tuning(Schedule.TUNE_TAP_TILES) == 16
-    for knob, vals in ((Schedule.TUNE_EQ_ORDER, (0, 1)), (Schedule.TUNE_DYN_ORDER, (0, 1, 2)),
+    for knob, vals in ((Schedule.TUNE_EQ_ORDER, (1, 0)), (Schedule.TUNE_DYN_ORDER, (0, 1, 2)),
                        (Schedule.TUNE_TAP_TILES, (4, 8, 16))):
         for v in vals:
             s.set_tuning(knob, v)
