@@ -44,14 +44,14 @@ FP32_VALU_TFLOPS = 78.6
 EQ_FFT = 4096
 WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "large_console",
              "batch": "batched_graphs", "console_ar": "mixing_console",
-             "learned_init": "labelled_tiny_consoles"}
+             "learned_init": "labelled_tiny_consoles", "reverb": "reverb_console"}
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
-              "noisegate", "compressor_ar")
+              "noisegate", "compressor_ar", "reverb")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
 KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
               "imager": "k_pointwise.hip", "tanh": "k_pointwise.hip", "eq": "k_eq.hip",
               "compressor": "k_comp.hip", "noisegate": "k_comp.hip", "compressor_ar": "k_comp_ar.hip",
-              "delay": "k_delay.hip"}
+              "delay": "k_delay.hip", "reverb": "k_reverb.hip"}
 
 
 def parse():
@@ -117,6 +117,7 @@ def _len(sched, i: int, T: int) -> int:
 
 
 DELAY_FMA = 2 * 5 * 39  # per stereo sample: 2 channels x 5 taps x 39-tap FIR
+RV_BLOCK, RV_HALF = 2048, 2049  # reverb output block, one-sided bins of its 4096-point transforms
 
 
 def step_flops(sched, n: int, T: int, backward: bool) -> float:
@@ -126,6 +127,8 @@ def step_flops(sched, n: int, T: int, backward: bool) -> float:
     the spectral product and the complex cross-spectrum accumulation. Delay: 2 flops per FMA of
     the 5 x 39-tap filters per channel, once forward, twice backward (input adjoint and tap
     gradients)."""
+    if int(sched.step_type[n]) == 11:
+        return reverb_flops(sched, n, T, backward)
     if int(sched.step_type[n]) == 7:
         samples = sum(_len(sched, i, T) for i in range(int(sched.step_ptr[n]),
                                                          int(sched.step_ptr[n + 1])))
@@ -135,6 +138,22 @@ def step_flops(sched, n: int, T: int, backward: bool) -> float:
     fft = 5.0 * EQ_FFT * np.log2(EQ_FFT)
     per_tile = 3 * fft + 2 * EQ_FFT + 8 * EQ_FFT if backward else 2 * fft + 2 * EQ_FFT
     return tiles * per_tile
+
+
+def reverb_flops(sched, n: int, T: int, backward: bool) -> float:
+    """Reverb step (partitioned overlap-save with 2048-tap partitions): per output block one
+    4096-point FFT and one inverse (5 N log2 N each) and, for each partition in reach, the
+    per-channel complex multiply-add of 2049 one-sided bins (2 x 8 flops); the adjoint does the
+    same (its FIR-gradient cross-spectra run once after the last step and are not counted)."""
+    L = sched.reverb_len
+    parts = -(-L // RV_BLOCK)
+    fft = 5.0 * EQ_FFT * np.log2(EQ_FFT)
+    total = 0.0
+    for i in range(int(sched.step_ptr[n]), int(sched.step_ptr[n + 1])):
+        nb = -(-_len(sched, i, T) // RV_BLOCK)
+        pairs = sum(min(parts, b + 1) for b in range(nb))  # same count forward and adjoint
+        total += nb * 2 * fft + pairs * RV_HALF * 16
+    return total
 
 
 def stored_traffic(kernel_type: str, direction: str, workload: str):
@@ -189,18 +208,20 @@ def cpu_baseline(maker, T_full: int, seed_T: int, min_seconds: float = 8.0, max_
     # one untimed pass on a short signal first (thread pool and FFT plan set-up)
     wu = maker(T=4096)
     Pu = OR.as_params64(wu.params, requires_grad=True)
-    Lu = OM.mrstft(OR.render(wu.graph.node_type, wu.graph.edges, wu.sources, Pu),
+    Lu = OM.mrstft(OR.render(wu.graph.node_type, wu.graph.edges, wu.sources, Pu,
+                             reverb_noise=wu.reverb_noise),
                    torch.as_tensor(wu.sources[:1], dtype=torch.float64))
     torch.autograd.grad(Lu, [Pu[t] for t in Pu if Pu[t].shape[0] > 0])
     w = maker(T=seed_T)
     g = w.graph
     P = OR.as_params64(w.params, requires_grad=True)
     with torch.no_grad():
-        tgt = OR.render(g.node_type, g.edges, w.sources, OR.as_params64(w.target_params))
+        tgt = OR.render(g.node_type, g.edges, w.sources, OR.as_params64(w.target_params),
+                        reverb_noise=w.reverb_noise)
     keys = [t for t in P if P[t].shape[0] > 0]
 
     def step():
-        Y = OR.render(g.node_type, g.edges, w.sources, P)
+        Y = OR.render(g.node_type, g.edges, w.sources, P, reverb_noise=w.reverb_noise)
         L = OM.mrstft(Y, tgt)
         torch.autograd.grad(L, [P[t] for t in keys])
 
@@ -283,6 +304,8 @@ def setup_console(args, dev):
     t_s = time.perf_counter()
     sched = Schedule(g.node_type, g.edges, args.method)
     schedule_ms = (time.perf_counter() - t_s) * 1e3
+    if w.reverb_noise is not None:
+        sched.set_reverb_noise(torch.as_tensor(w.reverb_noise, device=dev))
     S = torch.as_tensor(w.sources, device=dev)
     P = {t: torch.as_tensor(p, device=dev).requires_grad_(True)
          for t, p in w.params.items() if p.shape[0] > 0}
@@ -578,15 +601,18 @@ def main():
                     "kernel": f"{tname} {d}", "launches": cnt,
                     "algorithmic_bytes_per_launch": round(b_tot / cnt),
                     "ms_per_launch": round(t_tot / cnt, 5)}
-        if tname in ("eq", "delay"):  # FFT / FIR arithmetic: also its flop rate
+        if tname in ("eq", "delay", "reverb"):  # FFT / FIR arithmetic: also its flop rate
             flops = sum(step_flops(sched, r["step"], T, d == "bwd") for r in table
                         if r["dir"] == d and r["type"] == tname)
             tf = flops / (t_tot * 1e-3) / 1e12
             roofline["alu_view"] = {
                 "achieved": round(tf, 2), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tf / FP32_VALU_TFLOPS, 4),
-                "count": "5 N log2 N flops per 4096-point complex FFT plus the spectral products"
-                         if tname == "eq" else "2 flops per FIR multiply-add",
+                "count": {"eq": "5 N log2 N flops per 4096-point complex FFT plus the spectral "
+                                "products",
+                          "delay": "2 flops per FIR multiply-add",
+                          "reverb": "5 N log2 N flops per 4096-point complex FFT plus 16 flops "
+                                    "per one-sided bin, partition and block"}[tname],
                 "peak_basis": "FP32 vector issue without packed-FP32 instructions"}
         all_t = sum(v[0] for v in agg.values())
         all_b = sum(v[1] for v in agg.values())

@@ -19,8 +19,9 @@
  * - Ownership: the caller owns all device memory (plan, signal buffers, workspaces, gradients);
  *   the library never allocates or frees device memory and never synchronises a stream (its one
  *   device array, the scratch of grafx_render_noalloc, is part of its code object). A
- *   schedule handle owns host memory only; it is immutable after creation and may be shared by
- *   threads and streams.
+ *   schedule handle owns host memory only; its graph and plan are immutable after creation, and
+ *   it may be shared by threads and streams. Its settings (tuning knobs, the reverb noise, the
+ *   delay-time gradient) are changed only by the grafx_schedule_set_* calls.
  * - Device work is enqueued on the caller's stream and runs asynchronously. Two calls that share
  *   a workspace must be ordered on one stream (or otherwise synchronised) by the caller.
  * - Signals are float32, stereo (C = 2), time-contiguous: a node's row is [2][T] (channel-major,
@@ -43,6 +44,8 @@
  *                     curve, ratio R >= 1 below T - W, quadratic knee   (Sec. 3 "Noisegate")
  *  10 compressor_ar 5 (alpha_a, alpha_r, T, W, R): the compressor with distinct attack and
  *                     release coefficients, alpha_a while x[t] > g[t-1]  (Eq. 8 unrestricted)
+ *  11 reverb     768  [mid, side][H0, HD][192 bins]: filtered-noise mid/side reverb (Eqs. 6-7),
+ *                     a causal stereo FIR made from the noise of grafx_schedule_set_reverb_noise
  * The node input is the sum over incoming edges of the source node outputs (Eq. 1b), parallel
  * edges counted once each, summed in original edge order.
  */
@@ -73,7 +76,7 @@ typedef enum grafx_status {
 enum {
   GRAFX_IN = 0, GRAFX_OUT = 1, GRAFX_MIX = 2, GRAFX_GAIN_PAN = 3, GRAFX_EQ = 4,
   GRAFX_COMPRESSOR = 5, GRAFX_IMAGER = 6, GRAFX_DELAY = 7, GRAFX_TANH = 8, GRAFX_NOISEGATE = 9,
-  GRAFX_COMPRESSOR_AR = 10, GRAFX_NUM_TYPES = 11
+  GRAFX_COMPRESSOR_AR = 10, GRAFX_REVERB = 11, GRAFX_NUM_TYPES = 12
 };
 
 /* Schedule search methods (paper Sec. 2 "Type scheduling"; Sec. 4 "Speed benchmark"). */
@@ -111,7 +114,7 @@ typedef struct grafx_schedule_sizes {
  * a width cap. Nodes are then reordered by (step, original id) ("sigma"), and the read/write
  * index lists are built as CSR arrays in that order.
  *
- *   num_nodes, node_type    host int32[num_nodes], codes 0..10 (the node types above)
+ *   num_nodes, node_type    host int32[num_nodes], codes 0..11 (the node types above)
  *   num_edges, edge_src/dst host int32[num_edges] each (may be NULL when num_edges == 0)
  *   edge_type               host int32[2*num_edges] or NULL; must be all zero (SISO graphs)
  *   method                  grafx_sched_method
@@ -371,6 +374,25 @@ enum {
 grafx_status grafx_schedule_set_tuning(grafx_schedule_t* sched, int32_t knob, int32_t value);
 grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* sched, int32_t knob,
                                        int32_t* value);
+
+/*
+ * grafx_schedule_set_reverb_noise -- the fixed noise realisation of the reverb (paper Sec. 3
+ * "Reverb": the impulse response is a noise signal shaped by the mask of Eq. 7 in the STFT
+ * domain, then turned from mid/side into left/right).
+ *
+ *   noise   device float32 [2][length]: the mid noise, then the side noise; every reverb node of
+ *           the schedule uses it. Borrowed, not copied: it must stay valid and unchanged while
+ *           any render or adjoint that uses the schedule runs. NULL (with length 0) clears it.
+ *   length  samples per signal, 1..GRAFX_REVERB_MAX_LEN; it is also the length of every reverb
+ *           node's FIR (2 s, 88200 samples, in the paper) and enters the workspace size, so set
+ *           it before grafx_workspace_bytes.
+ * Renders of a graph with reverb nodes fail with GRAFX_E_ARG while no noise is set.
+ * Errors: GRAFX_E_ARG (NULL schedule, NULL noise with a non-zero length), GRAFX_E_SHAPE (length
+ * out of range, noise not 4-byte aligned).
+ */
+#define GRAFX_REVERB_MAX_LEN ((int64_t)1 << 22)
+grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* sched, const float* noise,
+                                            int64_t length);
 
 /*
  * grafx_workspace_error -- the error word of the dynamics kernels (compressor, noisegate,

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgrafx.so")
 
-NUM_TYPES = 11
+NUM_TYPES = 12
 STATUS = {0: "GRAFX_OK", 1: "GRAFX_E_ARG", 2: "GRAFX_E_GRAPH", 3: "GRAFX_E_CYCLE",
           4: "GRAFX_E_TYPE", 5: "GRAFX_E_SHAPE", 6: "GRAFX_E_LIMIT", 7: "GRAFX_E_WORKSPACE",
           8: "GRAFX_E_HIP"}
@@ -25,7 +25,7 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
            "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
            "grafx_set_schedule_threads", "grafx_workspace_error", "grafx_last_error",
-           "grafx_render_noalloc")
+           "grafx_render_noalloc", "grafx_schedule_set_reverb_noise")
 
 
 class GrafxError(RuntimeError):
@@ -90,6 +90,7 @@ def load() -> ctypes.CDLL:
         "grafx_encoder_params": (i32, [i32, vp, vp, vp, vp, vp]),
         "grafx_schedule_set_tuning": (i32, [vp, i32, i32]),
         "grafx_schedule_get_tuning": (i32, [vp, i32, c_i32p]),
+        "grafx_schedule_set_reverb_noise": (i32, [vp, vp, i64]),
         "grafx_workspace_error": (i32, [vp, i64, vp, sz, vp, vp]),
         "grafx_last_error": (ctypes.c_char_p, []),
     }

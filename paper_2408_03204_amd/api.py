@@ -17,8 +17,8 @@ from . import _lib
 from ._lib import check, load
 
 TYPE_CODES = {"in": 0, "out": 1, "mix": 2, "gain_pan": 3, "eq": 4, "compressor": 5, "imager": 6,
-              "delay": 7, "tanh": 8, "noisegate": 9, "compressor_ar": 10}
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5)
+              "delay": 7, "tanh": 8, "noisegate": 9, "compressor_ar": 10, "reverb": 11}
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768)
 NUM_TYPES = _lib.NUM_TYPES
 METHODS = {"one_by_one": 0, "greedy": 1, "beam": 2, "optimal": 3}
 
@@ -79,6 +79,7 @@ class Schedule:
         self.len_sigma = None if lengths is None else ln[self.perm]
         self.out_begin = int(self.step_ptr[N])
         self._plans: dict = {}
+        self._rv_noise, self.reverb_len = None, 0  # set_reverb_noise
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -107,7 +108,6 @@ class Schedule:
     TUNE_EQ_ORDER = 3
     TUNE_DYN_ORDER = 4
     TUNE_TAP_TILES = 5
-    TUNE_EQ_GROUP = 6
 
     def set_tuning(self, knob: int, value: int) -> None:
         """A tuning setting of the schedule (see include/grafx.h, grafx_schedule_set_tuning)."""
@@ -117,6 +117,20 @@ class Schedule:
         v = ctypes.c_int32()
         check(load().grafx_schedule_get_tuning(self._h, knob, ctypes.byref(v)))
         return int(v.value)
+
+    def set_reverb_noise(self, noise) -> None:
+        """The reverb's noise realisation: a float32 CUDA tensor [2, L] (mid, side) shared by
+        every reverb node, or None to clear it. The schedule keeps a reference to the tensor,
+        which the library borrows (see grafx_schedule_set_reverb_noise)."""
+        if noise is None:
+            check(load().grafx_schedule_set_reverb_noise(self._h, None, 0))
+            self._rv_noise, self.reverb_len = None, 0
+            return
+        if not (torch.is_tensor(noise) and noise.is_cuda and noise.dtype == torch.float32
+                and noise.dim() == 2 and noise.shape[0] == 2 and noise.is_contiguous()):
+            raise ValueError("reverb noise must be a contiguous float32 CUDA tensor [2, L]")
+        check(load().grafx_schedule_set_reverb_noise(self._h, noise.data_ptr(), noise.shape[1]))
+        self._rv_noise, self.reverb_len = noise, int(noise.shape[1])
 
     def workspace_bytes(self, T: int, with_backward: bool) -> int:
         n = ctypes.c_size_t()

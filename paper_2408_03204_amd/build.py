@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgrafx.so")
 
 SOURCES = ["schedule.cpp", "driver.hip", "k_pointwise.hip", "k_eq.hip", "k_comp.hip",
-           "k_comp_ar.hip", "k_delay.hip", "k_mrstft.hip", "k_encoder.hip"]
+           "k_comp_ar.hip", "k_delay.hip", "k_reverb.hip", "k_mrstft.hip", "k_encoder.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

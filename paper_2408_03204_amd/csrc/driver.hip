@@ -25,9 +25,11 @@ namespace {
 struct WsLayout {
   size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps, delay_offs;
   size_t ar_slots, ar_carry, ar_pat, ar_tickets;
+  size_t rv_Un, rv_h, rv_H, rv_Z;
   size_t fwd_end;
   size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part;
   size_t ar_ragg, ar_part;
+  size_t rv_Y0, rv_G, rv_hbar, rv_part;
   size_t total;
 };
 
@@ -67,6 +69,17 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   L.ar_carry = take(n_ar * chunks * sizeof(double));
   L.ar_pat = take(n_ar * chunks * kBlock * sizeof(uint16_t));
   L.ar_tickets = take(2 * n_ar * kCompTicketStride * sizeof(unsigned));
+  // reverb: noise STFT (shared), FIRs, partition spectra, input-window spectra (kept for the
+  // FIR gradient)
+  const size_t n_rv = h->type_count[GRAFX_REVERB];
+  const size_t rv_L = n_rv ? (size_t)h->rv_len : 0;
+  const size_t rv_M = n_rv ? (size_t)rv_frames(h->rv_len) : 0;
+  const size_t rv_P = n_rv ? (size_t)rv_parts(h->rv_len) : 0;
+  const size_t rv_nb = n_rv ? (size_t)rv_blocks(T) : 0;
+  L.rv_Un = take(2 * rv_M * (kRvFft / 2 + 1) * sizeof(double2));
+  L.rv_h = take(n_rv * 2 * rv_L * sizeof(float));
+  L.rv_H = take(n_rv * rv_P * kRvStride * sizeof(float4));
+  L.rv_Z = take(n_rv * rv_nb * kRvStride * sizeof(float4));
   L.fwd_end = off;
   if (with_bwd) {
     const size_t tiles = pointwise_tiles(T);
@@ -83,6 +96,10 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.delay_part = take(n_del * delay_groups(T, kTapTilesMin) * kDelayCoef * sizeof(float));
     L.ar_ragg = take(n_ar * chunks * 2 * sizeof(uint64_t));
     L.ar_part = take(n_ar * chunks * kArParams * sizeof(double));
+    L.rv_Y0 = take(n_rv * rv_nb * kRvStride * sizeof(float4));
+    L.rv_G = take(n_rv * rv_P * kRvStride * sizeof(float4));
+    L.rv_hbar = take(n_rv * 2 * rv_L * sizeof(float));
+    L.rv_part = take(n_rv * 2 * rv_M * (kRvFft / 2 + 1) * sizeof(double));
   }
   L.total = off;
   return L;
@@ -137,6 +154,9 @@ grafx_status check_common(const grafx_schedule_t* h, const void* dev_plan, int64
   for (int t = 0; t < kNumTypes; ++t)
     if (kParamCount[t] > 0 && h->type_count[t] > 0 && (!P || !P[t]))
       return fail(GRAFX_E_SHAPE, "missing parameter tensor for node type " + std::to_string(t));
+  if (h->type_count[GRAFX_REVERB] > 0 && !h->rv_noise)
+    return fail(GRAFX_E_ARG,
+                "the graph has reverb nodes but no noise was set (grafx_schedule_set_reverb_noise)");
   const WsLayout L = ws_layout(h, T, with_bwd);
   if (L.total > 0 && (!ws || ws_bytes < L.total))
     return fail(GRAFX_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
@@ -228,6 +248,9 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
                                 at<double>(ws, L.ar_carry), at<uint16_t>(ws, L.ar_pat),
                                 at<unsigned>(ws, L.ar_tickets), error_word(ws, L), stream);
     }
+    case GRAFX_REVERB:
+      return launch_rv_fwd(g, U, b, cnt, h->rv_len, at<float4>(ws, L.rv_H), at<float4>(ws, L.rv_Z),
+                           stream);
     default:
       return hipErrorInvalidValue;
   }
@@ -266,6 +289,9 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
                                 at<unsigned>(ws, L.ar_tickets) +
                                     (size_t)h->type_count[GRAFX_COMPRESSOR_AR] * kCompTicketStride,
                                 error_word(ws, L), stream);
+    case GRAFX_REVERB:
+      return launch_rv_bwd(g, dU, b, cnt, h->rv_len, at<float4>(ws, L.rv_H),
+                           at<float4>(ws, L.rv_Y0), stream);
     default:
       return hipErrorInvalidValue;
   }
@@ -292,6 +318,10 @@ grafx_status enqueue_render(const grafx_schedule_t* h, const void* dev_plan, int
   if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
     e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
                             at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
+  if (e == hipSuccess && h->type_count[GRAFX_REVERB] > 0)
+    e = launch_rv_design(par(GRAFX_REVERB), h->type_count[GRAFX_REVERB], h->rv_noise, h->rv_len,
+                         at<double2>(ws, L.rv_Un), at<float>(ws, L.rv_h), at<float4>(ws, L.rv_H),
+                         stream);
   if (e == hipSuccess) e = reset_comp(h, ws, L, false, T, stream);
   if (e == hipSuccess) e = reset_ar(h, ws, L, false, T, stream);
   for (int n = 1; n <= h->N && e == hipSuccess; ++n)
@@ -426,6 +456,11 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
                           h->type_count[GRAFX_DELAY], delay_groups(T, h->tap_tiles),
                           dpar(GRAFX_DELAY), stream);
+  if (e == hipSuccess && dpar(GRAFX_REVERB))
+    e = launch_rv_grad(h->type_count[GRAFX_REVERB], T, h->rv_len, par(GRAFX_REVERB),
+                       at<double2>(ws, L.rv_Un), at<float4>(ws, L.rv_Z), at<float4>(ws, L.rv_Y0),
+                       at<float4>(ws, L.rv_G), at<float>(ws, L.rv_hbar), at<double>(ws, L.rv_part),
+                       dpar(GRAFX_REVERB), stream);
   return hip_status(e, "render_backward launch");
 }
 
@@ -502,6 +537,24 @@ grafx_status grafx_schedule_set_tuning(grafx_schedule_t* h, int32_t knob, int32_
     default:
       return fail(GRAFX_E_ARG, "unknown tuning knob");
   }
+}
+
+grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* h, const float* noise,
+                                            int64_t length) {
+  clear_error();
+  if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
+  if (!noise) {
+    if (length != 0) return fail(GRAFX_E_ARG, "a NULL noise needs length 0");
+    h->rv_noise = nullptr;
+    h->rv_len = 0;
+    return GRAFX_OK;
+  }
+  if (length < 1 || length > kRvMaxLen)
+    return fail(GRAFX_E_SHAPE, "reverb noise length must be in 1.." + std::to_string(kRvMaxLen));
+  if (!aligned(noise, 4)) return fail(GRAFX_E_SHAPE, "reverb noise must be 4-byte aligned");
+  h->rv_noise = noise;
+  h->rv_len = length;
+  return GRAFX_OK;
 }
 
 grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* h, int32_t knob, int32_t* value) {

@@ -11,7 +11,8 @@
 namespace grafx {
 
 constexpr int kNumTypes = GRAFX_NUM_TYPES;
-constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5};
+constexpr int64_t kRvMaxLen = GRAFX_REVERB_MAX_LEN;
+constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768};
 
 // Thread-local error message, set by every failing entry point.
 grafx_status fail(grafx_status code, const std::string& msg);
@@ -53,6 +54,8 @@ struct grafx_schedule_t {
   int32_t dyn_order = 2;           // tuning: dynamics block order (0 node-major, 1 interleaved,
                                    // 2 interleaved only for launches of many blocks)
   int32_t tap_tiles = 16;          // tuning: delay tiles per tap-gradient block (4, 8 or 16)
+  const float* rv_noise = nullptr; // reverb noise realisation (device, [2][rv_len]; borrowed)
+  int64_t rv_len = 0;              // its length: the reverb FIR length
   grafx::PlanLayout layout{};
   std::vector<int32_t> plan;       // packed host image of the device plan
 };

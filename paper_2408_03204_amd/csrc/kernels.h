@@ -112,6 +112,35 @@ hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
 hipError_t launch_delay_grad(const float* P, const float* part, int n, int groups, float* dP,
                              hipStream_t s);
 
+// ---- reverb (k_reverb.hip) ------------------------------------------------------------------
+constexpr int kRvFft = 384, kRvHop = 192;  // STFT of the noise and of the masks
+constexpr int kRvBins = 192;               // parameterised one-sided bins (bin 192 takes 191's)
+constexpr int kRvParams = 4 * kRvBins;     // [mid, side][H0, HD][bins] = 768
+constexpr int kRvBlock = 2048;             // FIR partition length and output block length
+constexpr int kRvHalf = 2049;              // one-sided bins of the 4096-point block transforms
+constexpr int kRvStride = 2064;            // float4 entries per stored spectrum (256-byte rows)
+int rv_frames(int64_t L);  // STFT frames of an L-sample noise
+int rv_parts(int64_t L);   // FIR partitions of an L-tap response
+int rv_blocks(int64_t T);  // output blocks of a T-sample row
+// noise: float [2][L] (mid, side); Un: double2 [2][frames][193] (noise STFT); h: float
+// [n][2][L] (left, right FIR); Hs: float4 [n][parts][kRvStride] (per-channel one-sided partition
+// spectra (left re, left im, right re, right im), scaled by 1 / 4096)
+hipError_t launch_rv_design(const float* P, int n, const float* noise, int64_t L, double2* Un,
+                            float* h, float4* Hs, hipStream_t s);
+// Z: float4 [n][blocks][kRvStride] per-channel one-sided spectra of the input windows (kept for
+// the adjoint)
+hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nodes, int64_t L,
+                         const float4* Hs, float4* Z, hipStream_t s);
+// Y0: float4 [n][blocks][kRvStride] spectra of the output-adjoint blocks (kept for the FIR
+// gradient)
+hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
+                         const float4* Hs, float4* Y0, hipStream_t s);
+// After the last adjoint step, every reverb slot: Gs: float4 [n][parts][kRvStride] partition
+// cross-spectra; hbar: float [n][2][L]; part: double [n][2][frames][193]; dP: float [n][768]
+hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const double2* Un,
+                          const float4* Z, const float4* Y0, float4* Gs, float* hbar,
+                          double* part, float* dP, hipStream_t s);
+
 // ---- MRSTFT loss (k_mrstft.hip) -------------------------------------------------------------
 size_t mrstft_ws_bytes(int rows, int64_t T);
 hipError_t launch_mrstft_loss(int rows, int64_t T, const float* Y, const float* tgt, float* loss,

@@ -282,13 +282,14 @@ def _track_chains(rng, n_tracks, pool, kmin, kmax):
 
 
 def console_graph(rng, n_tracks: int, bus_levels: list[int], pool=CHAIN_POOL_C2, kmin=1,
-                  kmax=3, master_chain=(EQ, COMP, GAIN_PAN)) -> Graph:
-    """Mixing console: per track in -> random processor chain -> level-1 bus; each bus is
-    mix -> eq -> compressor; buses feed the next level; the master is
+                  kmax=3, master_chain=(EQ, COMP, GAIN_PAN), track_tail=()) -> Graph:
+    """Mixing console: per track in -> random processor chain (+ `track_tail`) -> level-1 bus;
+    each bus is mix -> eq -> compressor; buses feed the next level; the master is
     mix -> master_chain -> out. `bus_levels` lists the bus count per level (top level last)."""
     g = GraphBuilder()
     ends = []
     for chain in _track_chains(rng, n_tracks, pool, kmin, kmax):
+        chain = chain + list(track_tail)
         i = g.add(IN)
         if chain:
             a, b = g.chain(chain)
@@ -321,6 +322,7 @@ class Workload:
     target_params: dict | None
     T: int
     seed: int
+    reverb_noise: np.ndarray | None = None  # [2, L] float32 when the graph has reverb nodes
 
     @property
     def processed_nodes(self) -> int:
@@ -436,6 +438,17 @@ def large_console(seed=5, T=2 ** 20, n_tracks=256) -> Workload:
                     make_sources(rng_for(seed, S_SOURCE), K, T),
                     draw_params(rng_for(seed, S_PARAM), graph),
                     draw_params(rng_for(seed, S_TARGET), graph), T, seed)
+
+
+def reverb_console(seed=3, T=2 ** 18, n_tracks=64, n_bus=8) -> Workload:
+    """The 64-track console with a reverb closing every track chain (64 reverbs, 2 s noise)."""
+    graph = console_graph(rng_for(seed, S_STRUCT), n_tracks, [n_bus], track_tail=(REVERB,))
+    K = graph.count(IN)
+    return Workload(f"reverb_console_{n_tracks}trk", graph,
+                    make_sources(rng_for(seed, S_SOURCE), K, T),
+                    draw_params(rng_for(seed, S_PARAM), graph),
+                    draw_params(rng_for(seed, S_TARGET), graph), T, seed,
+                    reverb_noise(seed))
 
 
 def output_adjoint(seed: int, n_out: int, T: int) -> np.ndarray:

@@ -32,7 +32,7 @@ def console():
 def params(sched, skip=None):
     arr = _lib.ptr_array()
     for t in range(_lib.NUM_TYPES):
-        if sched.type_count[t] and t != skip and t in (3, 4, 5, 6, 7, 8, 9, 10):
+        if sched.type_count[t] and t != skip and t in (3, 4, 5, 6, 7, 8, 9, 10, 11):
             arr[t] = addr(10 + t)
     return arr
 
@@ -184,3 +184,38 @@ def test_noalloc_render_refuses_a_workspace_beyond_its_scratch():
 def _has_device() -> bool:
     import torch
     return torch.cuda.device_count() > 0
+
+
+@pytest.fixture(scope="module")
+def reverb_sched():
+    b = synth.GraphBuilder()
+    i0 = b.add(synth.IN)
+    r = b.add(synth.REVERB)
+    b.connect(i0, r)
+    b.connect(r, b.add(synth.OUT))
+    g = b.build()
+    return Schedule(g.node_type, g.edges)
+
+
+def test_reverb_needs_its_noise(reverb_sched):
+    """A graph with reverb nodes renders only once a noise realisation is set; the noise length
+    is the FIR length and enters the workspace size; bad settings are refused."""
+    s = reverb_sched
+    lib = load()
+    assert s.type_count[synth.REVERB] == 1
+    assert lib.grafx_schedule_set_reverb_noise(s._h, None, 0) == OK
+    assert render(s) == E_ARG and "noise" in err()
+    assert lib.grafx_schedule_set_reverb_noise(None, addr(9), 100) == E_ARG
+    assert lib.grafx_schedule_set_reverb_noise(s._h, None, 100) == E_ARG
+    assert lib.grafx_schedule_set_reverb_noise(s._h, addr(9), 0) == E_SHAPE
+    assert lib.grafx_schedule_set_reverb_noise(s._h, addr(9), (1 << 22) + 1) == E_SHAPE
+    assert lib.grafx_schedule_set_reverb_noise(s._h, addr(9, 2), 100) == E_SHAPE
+    assert lib.grafx_schedule_set_reverb_noise(s._h, addr(9), 4000) == OK
+    short_ws = s.workspace_bytes(4096, True)
+    assert lib.grafx_schedule_set_reverb_noise(s._h, addr(9), 88200) == OK
+    long_ws = s.workspace_bytes(4096, True)
+    assert long_ws > short_ws
+    # with the noise set, the remaining checks are the render's own
+    assert render(s, P=params(s, skip=synth.REVERB)) == E_SHAPE and "11" in err()
+    assert render(s, nbytes=long_ws // 4) == E_WORKSPACE
+    assert lib.grafx_schedule_set_reverb_noise(s._h, None, 0) == OK
