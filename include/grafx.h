@@ -304,8 +304,8 @@ grafx_status grafx_render_noalloc(const grafx_schedule_t* sched, const void* dev
  *   dS       device float32 [K][2][T] or NULL: adjoint of the sources
  *   dP       host array of GRAFX_NUM_TYPES device pointers or NULL; dP[t] (same layout as P[t])
  *            receives the parameter gradient (overwritten, not accumulated); a NULL entry skips
- *            that type. Delay phasors (re z, im z) receive 0: the delay times are not
- *            differentiated.
+ *            that type. Delay phasors (re z, im z) receive 0 unless the delay-time surrogate is
+ *            on (grafx_schedule_set_delay_surrogate).
  */
 grafx_status grafx_render_backward(const grafx_schedule_t* sched, const void* dev_plan,
                                    int64_t T, const float* S, const float* const* P,
@@ -393,6 +393,21 @@ grafx_status grafx_schedule_get_tuning(const grafx_schedule_t* sched, int32_t kn
 #define GRAFX_REVERB_MAX_LEN ((int64_t)1 << 22)
 grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* sched, const float* noise,
                                             int64_t length);
+
+/*
+ * grafx_schedule_set_delay_surrogate -- the gradient of the delay times (paper Sec. 3 "Multitap
+ * delay", Eq. 15). With enable = 0 (the default) grafx_render_backward writes 0 to every delay
+ * phasor entry (re z, im z). With enable = 1 it writes the straight-through gradient of the
+ * surrogate: the render keeps the exact integer delay of each 100 ms slot, and the phasor z of the
+ * slot gets the gradient that the render would have if the slot's unit impulse were the real part
+ * of s[n] = (1/4410) sum_{k=0}^{4409} z^k exp(2 pi i k n / 4410), n = 0..4409 lags from the slot's
+ * start (the unit impulse at the integer delay when z lies on the unit circle at that delay).
+ * The paper's per-delay gradient normalisation and its unit-circle regulariser belong to the
+ * optimiser and are not applied here. The setting enters the adjoint's workspace size (spectra of
+ * every delay node's input and output adjoint), so set it before grafx_workspace_bytes.
+ * Errors: GRAFX_E_ARG (NULL schedule, enable not 0 or 1).
+ */
+grafx_status grafx_schedule_set_delay_surrogate(grafx_schedule_t* sched, int32_t enable);
 
 /*
  * grafx_workspace_error -- the error word of the dynamics kernels (compressor, noisegate,

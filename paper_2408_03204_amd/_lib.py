@@ -25,7 +25,8 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_encoder_sizes", "grafx_encoder_forward", "grafx_encoder_backward", "grafx_adam",
            "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
            "grafx_set_schedule_threads", "grafx_workspace_error", "grafx_last_error",
-           "grafx_render_noalloc", "grafx_schedule_set_reverb_noise")
+           "grafx_render_noalloc", "grafx_schedule_set_reverb_noise",
+           "grafx_schedule_set_delay_surrogate")
 
 
 class GrafxError(RuntimeError):
@@ -91,6 +92,7 @@ def load() -> ctypes.CDLL:
         "grafx_schedule_set_tuning": (i32, [vp, i32, i32]),
         "grafx_schedule_get_tuning": (i32, [vp, i32, c_i32p]),
         "grafx_schedule_set_reverb_noise": (i32, [vp, vp, i64]),
+        "grafx_schedule_set_delay_surrogate": (i32, [vp, i32]),
         "grafx_workspace_error": (i32, [vp, i64, vp, sz, vp, vp]),
         "grafx_last_error": (ctypes.c_char_p, []),
     }

@@ -132,6 +132,11 @@ class Schedule:
         check(load().grafx_schedule_set_reverb_noise(self._h, noise.data_ptr(), noise.shape[1]))
         self._rv_noise, self.reverb_len = noise, int(noise.shape[1])
 
+    def set_delay_surrogate(self, enable: bool) -> None:
+        """Straight-through gradient of the delay phasors through the delay-time surrogate
+        (see grafx_schedule_set_delay_surrogate); off by default (phasor gradients are 0)."""
+        check(load().grafx_schedule_set_delay_surrogate(self._h, int(bool(enable))))
+
     def workspace_bytes(self, T: int, with_backward: bool) -> int:
         n = ctypes.c_size_t()
         check(load().grafx_workspace_bytes(self._h, T, int(with_backward), ctypes.byref(n)))

@@ -30,6 +30,7 @@ struct WsLayout {
   size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part;
   size_t ar_ragg, ar_part;
   size_t rv_Y0, rv_G, rv_hbar, rv_part;
+  size_t dl_X, dl_Y0, dl_G, dl_R;
   size_t total;
 };
 
@@ -100,6 +101,13 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.rv_G = take(n_rv * rv_P * kRvStride * sizeof(float4));
     L.rv_hbar = take(n_rv * 2 * rv_L * sizeof(float));
     L.rv_part = take(n_rv * 2 * rv_M * (kRvFft / 2 + 1) * sizeof(double));
+    // delay-time surrogate: input-window and adjoint-block spectra, cross-spectra, correlation
+    const size_t n_sur = h->delay_surrogate ? n_del : 0;
+    const size_t sur_nb = n_sur ? (size_t)rv_blocks(T + kDelaySurShift) : 0;
+    L.dl_X = take(n_sur * sur_nb * kRvStride * sizeof(float4));
+    L.dl_Y0 = take(n_sur * sur_nb * kRvStride * sizeof(float4));
+    L.dl_G = take(n_sur * kDelaySurParts * kRvStride * sizeof(float4));
+    L.dl_R = take(n_sur * 2 * kDelaySurLen * sizeof(float));
   }
   L.total = off;
   return L;
@@ -279,9 +287,19 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
                              at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
                              tickets(ws, L, h, true), error_word(ws, L), stream);
-    case GRAFX_DELAY:
-      return launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs),
-                              b, cnt, at<float>(ws, L.delay_part), stream);
+    case GRAFX_DELAY: {
+      hipError_t e = launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps),
+                                      at<int32_t>(ws, L.delay_offs), b, cnt,
+                                      at<float>(ws, L.delay_part), stream);
+      // R[n] = sum_t ybar[t - 19] u[t - n]: lag n - 19 of the plain correlation
+      const int nb = rv_blocks(g.T + kDelaySurShift);
+      if (e == hipSuccess && h->delay_surrogate)
+        e = launch_xcorr_spectra(g, b, cnt, false, 0, nb, at<float4>(ws, L.dl_X), stream);
+      if (e == hipSuccess && h->delay_surrogate)
+        e = launch_xcorr_spectra(g, b, cnt, true, -kDelaySurShift, nb, at<float4>(ws, L.dl_Y0),
+                                 stream);
+      return e;
+    }
     case GRAFX_COMPRESSOR_AR:
       return launch_comp_ar_bwd(dyn_view(g, cnt), dU, p, b, cnt, at<double>(ws, L.ar_carry),
                                 at<uint16_t>(ws, L.ar_pat), at<uint64_t>(ws, L.ar_ragg),
@@ -456,6 +474,16 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
                           h->type_count[GRAFX_DELAY], delay_groups(T, h->tap_tiles),
                           dpar(GRAFX_DELAY), stream);
+  if (e == hipSuccess && dpar(GRAFX_DELAY) && h->delay_surrogate) {
+    const int n_del = h->type_count[GRAFX_DELAY];
+    e = launch_xcorr(n_del, rv_blocks(T + kDelaySurShift), kDelaySurParts, kDelaySurLen,
+                     at<float4>(ws, L.dl_Y0),
+                     at<float4>(ws, L.dl_X), at<float4>(ws, L.dl_G), at<float>(ws, L.dl_R),
+                     stream);
+    if (e == hipSuccess)
+      e = launch_delay_phasor_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_taps),
+                                   at<float>(ws, L.dl_R), n_del, dpar(GRAFX_DELAY), stream);
+  }
   if (e == hipSuccess && dpar(GRAFX_REVERB))
     e = launch_rv_grad(h->type_count[GRAFX_REVERB], T, h->rv_len, par(GRAFX_REVERB),
                        at<double2>(ws, L.rv_Un), at<float4>(ws, L.rv_Z), at<float4>(ws, L.rv_Y0),
@@ -554,6 +582,14 @@ grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* h, const float* n
   if (!aligned(noise, 4)) return fail(GRAFX_E_SHAPE, "reverb noise must be 4-byte aligned");
   h->rv_noise = noise;
   h->rv_len = length;
+  return GRAFX_OK;
+}
+
+grafx_status grafx_schedule_set_delay_surrogate(grafx_schedule_t* h, int32_t enable) {
+  clear_error();
+  if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");
+  if (enable != 0 && enable != 1) return fail(GRAFX_E_ARG, "enable must be 0 or 1");
+  h->delay_surrogate = enable;
   return GRAFX_OK;
 }
 

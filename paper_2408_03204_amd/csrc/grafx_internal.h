@@ -56,6 +56,7 @@ struct grafx_schedule_t {
   int32_t tap_tiles = 16;          // tuning: delay tiles per tap-gradient block (4, 8 or 16)
   const float* rv_noise = nullptr; // reverb noise realisation (device, [2][rv_len]; borrowed)
   int64_t rv_len = 0;              // its length: the reverb FIR length
+  int32_t delay_surrogate = 0;     // delay phasors: 0 no gradient, 1 straight-through surrogate
   grafx::PlanLayout layout{};
   std::vector<int32_t> plan;       // packed host image of the device plan
 };

@@ -9,7 +9,17 @@
 // Adjoint: the input adjoint is the correlation with the same taps (a separate launch), and the
 // tap gradient c-bar_{c,m}[j] = sum_t ybar_c[t] u_c[t - d - j] is accumulated per block over a
 // fixed group of tiles, reduced in a fixed order and mapped back to the log-magnitudes through
-// the design. The delay times themselves are not differentiated (their phasor gradients are 0).
+// the design. By default the delay times are not differentiated (their phasor gradients are 0).
+//
+// Delay-time surrogate (Sec. 3 "Multitap delay", Eq. 15), an option of the schedule: the phasor z
+// of slot m gets the straight-through gradient of the surrogate impulse
+// s[n] = Re (1/N) sum_{k<N} z^k e^(2 pi i k n / N) (N = 4410 lags from the slot's start), which is
+// the unit impulse at the slot's integer delay when z lies on the unit circle at that delay. With
+// G[n] = dL/ds[n] = sum_j c[j] R[4410 m + n + j - 19] (R[l] = sum_t ybar[t] u[t - l], the
+// cross-correlation of the output adjoint and the input, from the partitioned correlation of the
+// reverb's FIR gradient with the output adjoint delayed by 19 samples so that lags start at -19),
+// dL/dRe z = Re Q and dL/dIm z = -Im Q with Q = sum_n G[n] s'(z)[n]
+// = (1/N) sum_{k>=1} k z^(k-1) sum_n G[n] e^(2 pi i k n / N), all in double.
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
@@ -227,6 +237,69 @@ __global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, cons
   }
 }
 
+// Straight-through phasor gradient of one (node slot, channel x slot) pair: G into LDS, then Q as
+// above, each thread taking the k = 1 + thread, 1 + thread + 256, ... terms; the inner sum over n
+// steps the phasor e^(2 pi i k n / N) by multiplication, restarting from an exact value every 256
+// steps; per-thread partials are added in a fixed order.
+__global__ __launch_bounds__(kBlock) void delay_phasor_grad_kernel(const float* P,
+                                                                   const float* taps,
+                                                                   const float* R, int64_t Lr,
+                                                                   float* dP) {
+  __shared__ double G[kDelaySlot];
+  __shared__ double2 red[kBlock / 64];
+  const int slot = blockIdx.x, cm = blockIdx.y;  // cm = channel * 5 + slot
+  const int c = cm / kDelayTaps, m = cm % kDelayTaps;
+  const float* tp = taps + (int64_t)slot * kDelayCoef + cm * kDelayFir;
+  const float* Rc = R + ((int64_t)slot * 2 + c) * Lr + (int64_t)m * kDelaySlot;
+  for (int n = threadIdx.x; n < kDelaySlot; n += kBlock) {
+    double acc = 0.0;
+    for (int j = 0; j < kDelayFir; ++j) acc = fma((double)tp[j], (double)Rc[n + j], acc);
+    G[n] = acc;
+  }
+  __syncthreads();
+  const float* q = P + (int64_t)slot * kRow + cm * 22;
+  const double zr = q[0], zi = q[1];
+  const double lr = 0.5 * log(zr * zr + zi * zi), th = atan2(zi, zr);  // principal log z
+  double qr = 0.0, qi = 0.0;
+  for (int k = 1 + threadIdx.x; k < kDelaySlot; k += kBlock) {
+    double gr = 0.0, gi = 0.0, sr, si;  // the step e^(2 pi i k / N)
+    sincospi(2.0 * (double)k / kDelaySlot, &si, &sr);
+    for (int n0 = 0; n0 < kDelaySlot; n0 += 256) {
+      double wr, wi;  // e^(2 pi i k n0 / N), exactly
+      sincospi(2.0 * (double)(((int64_t)k * n0) % kDelaySlot) / kDelaySlot, &wi, &wr);
+      const int n1 = min(n0 + 256, kDelaySlot);
+      for (int n = n0; n < n1; ++n) {
+        gr = fma(G[n], wr, gr);
+        gi = fma(G[n], wi, gi);
+        const double t = wr * sr - wi * si;
+        wi = fma(wr, si, wi * sr);
+        wr = t;
+      }
+    }
+    // k z^(k - 1) = k exp((k - 1) log z)
+    double sn, cs;
+    sincos((double)(k - 1) * th, &sn, &cs);
+    const double mag = (double)k * exp((double)(k - 1) * lr);
+    const double ar = mag * cs, ai = mag * sn;
+    qr += ar * gr - ai * gi;
+    qi += ar * gi + ai * gr;
+  }
+  qr = wave_sum(qr);
+  qi = wave_sum(qi);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(qr, qi);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      sr += red[w].x;
+      si += red[w].y;
+    }
+    float* d = dP + (int64_t)slot * kRow + cm * 22;
+    d[0] = (float)(sr / kDelaySlot);
+    d[1] = (float)(-si / kDelaySlot);
+  }
+}
+
 }  // namespace
 
 int delay_tiles(int64_t T) { return (int)((T + kHop - 1) / kHop); }
@@ -265,6 +338,14 @@ hipError_t launch_delay_grad(const float* P, const float* part, int n, int group
                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
   delay_grad_kernel<<<n, kBlock, 0, s>>>(P, part, groups, dP);
+  return hipGetLastError();
+}
+
+hipError_t launch_delay_phasor_grad(const float* P, const float* taps, const float* R, int n,
+                                    float* dP, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  delay_phasor_grad_kernel<<<dim3(n, 2 * kDelayTaps), kBlock, 0, s>>>(P, taps, R, kDelaySurLen,
+                                                                      dP);
   return hipGetLastError();
 }
 

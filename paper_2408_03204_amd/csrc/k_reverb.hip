@@ -199,11 +199,12 @@ __global__ __launch_bounds__(kBlock) void rv_partition_kernel(const float* h, in
 }
 
 // ---- block spectra ----------------------------------------------------------------------------
-// ADJ false: input window [2048 b - 2048, 2048 b + 2048) of the node's input sum;
-// ADJ true: output-adjoint block [2048 b, 2048 b + 2048) in the second half of a zero window.
+// ADJ false: input window [2048 b - 2048 + shift, 2048 b + 2048 + shift) of the node's input sum;
+// ADJ true: output-adjoint block [2048 b + shift, 2048 b + 2048 + shift) in the second half of a
+// zero window. Stored at the node's parameter slot.
 template <bool ADJ>
 __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int node_begin, int nb,
-                                                            float4* out) {
+                                                            int shift, float4* out) {
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
   const int b = blockIdx.x, node = node_begin + blockIdx.y;
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int nod
   Twiddles tw;
   load_twiddles(tw, w1lds);
   float2 v[16];
-  gather_window<ADJ>(g, node, kB * b - kB, v, ADJ ? 8 : 0, 16);
+  gather_window<ADJ>(g, node, kB * b - kB + shift, v, ADJ ? 8 : 0, 16);
   fft4096<false>(v, lds, tw);
   store_separated(v, lds, out + ((int64_t)slot * nb + b) * kRvStride, 1.0f);
 }
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void rv_product_kernel(GraphView g, float* 
   }
 }
 
-// ---- FIR gradient -------------------------------------------------------------------------------
+// ---- FIR gradient (the partitioned cross-correlation) ---------------------------------------------
 // Cross-spectrum of partition p per channel, one-sided bins: G_c[k] = sum_{b >= p} Y0_c[b][k]
 // conj(X_c[b - p][k]), summed in block order in double, scaled by 1 / 4096.
 __global__ __launch_bounds__(kBlock) void rv_cross_kernel(int nb, int parts, const float4* Y0,
@@ -403,10 +404,28 @@ hipError_t launch_rv_design(const float* P, int n, const float* noise, int64_t L
   return hipGetLastError();
 }
 
+hipError_t launch_xcorr_spectra(const GraphView& g, int node_begin, int n_nodes, bool adj,
+                                int shift, int nb, float4* out, hipStream_t s) {
+  if (adj)
+    rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, shift, out);
+  else
+    rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, shift, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const float4* Y0, const float4* X,
+                        float4* Gs, float* R, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  rv_cross_kernel<<<dim3(parts, (kN / 2 + kBlock) / kBlock, n), kBlock, 0, s>>>(nb, parts, Y0, X,
+                                                                                 Gs);
+  rv_hbar_kernel<<<dim3(parts, n), kBlock, 0, s>>>(Gs, parts, len, R);
+  return hipGetLastError();
+}
+
 hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nodes, int64_t L,
                          const float4* Hs, float4* Z, hipStream_t s) {
   const int nb = rv_blocks(g.T), parts = rv_parts(L);
-  rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, Z);
+  rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Z);
   rv_product_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, U, node_begin, nb, parts, Z,
                                                                 Hs);
   return hipGetLastError();
@@ -415,7 +434,7 @@ hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nod
 hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
                          const float4* Hs, float4* Y0, hipStream_t s) {
   const int nb = rv_blocks(g.T), parts = rv_parts(L);
-  rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, Y0);
+  rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Y0);
   rv_product_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, dU, node_begin, nb, parts, Y0,
                                                                Hs);
   return hipGetLastError();
@@ -426,9 +445,8 @@ hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const dou
                           double* part, float* dP, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int nb = rv_blocks(T), parts = rv_parts(L), M = rv_frames(L);
-  rv_cross_kernel<<<dim3(parts, (kN / 2 + kBlock) / kBlock, n), kBlock, 0, s>>>(nb, parts, Y0, Z,
-                                                                                 Gs);
-  rv_hbar_kernel<<<dim3(parts, n), kBlock, 0, s>>>(Gs, parts, L, hbar);
+  const hipError_t e = launch_xcorr(n, nb, parts, L, Y0, Z, Gs, hbar, s);
+  if (e != hipSuccess) return e;
   rv_frame_grad_kernel<<<dim3(M, 2, n), kBlock, 0, s>>>(P, Un, hbar, L, M, part);
   rv_param_grad_kernel<<<dim3(n, 2), kBlock, 0, s>>>(part, M, dP);
   return hipGetLastError();

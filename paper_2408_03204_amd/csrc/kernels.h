@@ -111,6 +111,17 @@ hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
                             hipStream_t s);
 hipError_t launch_delay_grad(const float* P, const float* part, int n, int groups, float* dP,
                              hipStream_t s);
+// Delay-time surrogate: lags -19 .. 5 x 4410 + 19 of the input/adjoint cross-correlation (the
+// output adjoint delayed by kDelaySurShift, so that the lags start at 0), rounded up to whole
+// 2048-lag partitions
+constexpr int kDelaySurShift = (kDelayFir - 1) / 2;                       // 19
+constexpr int kDelaySurLags = kDelayTaps * kDelaySlot + kDelayFir - 1;    // 22088
+constexpr int kDelaySurParts = (kDelaySurLags + 2047) / 2048;             // 11
+constexpr int64_t kDelaySurLen = (int64_t)kDelaySurParts * 2048;
+// R: float [n][2][kDelaySurLen] correlation (launch_xcorr); writes the phasor entries of dP
+// (after launch_delay_grad, which sets them to 0)
+hipError_t launch_delay_phasor_grad(const float* P, const float* taps, const float* R, int n,
+                                    float* dP, hipStream_t s);
 
 // ---- reverb (k_reverb.hip) ------------------------------------------------------------------
 constexpr int kRvFft = 384, kRvHop = 192;  // STFT of the noise and of the masks
@@ -135,6 +146,18 @@ hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nod
 // gradient)
 hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
                          const float4* Hs, float4* Y0, hipStream_t s);
+// Partitioned cross-correlation R_c[n] = sum_t ybar_c[t + s_a] u_c[t + s_i - n], n in [0, len),
+// of a node's output adjoint and its input sum (the reverb's FIR gradient; the delay's surrogate
+// gradient), over nb blocks of 2048 (nb x 2048 must cover every t with a non-zero term). Spectra
+// per node parameter slot: input windows (adj false, shift s_i: [2048 b - 2048 + s_i,
+// 2048 b + 2048 + s_i)) or single output-adjoint blocks (adj true, shift s_a:
+// [2048 b + s_a, 2048 b + 2048 + s_a)), float4 [slots][nb][kRvStride]; then, for n slots, Gs:
+// float4 [n][parts][kRvStride] cross-spectra and R: float [n][2][len] (parts = ceil(len / 2048)).
+// Input samples before 0 must not reach a term (s_i <= 0): the input windows start at b = 0.
+hipError_t launch_xcorr_spectra(const GraphView& g, int node_begin, int n_nodes, bool adj,
+                                int shift, int nb, float4* out, hipStream_t s);
+hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const float4* Y0, const float4* X,
+                        float4* Gs, float* R, hipStream_t s);
 // After the last adjoint step, every reverb slot: Gs: float4 [n][parts][kRvStride] partition
 // cross-spectra; hbar: float [n][2][L]; part: double [n][2][frames][193]; dP: float [n][768]
 hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const double2* Un,

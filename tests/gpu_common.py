@@ -81,15 +81,29 @@ def oracle_grads(w: synth.Workload, dY: np.ndarray):
 ZERO_COLUMN_FLOOR = 1e-9
 
 # Columns that hold one kind of parameter, in the same units, form a group: the EQ's 1024 bin
-# log-magnitudes, and each of the reverb's four 192-bin masks (mid H0, mid HD, side H0, side HD).
-# Within a group a column's scale is floored at GROUP_FLOOR times the group's largest entry. A
-# gradient entry that crosses zero (e.g. one EQ bin of a single EQ node, 4e-5 of the tensor's
-# largest entry) cannot be computed to 1e-3 of itself in FP32, whose rounding of the neighbouring
-# large entries is already of that size; judged against its group it must still be within 1e-6 of
-# the group's largest entry. Groups are contiguous and keyed by the tensor's width, which is
-# unique for these two types (N_t = 1024, 768). Every other column is its own group.
-GROUP_SIZE_BY_WIDTH = {1024: 1024, 768: 192}
+# log-magnitudes; each of the reverb's four 192-bin masks (mid H0, mid HD, side H0, side HD); the
+# two coordinates (re z, im z) of each delay phasor, whose gradient is a 2-vector (the paper
+# normalises it per delay, so its direction is what the optimiser uses). Within a group a column's
+# scale is floored at GROUP_FLOOR times the group's largest entry. A gradient entry that crosses
+# zero (e.g. one EQ bin of a single EQ node, 4e-5 of the tensor's largest entry; the real part of
+# a phasor gradient that points along the imaginary axis) cannot be computed to 1e-3 of itself in
+# FP32, whose rounding of the neighbouring large entries is already of that size; judged against
+# its group it must still be within 1e-6 of the group's largest entry. Groups are keyed by the
+# tensor's width, which is unique for these types (N_t = 1024, 768, 220). Every other column is
+# its own group.
 GROUP_FLOOR = 1e-3
+
+
+def _groups(width: int):
+    """Group id of every column of a parameter tensor of this width, or None (no groups)."""
+    if width == 1024:  # EQ
+        return np.zeros(1024, dtype=np.int64)
+    if width == 768:  # reverb: [mid, side][H0, HD][192]
+        return np.arange(768) // 192
+    if width == 220:  # delay: [channel 2][slot 5][re z, im z, 20 log-magnitudes]
+        i = np.arange(220)
+        return np.where(i % 22 < 2, i // 22, 1000 + i)
+    return None
 
 
 def column_scales(ref: np.ndarray) -> np.ndarray:
@@ -100,10 +114,11 @@ def column_scales(ref: np.ndarray) -> np.ndarray:
     col = col.max(axis=0) if col.ndim == 2 else col
     whole = float(col.max()) if col.size else 0.0
     scale = np.maximum(col, ZERO_COLUMN_FLOOR * whole if whole > 0 else 1.0)
-    g = GROUP_SIZE_BY_WIDTH.get(col.shape[0])
-    if g:
-        grp = col.reshape(-1, g).max(axis=1, keepdims=True)
-        scale = np.maximum(scale, (GROUP_FLOOR * grp * np.ones((1, g))).reshape(-1))
+    gid = _groups(col.shape[0])
+    if gid is not None:
+        for g in np.unique(gid):
+            sel = gid == g
+            scale[sel] = np.maximum(scale[sel], GROUP_FLOOR * col[sel].max())
     return np.maximum(scale, 1e-300)
 
 

@@ -1,0 +1,109 @@
+"""GPU parity of the delay-time surrogate gradient (paper Sec. 3 "Multitap delay", Eq. 15):
+with the schedule's surrogate setting on, the render is unchanged and every delay phasor
+(re z, im z) gets the straight-through gradient of the surrogate impulse; checked against the
+FP64 oracle (oracle.processors.delay with surrogate=True) on graphs with delays in parallel and in
+series, at lengths that are not multiples of the 2048-sample block, shorter than the five
+100 ms slots, and several seconds long. Phasors lie on the unit circle (as drawn) or slightly
+off it, inside and outside. Tolerances: the render's 1e-5 of the peak output and the gradients'
+1e-3 of each parameter column's largest entry over the graph's delay nodes, the two coordinates
+of a phasor judged as one 2-vector (tests/gpu_common.py, column groups)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import GRAD_TOL, RENDER_TOL, grad_err, rel_err, say
+from oracle import render as OR
+from paper_2408_03204_amd import Schedule, render
+
+pytestmark = pytest.mark.gpu
+
+F64 = torch.float64
+
+
+def delay_graph(T, seed, off_circle=0.0):
+    """Four delays: two in parallel on separate inputs, one behind another (two steps), one on
+    the sum of both inputs next to a gain."""
+    b = synth.GraphBuilder()
+    i0, i1 = b.add(synth.IN), b.add(synth.IN)
+    d0, d1, d2, d3 = (b.add(synth.DELAY) for _ in range(4))
+    gp = b.add(synth.GAIN_PAN)
+    o = b.add(synth.OUT)
+    for s, d in ((i0, d0), (i1, d1), (d1, d2), (i0, d3), (i1, d3), (i0, gp), (d0, o), (d2, o),
+                 (d3, o), (gp, o)):
+        b.connect(s, d)
+    g = b.build()
+    P = synth.draw_params(synth.rng_for(seed, 2), g)
+    if off_circle:
+        q = P[synth.DELAY].reshape(-1, 2, 5, 22)
+        r = 1.0 + off_circle * synth.rng_for(seed, 3).uniform(-1.0, 1.0, size=q.shape[:3] + (1,))
+        q[..., :2] *= r.astype(np.float32)
+    w = synth.Workload("delay_graph", g, synth.make_sources(synth.rng_for(seed, 1), 2, T), P,
+                       None, T, seed)
+    return w
+
+
+def run(w, seed, surrogate=True):
+    sched = Schedule(w.graph.node_type, w.graph.edges)
+    sched.set_delay_surrogate(surrogate)
+    S = torch.as_tensor(w.sources).cuda().requires_grad_(True)
+    P = {t: torch.as_tensor(p).cuda().requires_grad_(True) for t, p in w.params.items()
+         if p.shape[0] > 0}
+    Y = render(sched, S, P)
+    dY = np.random.default_rng(seed).normal(size=tuple(Y.shape)).astype(np.float32)
+    Y.backward(torch.as_tensor(dY).cuda())
+    torch.cuda.synchronize()
+    g = w.graph
+    S64 = torch.as_tensor(w.sources, dtype=F64).requires_grad_(True)
+    P64 = OR.as_params64(w.params, requires_grad=True)
+    Yr = OR.render(g.node_type, g.edges, S64, P64, delay_surrogate=surrogate)
+    keys = [t for t in sorted(P64) if P64[t].shape[0] > 0]
+    gr = torch.autograd.grad((Yr * torch.as_tensor(dY, dtype=F64)).sum(),
+                             [S64] + [P64[t] for t in keys])
+    ref = dict(zip(["S"] + keys, [x.detach().numpy() for x in gr]))
+    Yh = Y.detach().cpu().numpy().astype(np.float64)
+    errs = {"Y": rel_err(Yh[0], Yr.detach().numpy()[0]), "S": grad_err(S.grad.cpu().numpy(),
+                                                                         ref["S"])}
+    for t, p in P.items():
+        errs[synth.TYPE_NAMES[t]] = grad_err(p.grad.cpu().numpy(), ref[t])
+    dd = P[synth.DELAY].grad.cpu().numpy().reshape(-1, 2, 5, 22)
+    rd = ref[synth.DELAY].reshape(-1, 2, 5, 22)
+    # the phasor entries alone (log-magnitude entries set to the oracle's), judged like the whole
+    # tensor: each (re z, im z) pair against its largest entry over the graph's delay nodes
+    only = rd.copy()
+    only[..., :2] = dd[..., :2]
+    errs["phasor"] = grad_err(only.reshape(rd.shape[0], -1), rd.reshape(rd.shape[0], -1))
+    return errs, dd, rd
+
+
+def check(errs):
+    say("   errs", {k: f"{e:.2e}" for k, e in errs.items()})
+    assert errs["Y"] <= RENDER_TOL, errs
+    for k, e in errs.items():
+        if k != "Y":
+            assert e <= GRAD_TOL, (k, e)
+
+
+@pytest.mark.parametrize("T,off", [(3 * 2048 + 555, 0.0), (2 ** 15, 1e-4),
+                                   (5 * 4410 + 3000, 0.0), (9000, 1e-4)])
+def test_delay_surrogate_gradient(T, off):
+    say(f"[delay surrogate] T={T} off-circle={off}")
+    w = delay_graph(T, 81, abs(off))
+    errs, dd, rd = run(w, 6)
+    assert np.abs(rd[..., :2]).max() > 0  # the oracle's phasor gradients are not all zero
+    check(errs)
+
+
+def test_delay_surrogate_full_length():
+    T = 2 ** 18
+    say(f"[delay surrogate full] T={T}")
+    w = delay_graph(T, 82, 1e-4)
+    errs, _, _ = run(w, 7)
+    check(errs)
+
+
+def test_delay_phasors_have_no_gradient_by_default():
+    w = delay_graph(4 * 2048 + 7, 83)
+    errs, dd, rd = run(w, 8, surrogate=False)
+    check(errs)
+    assert np.all(dd[..., :2] == 0.0) and np.all(rd[..., :2] == 0.0)

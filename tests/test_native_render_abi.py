@@ -219,3 +219,24 @@ def test_reverb_needs_its_noise(reverb_sched):
     assert render(s, P=params(s, skip=synth.REVERB)) == E_SHAPE and "11" in err()
     assert render(s, nbytes=long_ws // 4) == E_WORKSPACE
     assert lib.grafx_schedule_set_reverb_noise(s._h, None, 0) == OK
+
+
+def test_delay_surrogate_setting():
+    """The delay-time surrogate is off by default; turning it on grows the adjoint's workspace
+    (spectra and correlation of every delay node) and leaves the forward workspace alone."""
+    b = synth.GraphBuilder()
+    i0 = b.add(synth.IN)
+    d = b.add(synth.DELAY)
+    b.connect(i0, d)
+    b.connect(d, b.add(synth.OUT))
+    g = b.build()
+    s = Schedule(g.node_type, g.edges)
+    lib = load()
+    fwd, bwd = s.workspace_bytes(1 << 16, False), s.workspace_bytes(1 << 16, True)
+    assert lib.grafx_schedule_set_delay_surrogate(None, 1) == E_ARG
+    assert lib.grafx_schedule_set_delay_surrogate(s._h, 2) == E_ARG
+    assert lib.grafx_schedule_set_delay_surrogate(s._h, 1) == OK
+    assert s.workspace_bytes(1 << 16, False) == fwd
+    assert s.workspace_bytes(1 << 16, True) > bwd
+    s.set_delay_surrogate(False)
+    assert s.workspace_bytes(1 << 16, True) == bwd
