@@ -168,19 +168,20 @@ def noisegate(u, p, ybar):
 
 def delay(u, p, ybar):
     d = P.delay_offsets(p.numpy())
-    q = p.reshape(2, P.DELAY_TAPS, 2 + P.DELAY_BINS)
+    M = d.shape[1]
+    q = p.reshape(2, M, 2 + P.DELAY_BINS)
     span = int(d.max()) + 39
     ubar, pbar = [], torch.zeros_like(q)
     for c in range(2):
         h = torch.zeros(span, dtype=F64)
-        for m in range(P.DELAY_TAPS):
+        for m in range(M):
             start = int(d[c, m])
             h[start:start + 39] += P.zero_phase_fir(q[c, m, 2:], 39)
         # forward: y[t] = sum_j h[j] u[t - (j - 19)]; adjoint: the reversed filter
         ubar.append(P.linear_conv_centred(ybar[c:c + 1], torch.flip(h, [0]), -(span - 20))[0])
         # hbar[j] = sum_t ybar[t] u[t - (j - 19)] for j = 0..span-1
         hbar = xcorr(ybar[c], u[c], -19, span - 20)
-        for m in range(P.DELAY_TAPS):
+        for m in range(M):
             start = int(d[c, m])
             pbar[c, m, 2:] = fir_param_adjoint(q[c, m, 2:], hbar[start:start + 39], 39)
     return torch.stack(ubar), pbar.reshape(-1)
@@ -198,4 +199,4 @@ def identity(u, p, ybar):
 
 
 ADJOINT = {1: identity, 2: identity, 3: gain_pan, 4: eq, 5: compressor, 6: imager, 7: delay,
-           8: tanh_dist, 9: noisegate}
+           8: tanh_dist, 9: noisegate, 12: delay}

@@ -19,10 +19,11 @@ Readings of passages the paper leaves open (each is listed with its reason in th
   the gain exp(G_y - G_u) multiplies the amplitude as printed; W <= 0 means a hard knee.
 * attack/release ballistics (Eq. 8 unrestricted): the attack coefficient applies while the
   envelope rises, i.e. when x[t] > g[t-1]; a tie counts as release.
-* delay (Eq. 14, limited to 500 ms): five 100 ms slots of 4410 samples per channel; the delay
-  inside slot m is read from the phase of z as rint(-arg(z) * 4410 / 2 pi) mod 4410, computed in
-  float32 because it decides an integer; each slot's 39-tap filter follows the EQ recipe with
-  N = 39 and 20 log-magnitudes; the output is the wet signal only.
+* delay (Eq. 14): M 100 ms slots of 4410 samples per channel, M = 20 (2 s, the paper's setting,
+  880 parameters: node type delay_long) or M = 5 (500 ms, 220 parameters: node type delay); the
+  delay inside slot m is read from the phase of z as rint(-arg(z) * 4410 / 2 pi) mod 4410,
+  computed in float32 because it decides an integer; each slot's 39-tap filter follows the EQ
+  recipe with N = 39 and 20 log-magnitudes; the output is the wet signal only.
 * tanh distortion (not in the paper): y = tanh(exp(p) u).
 """
 from __future__ import annotations
@@ -264,21 +265,31 @@ def envelope_loop(x: np.ndarray, alpha: float) -> np.ndarray:
 # multitap delay (Eq. 14), limited to five 100 ms slots
 
 DELAY_SLOT = 4410
-DELAY_TAPS = 5
+DELAY_TAPS = 5          # slots of the 500 ms delay (node type delay)
+DELAY_TAPS_LONG = 20    # slots of the 2 s delay (node type delay_long)
 DELAY_BINS = 20
+
+
+def delay_slots(p) -> int:
+    """Slots per channel of a delay parameter row: 220 values -> 5, 880 -> 20."""
+    m = int(np.prod(np.shape(p))) // (2 * (2 + DELAY_BINS))
+    if m not in (DELAY_TAPS, DELAY_TAPS_LONG) or m * 2 * (2 + DELAY_BINS) != int(np.prod(np.shape(p))):
+        raise ValueError(f"a delay row has 220 or 880 values, not {int(np.prod(np.shape(p)))}")
+    return m
 
 
 def delay_offsets(p: np.ndarray) -> np.ndarray:
     """Integer delay per (channel, slot), decided in float32 from the phase of z."""
-    q = np.asarray(p, dtype=np.float32).reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
+    M = delay_slots(p)
+    q = np.asarray(p, dtype=np.float32).reshape(2, M, 2 + DELAY_BINS)
     ph = np.arctan2(q[..., 1], q[..., 0]).astype(np.float32)
     frac = np.rint(-ph * np.float32(DELAY_SLOT / (2.0 * math.pi))).astype(np.int64)
     d = np.mod(frac, DELAY_SLOT)
-    return d + DELAY_SLOT * np.arange(DELAY_TAPS)[None, :]
+    return d + DELAY_SLOT * np.arange(M)[None, :]
 
 
 def delay(u: torch.Tensor, p: torch.Tensor, surrogate: bool = False) -> torch.Tensor:
-    """y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j]: per channel, five
+    """y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j]: per channel, M (5 or 20)
     integer delays, each followed by its own 39-tap zero-phase FIR. The integer delays carry no
     gradient; with `surrogate`, the phasors get the straight-through gradient of Eq. 15 (the
     value is unchanged: see `_delay_surrogate_term`)."""
@@ -295,12 +306,13 @@ def _delay_surrogate_term(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
     taps and input held constant: its gradient with respect to the phasors is the
     straight-through gradient."""
     from .reverb import surrogate as surr  # the surrogate lives with the other Eq. 15 helpers
-    q = p.reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
-    span = DELAY_TAPS * DELAY_SLOT + 38
+    M = delay_slots(p)
+    q = p.reshape(2, M, 2 + DELAY_BINS)
+    span = M * DELAY_SLOT + 38
     ys = []
     for c in range(2):
         K = torch.zeros(span, dtype=F64)
-        for m in range(DELAY_TAPS):
+        for m in range(M):
             z = torch.complex(q[c, m, 0], q[c, m, 1])
             s = surr(z, DELAY_SLOT).real  # impulse at lag n within the slot, n = 0..4409
             taps = zero_phase_fir(q[c, m, 2:].detach(), 39)
@@ -313,12 +325,13 @@ def _delay_surrogate_term(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
 
 def _delay_exact(u: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
     d = delay_offsets(p.detach().numpy())
-    q = p.reshape(2, DELAY_TAPS, 2 + DELAY_BINS)
+    M = d.shape[1]
+    q = p.reshape(2, M, 2 + DELAY_BINS)
     span = int(d.max()) + 39
     ys = []
     for c in range(2):
         h = torch.zeros(span, dtype=F64)
-        for m in range(DELAY_TAPS):
+        for m in range(M):
             taps = zero_phase_fir(q[c, m, 2:], 39)
             start = int(d[c, m])  # tap j=-19 sits at lag d - 19 -> index d
             h = h + torch.nn.functional.pad(taps, (start, span - start - 39))
@@ -338,6 +351,7 @@ def identity(u: torch.Tensor, p=None) -> torch.Tensor:
 
 
 PROCESS = {2: identity, 3: gain_pan, 4: eq, 5: compressor, 6: imager, 7: delay, 8: tanh_dist,
-           9: noisegate, 10: compressor_ar, 1: identity}
-N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4, 10: 5, 11: 768}
+           9: noisegate, 10: compressor_ar, 1: identity, 12: delay}
+N_PARAMS = {0: 0, 1: 0, 2: 0, 3: 2, 4: 1024, 5: 4, 6: 1, 7: 220, 8: 1, 9: 4, 10: 5, 11: 768,
+            12: 880}
 REVERB = 11  # the reverb takes its noise realisation besides u and p (oracle.reverb.reverb)

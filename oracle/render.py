@@ -82,7 +82,7 @@ def node_forward(t: int, u: torch.Tensor, p: torch.Tensor | None, reverb_noise=N
         if reverb_noise is None:
             raise ValueError("a reverb node needs the reverb noise realisation")
         return reverb.reverb(u, p, reverb_noise)
-    if t == 7 and delay_surrogate:
+    if t in (7, 12) and delay_surrogate:  # delay, delay_long
         return processors.delay(u, p, surrogate=True)
     return processors.PROCESS[t](u, p)
 

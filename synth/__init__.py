@@ -24,20 +24,23 @@ import numpy as np
 
 FS = 44100
 
-IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE, COMP_AR, REVERB = range(12)
+IN, OUT, MIX, GAIN_PAN, EQ, COMP, IMAGER, DELAY, TANH, GATE, COMP_AR, REVERB, DELAY_LONG = \
+    range(13)
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
-              "noisegate", "compressor_ar", "reverb")
+              "noisegate", "compressor_ar", "reverb", "delay_long")
 NUM_TYPES = len(TYPE_NAMES)
 TYPE_CODES = {n: i for i, n in enumerate(TYPE_NAMES)}
 # parameters per node of each type (0 for in/out/mix)
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768)
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768, 880)
 # reverb: noise realisation of 2 s (mid, side); parameters [mid, side][H0, HD][192 bins]
 REVERB_LEN = 2 * FS
 REVERB_BINS = 192
 REVERB_HOP = 192
 
-# delay layout: [channel 2][tap 5][re z, im z, 20 log-magnitudes]
+# delay layout: [channel 2][slot M][re z, im z, 20 log-magnitudes]; M = 5 (delay, 500 ms) or
+# M = 20 (delay_long, 2 s)
 DELAY_TAPS = 5
+DELAY_TAPS_LONG = 20
 DELAY_SLOT = 4410  # 100 ms at 44.1 kHz
 DELAY_BINS = 20
 
@@ -180,22 +183,29 @@ def gate_params(rng, n, knee_db=3.0):
     return np.stack([alpha, thr, knee, ratio], axis=1).astype(np.float32)
 
 
-def delay_params(rng, n, max_ms=500.0):
+def delay_params(rng, n, max_ms=500.0, slots=None):
     """Per channel and 100 ms slot: an integer delay inside the slot encoded as a unit phasor
     z = exp(-2 pi i d / 4410), and 20 log-magnitudes for the slot's 39-tap filter: a flat level
-    U[-24,-6] dB plus +-3 dB ripple per bin."""
-    taps = min(DELAY_TAPS, int(round(max_ms / 100.0)))
-    out = np.zeros((n, 2, DELAY_TAPS, 2 + DELAY_BINS), dtype=np.float64)
+    U[-24,-6] dB plus +-3 dB ripple per bin. `slots`: 5 (the 500 ms delay, default) or 20 (the
+    2 s delay); slots past `max_ms` are silenced (-120 dB)."""
+    M = slots or DELAY_TAPS
+    taps = min(M, int(round(max_ms / 100.0)))
+    out = np.zeros((n, 2, M, 2 + DELAY_BINS), dtype=np.float64)
     for i in range(n):
         for c in range(2):
-            for m in range(DELAY_TAPS):
+            for m in range(M):
                 d = int(rng.integers(0, DELAY_SLOT))
                 ph = -2.0 * math.pi * d / DELAY_SLOT
                 out[i, c, m, 0] = math.cos(ph)
                 out[i, c, m, 1] = math.sin(ph)
                 level = rng.uniform(-24.0, -6.0) if m < taps else -120.0
                 out[i, c, m, 2:] = (level + rng.uniform(-3.0, 3.0, size=DELAY_BINS)) * LN10_20
-    return out.reshape(n, 2 * DELAY_TAPS * (2 + DELAY_BINS)).astype(np.float32)
+    return out.reshape(n, 2 * M * (2 + DELAY_BINS)).astype(np.float32)
+
+
+def delay_long_params(rng, n, max_ms=2000.0):
+    """The 2 s delay (20 slots per channel), drawn like `delay_params`."""
+    return delay_params(rng, n, max_ms, slots=DELAY_TAPS_LONG)
 
 
 def reverb_params(rng, n):
@@ -227,7 +237,7 @@ def reverb_noise(seed: int, length: int = REVERB_LEN) -> np.ndarray:
 
 PARAM_DRAW = {GAIN_PAN: gain_pan_params, EQ: eq_params, COMP: comp_params,
               IMAGER: imager_params, DELAY: delay_params, TANH: tanh_params, GATE: gate_params,
-              COMP_AR: comp_ar_params, REVERB: reverb_params}
+              COMP_AR: comp_ar_params, REVERB: reverb_params, DELAY_LONG: delay_long_params}
 
 
 def draw_params(rng: np.random.Generator, graph: Graph) -> dict[int, np.ndarray]:

@@ -100,11 +100,11 @@ def test_dynamics_adjoints_equal_autograd(gate, knee):
             assert abs(float(hp[j] - gp[j])) <= TOL * abs(float(gp[j])) * 10, j
 
 
-def test_delay_adjoint_equals_autograd():
+@pytest.mark.parametrize("slots,T", [(5, 23000), (20, 89000)])
+def test_delay_adjoint_equals_autograd(slots, T):
     rng = np.random.default_rng(3)
-    T = 23000
     u, ybar = _signal(rng, T), torch.as_tensor(rng.standard_normal((2, T)), dtype=F64)
-    p = torch.as_tensor(synth.delay_params(rng, 1)[0], dtype=F64)
+    p = torch.as_tensor(synth.delay_params(rng, 1, 100.0 * slots, slots)[0], dtype=F64)
     assert P.delay_offsets(p.numpy()).max() + 20 < T
     gu, gp = _autograd(P.delay, u, p, ybar)
     hu, hp = A.delay(u, p, ybar)

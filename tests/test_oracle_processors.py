@@ -310,62 +310,71 @@ def test_tanh():
 # --- delay (Eq. 14) ------------------------------------------------------------------------------
 
 def _delay_p(d, logmags):
-    """d [2,5] integer delays inside their slots, logmags [2,5,20]."""
-    p = np.zeros((2, 5, 22))
+    """d [2,M] integer delays inside their slots, logmags [2,M,20] (M = 5 or 20)."""
+    M = np.shape(d)[1]
+    p = np.zeros((2, M, 22))
     ph = -2 * np.pi * np.asarray(d) / 4410
     p[..., 0], p[..., 1] = np.cos(ph), np.sin(ph)
     p[..., 2:] = logmags
-    return p.reshape(220).astype(np.float32)
+    return p.reshape(2 * M * 22).astype(np.float32)
 
 
-def test_delay_offsets_from_phasor():
+@pytest.mark.parametrize("M", [5, 20])
+def test_delay_offsets_from_phasor(M):
     rng = np.random.default_rng(8)
-    d = rng.integers(0, 4410, (2, 5))
+    d = rng.integers(0, 4410, (2, M))
     d[0, 0], d[0, 1], d[1, 0] = 0, 2205, 4409
-    off = P.delay_offsets(_delay_p(d, np.zeros((2, 5, 20))))
-    assert np.array_equal(off, d + 4410 * np.arange(5)[None, :])
+    off = P.delay_offsets(_delay_p(d, np.zeros((2, M, 20))))
+    assert np.array_equal(off, d + 4410 * np.arange(M)[None, :])
 
 
-def test_delay_single_flat_tap_is_pure_shift():
+@pytest.mark.parametrize("M,slot0,T", [(5, 2, 30000), (20, 17, 90000)])
+def test_delay_single_flat_tap_is_pure_shift(M, slot0, T):
     rng = np.random.default_rng(9)
-    d = rng.integers(0, 4410, (2, 5))
-    lm = np.full((2, 5, 20), -1000.0)  # exp(-1000) = 0 to double precision
-    lm[0, 2] = 0.0
+    d = rng.integers(0, 4410, (2, M))
+    lm = np.full((2, M, 20), -1000.0)  # exp(-1000) = 0 to double precision
+    lm[0, slot0] = 0.0
     lm[1, 0] = math.log(0.5)
     p32 = _delay_p(d, lm)
     p = torch.as_tensor(p32, dtype=F64)
-    T = 30000
     u = _rand((2, T), 10)
     y = P.delay(u, p).numpy()
-    sh0 = int(d[0, 2]) + 2 * 4410
+    sh0 = int(d[0, slot0]) + slot0 * 4410
     sh1 = int(d[1, 0])
-    half = math.exp(float(p32.reshape(2, 5, 22)[1, 0, 2]))  # float32-rounded ln(0.5)
+    half = math.exp(float(p32.reshape(2, M, 22)[1, 0, 2]))  # float32-rounded ln(0.5)
     assert np.max(np.abs(y[0, sh0:] - u.numpy()[0, :T - sh0])) < 1e-12
     assert np.max(np.abs(y[0, :sh0])) < 1e-12
     assert np.max(np.abs(y[1, sh1:] - half * u.numpy()[1, :T - sh1])) < 1e-12
 
 
-def test_delay_direct_sum():
+@pytest.mark.parametrize("M,T,points", [(5, 23000, (0, 5, 4500, 13000, 22999)),
+                                        (20, 90000, (3, 20000, 70000, 86000, 89999))])
+def test_delay_direct_sum(M, T, points):
     rng = np.random.default_rng(11)
-    d = rng.integers(0, 4410, (2, 5))
-    lm = rng.uniform(-2, 0, (2, 5, 20))
+    d = rng.integers(0, 4410, (2, M))
+    lm = rng.uniform(-2, 0, (2, M, 20))
     p32 = _delay_p(d, lm)
     p = torch.as_tensor(p32, dtype=F64)
-    T = 23000
     u = _rand((2, T), 12).numpy()
     y = P.delay(torch.as_tensor(u), p).numpy()
     off = P.delay_offsets(p32)
-    q = p.reshape(2, 5, 22)
+    q = p.reshape(2, M, 22)
     for c in range(2):
-        for t in (0, 5, 4500, 13000, 22999):
+        for t in points:
             acc = 0.0
-            for m in range(5):
+            for m in range(M):
                 taps = P.zero_phase_fir(q[c, m, 2:], 39).numpy()
                 for j in range(-19, 20):
                     s = t - int(off[c, m]) - j
                     if 0 <= s < T:
                         acc += taps[j + 19] * u[c, s]
             assert abs(acc - y[c, t]) < 1e-12
+
+
+def test_delay_row_sizes():
+    assert P.delay_slots(np.zeros(220)) == 5 and P.delay_slots(np.zeros(880)) == 20
+    with pytest.raises(ValueError):
+        P.delay_slots(np.zeros(440))
 
 
 def test_lfilter_reference_for_delay_free_compressor_path():

@@ -234,6 +234,22 @@ def test_surrogate_delay_matches_exact_delay_on_the_unit_circle():
     assert np.max(np.abs(ys - ye)) < 1e-10 * np.max(np.abs(ye))
 
 
+def test_surrogate_delay_matches_exact_delay_on_the_unit_circle_2s():
+    """The same for the 2 s delay (20 slots): every slot's surrogate is its delayed impulse."""
+    rng = np.random.default_rng(14)
+    p0 = synth.delay_params(rng, 1, 2000.0, 20)[0].astype(np.float64)
+    d = OP.delay_offsets(p0) % RV.SLOT
+    q = p0.reshape(2, 20, 22)
+    q[:, :, 0] = np.cos(-2.0 * np.pi * d / RV.SLOT)
+    q[:, :, 1] = np.sin(-2.0 * np.pi * d / RV.SLOT)
+    assert np.array_equal(OP.delay_offsets(p0) % RV.SLOT, d)
+    u = torch.as_tensor(synth.make_sources(synth.rng_for(14, 1), 1, 90000)[0].astype(np.float64))
+    p = torch.as_tensor(p0)
+    ys = OP._delay_surrogate_term(u, p).numpy()
+    ye = OP.delay(u, p).numpy()
+    assert np.max(np.abs(ys - ye)) < 1e-10 * np.max(np.abs(ye))
+
+
 @pytest.mark.parametrize("unit", [True, False])
 def test_phasor_gradient_against_finite_differences(unit):
     """The straight-through phasor gradient equals central differences of the surrogate delay's
