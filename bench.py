@@ -46,12 +46,12 @@ WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "larg
              "batch": "batched_graphs", "console_ar": "mixing_console",
              "learned_init": "labelled_tiny_consoles", "reverb": "reverb_console"}
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
-              "noisegate", "compressor_ar", "reverb")
+              "noisegate", "compressor_ar", "reverb", "delay_long")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
 KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
               "imager": "k_pointwise.hip", "tanh": "k_pointwise.hip", "eq": "k_eq.hip",
               "compressor": "k_comp.hip", "noisegate": "k_comp.hip", "compressor_ar": "k_comp_ar.hip",
-              "delay": "k_delay.hip", "reverb": "k_reverb.hip"}
+              "delay": "k_delay.hip", "reverb": "k_reverb.hip", "delay_long": "k_delay.hip"}
 
 
 def parse():
@@ -129,10 +129,11 @@ def step_flops(sched, n: int, T: int, backward: bool) -> float:
     gradients)."""
     if int(sched.step_type[n]) == 11:
         return reverb_flops(sched, n, T, backward)
-    if int(sched.step_type[n]) == 7:
+    if int(sched.step_type[n]) in (7, 12):  # delay (5 slots), delay_long (20 slots)
         samples = sum(_len(sched, i, T) for i in range(int(sched.step_ptr[n]),
                                                          int(sched.step_ptr[n + 1])))
-        return samples * 2.0 * DELAY_FMA * (2 if backward else 1)
+        slots = 20 if int(sched.step_type[n]) == 12 else 5
+        return samples * 2.0 * DELAY_FMA * slots / 5 * (2 if backward else 1)
     tiles = sum(-(-_len(sched, i, T) // (EQ_FFT // 2))
                 for i in range(int(sched.step_ptr[n]), int(sched.step_ptr[n + 1])))
     fft = 5.0 * EQ_FFT * np.log2(EQ_FFT)
@@ -601,7 +602,7 @@ def main():
                     "kernel": f"{tname} {d}", "launches": cnt,
                     "algorithmic_bytes_per_launch": round(b_tot / cnt),
                     "ms_per_launch": round(t_tot / cnt, 5)}
-        if tname in ("eq", "delay", "reverb"):  # FFT / FIR arithmetic: also its flop rate
+        if tname in ("eq", "delay", "reverb", "delay_long"):  # FFT / FIR arithmetic: flop rate
             flops = sum(step_flops(sched, r["step"], T, d == "bwd") for r in table
                         if r["dir"] == d and r["type"] == tname)
             tf = flops / (t_tot * 1e-3) / 1e12
@@ -611,6 +612,7 @@ def main():
                 "count": {"eq": "5 N log2 N flops per 4096-point complex FFT plus the spectral "
                                 "products",
                           "delay": "2 flops per FIR multiply-add",
+                          "delay_long": "2 flops per FIR multiply-add",
                           "reverb": "5 N log2 N flops per 4096-point complex FFT plus 16 flops "
                                     "per one-sided bin, partition and block"}[tname],
                 "peak_basis": "FP32 vector issue without packed-FP32 instructions"}

@@ -46,6 +46,8 @@
  *                     release coefficients, alpha_a while x[t] > g[t-1]  (Eq. 8 unrestricted)
  *  11 reverb     768  [mid, side][H0, HD][192 bins]: filtered-noise mid/side reverb (Eqs. 6-7),
  *                     a causal stereo FIR made from the noise of grafx_schedule_set_reverb_noise
+ *  12 delay_long 880  [channel 2][slot 20][re z, im z, 20 log-magnitudes]: the multitap delay
+ *                     with the paper's 20 slots of 100 ms (2 s)                (Eq. 14)
  * The node input is the sum over incoming edges of the source node outputs (Eq. 1b), parallel
  * edges counted once each, summed in original edge order.
  */
@@ -76,7 +78,7 @@ typedef enum grafx_status {
 enum {
   GRAFX_IN = 0, GRAFX_OUT = 1, GRAFX_MIX = 2, GRAFX_GAIN_PAN = 3, GRAFX_EQ = 4,
   GRAFX_COMPRESSOR = 5, GRAFX_IMAGER = 6, GRAFX_DELAY = 7, GRAFX_TANH = 8, GRAFX_NOISEGATE = 9,
-  GRAFX_COMPRESSOR_AR = 10, GRAFX_REVERB = 11, GRAFX_NUM_TYPES = 12
+  GRAFX_COMPRESSOR_AR = 10, GRAFX_REVERB = 11, GRAFX_DELAY_LONG = 12, GRAFX_NUM_TYPES = 13
 };
 
 /* Schedule search methods (paper Sec. 2 "Type scheduling"; Sec. 4 "Speed benchmark"). */
@@ -114,7 +116,7 @@ typedef struct grafx_schedule_sizes {
  * a width cap. Nodes are then reordered by (step, original id) ("sigma"), and the read/write
  * index lists are built as CSR arrays in that order.
  *
- *   num_nodes, node_type    host int32[num_nodes], codes 0..11 (the node types above)
+ *   num_nodes, node_type    host int32[num_nodes], codes 0..12 (the node types above)
  *   num_edges, edge_src/dst host int32[num_edges] each (may be NULL when num_edges == 0)
  *   edge_type               host int32[2*num_edges] or NULL; must be all zero (SISO graphs)
  *   method                  grafx_sched_method
@@ -396,8 +398,8 @@ grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* sched, const floa
 
 /*
  * grafx_schedule_set_delay_surrogate -- the gradient of the delay times (paper Sec. 3 "Multitap
- * delay", Eq. 15). With enable = 0 (the default) grafx_render_backward writes 0 to every delay
- * phasor entry (re z, im z). With enable = 1 it writes the straight-through gradient of the
+ * delay", Eq. 15), for both delay types (delay, delay_long). With enable = 0 (the default)
+ * grafx_render_backward writes 0 to every delay phasor entry (re z, im z). With enable = 1 it writes the straight-through gradient of the
  * surrogate: the render keeps the exact integer delay of each 100 ms slot, and the phasor z of the
  * slot gets the gradient that the render would have if the slot's unit impulse were the real part
  * of s[n] = (1/4410) sum_{k=0}^{4409} z^k exp(2 pi i k n / 4410), n = 0..4409 lags from the slot's

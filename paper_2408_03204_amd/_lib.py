@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgrafx.so")
 
-NUM_TYPES = 12
+NUM_TYPES = 13
 STATUS = {0: "GRAFX_OK", 1: "GRAFX_E_ARG", 2: "GRAFX_E_GRAPH", 3: "GRAFX_E_CYCLE",
           4: "GRAFX_E_TYPE", 5: "GRAFX_E_SHAPE", 6: "GRAFX_E_LIMIT", 7: "GRAFX_E_WORKSPACE",
           8: "GRAFX_E_HIP"}

@@ -17,8 +17,9 @@ from . import _lib
 from ._lib import check, load
 
 TYPE_CODES = {"in": 0, "out": 1, "mix": 2, "gain_pan": 3, "eq": 4, "compressor": 5, "imager": 6,
-              "delay": 7, "tanh": 8, "noisegate": 9, "compressor_ar": 10, "reverb": 11}
-N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768)
+              "delay": 7, "tanh": 8, "noisegate": 9, "compressor_ar": 10, "reverb": 11,
+              "delay_long": 12}
+N_PARAMS = (0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768, 880)
 NUM_TYPES = _lib.NUM_TYPES
 METHODS = {"one_by_one": 0, "greedy": 1, "beam": 2, "optimal": 3}
 

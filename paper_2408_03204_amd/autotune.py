@@ -26,7 +26,7 @@ KNOBS = {
     Schedule.TUNE_POINTWISE_UNROLL: (POINTWISE_TYPES, CANDIDATES),
     Schedule.TUNE_EQ_ORDER: ((4,), (0, 1)),
     Schedule.TUNE_DYN_ORDER: ((5, 9, 10), (2, 1, 0)),
-    Schedule.TUNE_TAP_TILES: ((7,), (16, 8, 4)),
+    Schedule.TUNE_TAP_TILES: ((7, 12), (16, 8, 4)),
 }
 KNOB_NAMES = {Schedule.TUNE_POINTWISE_UNROLL: "pointwise_unroll",
               Schedule.TUNE_EQ_ORDER: "eq_order", Schedule.TUNE_DYN_ORDER: "dyn_order",

@@ -23,14 +23,14 @@ namespace {
 // compressor nodes (by parameter slot) followed by the noisegate nodes: both run the same
 // envelope scan and share one set of chunk totals, carries, tickets and gradient partials.
 struct WsLayout {
-  size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps, delay_offs;
+  size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps[2], delay_offs[2];
   size_t ar_slots, ar_carry, ar_pat, ar_tickets;
   size_t rv_Un, rv_h, rv_H, rv_Z;
   size_t fwd_end;
-  size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part;
+  size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part[2];
   size_t ar_ragg, ar_part;
   size_t rv_Y0, rv_G, rv_hbar, rv_part;
-  size_t dl_X, dl_Y0, dl_G, dl_R;
+  size_t dl_X[2], dl_Y0[2], dl_G[2], dl_R[2];
   size_t total;
 };
 
@@ -42,6 +42,12 @@ int dyn_row(const grafx_schedule_t* h, int t) {
   return t == GRAFX_NOISEGATE ? h->type_count[GRAFX_COMPRESSOR] : 0;
 }
 
+// The two multitap delay types (family 0: 500 ms, 5 slots; family 1: 2 s, 20 slots) run the same
+// kernels and keep separate workspace sections.
+constexpr int kDelayType[2] = {GRAFX_DELAY, GRAFX_DELAY_LONG};
+constexpr int kDelaySlots[2] = {kDelayTaps, kDelayTapsLong};
+int delay_family(int t) { return t == GRAFX_DELAY_LONG ? 1 : 0; }
+
 // Published words per attack/release node: kArPasses pass rows of (A, B, flag), then the final
 // (A, B) of every chunk.
 size_t ar_slot_words(size_t chunks) { return (size_t)kArPasses * chunks * 3 + chunks * 2; }
@@ -52,7 +58,6 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   const size_t n_eq = h->type_count[GRAFX_EQ];
   const size_t n_comp = n_dynamics(h);
-  const size_t n_del = h->type_count[GRAFX_DELAY];
   const size_t chunks = comp_chunks(T);
   L.eq_h = take(n_eq * 1024 * sizeof(double));
   L.eq_H = take(n_eq * kEqFFT * sizeof(float));
@@ -61,8 +66,11 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   // the error word on a cache line of its own, then one ticket counter per dynamics node
   // (forward) and one per node (adjoint), each on its own cache line
   L.comp_tickets = take((1 + 2 * n_comp) * kCompTicketStride * sizeof(unsigned));
-  L.delay_taps = take(n_del * kDelayCoef * sizeof(float));
-  L.delay_offs = take(n_del * 2 * kDelayTaps * sizeof(int32_t));
+  for (int f = 0; f < 2; ++f) {
+    const size_t n_del = h->type_count[kDelayType[f]];
+    L.delay_taps[f] = take(n_del * delay_coef(kDelaySlots[f]) * sizeof(float));
+    L.delay_offs[f] = take(n_del * 2 * kDelaySlots[f] * sizeof(int32_t));
+  }
   // attack/release compressors: per-pass and final chunk maps (reset), entering states and final
   // branch patterns (kept for the adjoint), forward then adjoint ticket counters
   const size_t n_ar = h->type_count[GRAFX_COMPRESSOR_AR];
@@ -94,7 +102,9 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.eq_spec = take(n_eq * kEqFoldStride * sizeof(float));
     L.eq_s = take(n_eq * 1024 * sizeof(double));
     // sized for the smallest tap-gradient group, so that the size does not depend on tuning
-    L.delay_part = take(n_del * delay_groups(T, kTapTilesMin) * kDelayCoef * sizeof(float));
+    for (int f = 0; f < 2; ++f)
+      L.delay_part[f] = take((size_t)h->type_count[kDelayType[f]] * delay_groups(T, kTapTilesMin) *
+                             delay_coef(kDelaySlots[f]) * sizeof(float));
     L.ar_ragg = take(n_ar * chunks * 2 * sizeof(uint64_t));
     L.ar_part = take(n_ar * chunks * kArParams * sizeof(double));
     L.rv_Y0 = take(n_rv * rv_nb * kRvStride * sizeof(float4));
@@ -102,12 +112,14 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.rv_hbar = take(n_rv * 2 * rv_L * sizeof(float));
     L.rv_part = take(n_rv * 2 * rv_M * (kRvFft / 2 + 1) * sizeof(double));
     // delay-time surrogate: input-window and adjoint-block spectra, cross-spectra, correlation
-    const size_t n_sur = h->delay_surrogate ? n_del : 0;
-    const size_t sur_nb = n_sur ? (size_t)rv_blocks(T + kDelaySurShift) : 0;
-    L.dl_X = take(n_sur * sur_nb * kRvStride * sizeof(float4));
-    L.dl_Y0 = take(n_sur * sur_nb * kRvStride * sizeof(float4));
-    L.dl_G = take(n_sur * kDelaySurParts * kRvStride * sizeof(float4));
-    L.dl_R = take(n_sur * 2 * kDelaySurLen * sizeof(float));
+    for (int f = 0; f < 2; ++f) {
+      const size_t n_sur = h->delay_surrogate ? (size_t)h->type_count[kDelayType[f]] : 0;
+      const size_t sur_nb = n_sur ? (size_t)rv_blocks(T + kDelaySurShift) : 0;
+      L.dl_X[f] = take(n_sur * sur_nb * kRvStride * sizeof(float4));
+      L.dl_Y0[f] = take(n_sur * sur_nb * kRvStride * sizeof(float4));
+      L.dl_G[f] = take(n_sur * delay_sur_parts(kDelaySlots[f]) * kRvStride * sizeof(float4));
+      L.dl_R[f] = take(n_sur * 2 * delay_sur_len(kDelaySlots[f]) * sizeof(float));
+    }
   }
   L.total = off;
   return L;
@@ -246,8 +258,11 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
                              at<double>(ws, L.comp_carry), tickets(ws, L, h, false),
                              error_word(ws, L), stream);
     case GRAFX_DELAY:
-      return launch_delay_fwd(g, U, at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), b,
-                              cnt, stream);
+    case GRAFX_DELAY_LONG: {
+      const int f = delay_family(t);
+      return launch_delay_fwd(kDelaySlots[f], g, U, at<float>(ws, L.delay_taps[f]),
+                              at<int32_t>(ws, L.delay_offs[f]), b, cnt, stream);
+    }
     case GRAFX_COMPRESSOR_AR: {
       const size_t n_ar = h->type_count[GRAFX_COMPRESSOR_AR], chunks = comp_chunks(g.T);
       uint64_t* slots = at<uint64_t>(ws, L.ar_slots);
@@ -287,16 +302,18 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
                              at<double>(ws, L.comp_carry),
                              at<uint64_t>(ws, L.comp_ragg), at<double>(ws, L.comp_part),
                              tickets(ws, L, h, true), error_word(ws, L), stream);
-    case GRAFX_DELAY: {
-      hipError_t e = launch_delay_bwd(g, dU, at<float>(ws, L.delay_taps),
-                                      at<int32_t>(ws, L.delay_offs), b, cnt,
-                                      at<float>(ws, L.delay_part), stream);
+    case GRAFX_DELAY:
+    case GRAFX_DELAY_LONG: {
+      const int f = delay_family(t);
+      hipError_t e = launch_delay_bwd(kDelaySlots[f], g, dU, at<float>(ws, L.delay_taps[f]),
+                                      at<int32_t>(ws, L.delay_offs[f]), b, cnt,
+                                      at<float>(ws, L.delay_part[f]), stream);
       // R[n] = sum_t ybar[t - 19] u[t - n]: lag n - 19 of the plain correlation
       const int nb = rv_blocks(g.T + kDelaySurShift);
       if (e == hipSuccess && h->delay_surrogate)
-        e = launch_xcorr_spectra(g, b, cnt, false, 0, nb, at<float4>(ws, L.dl_X), stream);
+        e = launch_xcorr_spectra(g, b, cnt, false, 0, nb, at<float4>(ws, L.dl_X[f]), stream);
       if (e == hipSuccess && h->delay_surrogate)
-        e = launch_xcorr_spectra(g, b, cnt, true, -kDelaySurShift, nb, at<float4>(ws, L.dl_Y0),
+        e = launch_xcorr_spectra(g, b, cnt, true, -kDelaySurShift, nb, at<float4>(ws, L.dl_Y0[f]),
                                  stream);
       return e;
     }
@@ -333,9 +350,11 @@ grafx_status enqueue_render(const grafx_schedule_t* h, const void* dev_plan, int
   if (h->type_count[GRAFX_EQ] > 0)
     e = launch_eq_design(par(GRAFX_EQ), h->type_count[GRAFX_EQ], at<double>(ws, L.eq_h),
                          at<float>(ws, L.eq_H), stream);
-  if (e == hipSuccess && h->type_count[GRAFX_DELAY] > 0)
-    e = launch_delay_design(par(GRAFX_DELAY), h->type_count[GRAFX_DELAY],
-                            at<float>(ws, L.delay_taps), at<int32_t>(ws, L.delay_offs), stream);
+  for (int f = 0; f < 2 && e == hipSuccess; ++f)
+    if (h->type_count[kDelayType[f]] > 0)
+      e = launch_delay_design(kDelaySlots[f], par(kDelayType[f]), h->type_count[kDelayType[f]],
+                              at<float>(ws, L.delay_taps[f]), at<int32_t>(ws, L.delay_offs[f]),
+                              stream);
   if (e == hipSuccess && h->type_count[GRAFX_REVERB] > 0)
     e = launch_rv_design(par(GRAFX_REVERB), h->type_count[GRAFX_REVERB], h->rv_noise, h->rv_len,
                          at<double2>(ws, L.rv_Un), at<float>(ws, L.rv_h), at<float4>(ws, L.rv_H),
@@ -470,19 +489,18 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = launch_eq_grad(par(GRAFX_EQ), at<float>(ws, L.eq_C), eq_tiles(T),
                        at<float>(ws, L.eq_spec), h->type_count[GRAFX_EQ],
                        at<double>(ws, L.eq_s), dpar(GRAFX_EQ), stream);
-  if (e == hipSuccess && dpar(GRAFX_DELAY))
-    e = launch_delay_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_part),
-                          h->type_count[GRAFX_DELAY], delay_groups(T, h->tap_tiles),
-                          dpar(GRAFX_DELAY), stream);
-  if (e == hipSuccess && dpar(GRAFX_DELAY) && h->delay_surrogate) {
-    const int n_del = h->type_count[GRAFX_DELAY];
-    e = launch_xcorr(n_del, rv_blocks(T + kDelaySurShift), kDelaySurParts, kDelaySurLen,
-                     at<float4>(ws, L.dl_Y0),
-                     at<float4>(ws, L.dl_X), at<float4>(ws, L.dl_G), at<float>(ws, L.dl_R),
-                     stream);
-    if (e == hipSuccess)
-      e = launch_delay_phasor_grad(par(GRAFX_DELAY), at<float>(ws, L.delay_taps),
-                                   at<float>(ws, L.dl_R), n_del, dpar(GRAFX_DELAY), stream);
+  for (int f = 0; f < 2; ++f) {
+    const int t = kDelayType[f], M = kDelaySlots[f], n_del = h->type_count[t];
+    if (e != hipSuccess || !dpar(t)) continue;
+    e = launch_delay_grad(M, par(t), at<float>(ws, L.delay_part[f]), n_del,
+                          delay_groups(T, h->tap_tiles), dpar(t), stream);
+    if (e == hipSuccess && h->delay_surrogate)
+      e = launch_xcorr(n_del, rv_blocks(T + kDelaySurShift), delay_sur_parts(M), delay_sur_len(M),
+                       at<float4>(ws, L.dl_Y0[f]), at<float4>(ws, L.dl_X[f]),
+                       at<float4>(ws, L.dl_G[f]), at<float>(ws, L.dl_R[f]), stream);
+    if (e == hipSuccess && h->delay_surrogate)
+      e = launch_delay_phasor_grad(M, par(t), at<float>(ws, L.delay_taps[f]),
+                                   at<float>(ws, L.dl_R[f]), n_del, dpar(t), stream);
   }
   if (e == hipSuccess && dpar(GRAFX_REVERB))
     e = launch_rv_grad(h->type_count[GRAFX_REVERB], T, h->rv_len, par(GRAFX_REVERB),

@@ -12,7 +12,7 @@ namespace grafx {
 
 constexpr int kNumTypes = GRAFX_NUM_TYPES;
 constexpr int64_t kRvMaxLen = GRAFX_REVERB_MAX_LEN;
-constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768};
+constexpr int kParamCount[kNumTypes] = {0, 0, 0, 2, 1024, 4, 1, 220, 1, 4, 5, 768, 880};
 
 // Thread-local error message, set by every failing entry point.
 grafx_status fail(grafx_status code, const std::string& msg);

@@ -1,5 +1,7 @@
-// Multitap delay (paper Sec. 3 "Multitap delay", Eq. 14), limited to five 100 ms slots
-// (<= 500 ms) per channel: y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j].
+// Multitap delay (paper Sec. 3 "Multitap delay", Eq. 14) with M 100 ms slots per channel:
+// y_c[t] = sum_m sum_{j=-19}^{19} c_{c,m}[j] u_c[t - d_{c,m} - j]. Two node types share these
+// kernels, templated on M: the 2 s delay of the paper (M = 20, 880 parameters) and a 500 ms one
+// (M = 5, 220 parameters).
 //
 // Design (once per render): the integer delay of slot m is (m * 4410) plus
 // rint(-arg(z) * 4410 / 2 pi) mod 4410, decided in float32; each slot's 39-tap zero-phase FIR is
@@ -20,6 +22,8 @@
 // reverb's FIR gradient with the output adjoint delayed by 19 samples so that lags start at -19),
 // dL/dRe z = Re Q and dL/dIm z = -Im Q with Q = sum_n G[n] s'(z)[n]
 // = (1/N) sum_{k>=1} k z^(k-1) sum_n G[n] e^(2 pi i k n / N), all in double.
+#include <type_traits>
+
 #include "device_common.h"
 #include "grafx_internal.h"
 #include "kernels.h"
@@ -31,29 +35,29 @@ constexpr int kHop = 2048;
 constexpr int kHalf = 19;                 // taps j = -19..19
 constexpr int kWin = kHop + 2 * kHalf;    // 2086
 constexpr int kPer = kHop / kBlock;       // 8 outputs per thread
-constexpr int kRow = 2 * kDelayTaps * 22; // 220 parameters per node
-
+template <int M>
 __global__ __launch_bounds__(kBlock) void delay_design_kernel(const float* P, float* taps,
                                                               int32_t* offs) {
+  constexpr int kRow = delay_row(M), kCoef = delay_coef(M);
   const int node = blockIdx.x;
   const float* p = P + (int64_t)node * kRow;
-  for (int i = threadIdx.x; i < kDelayCoef; i += kBlock) {
+  for (int i = threadIdx.x; i < kCoef; i += kBlock) {
     const int cm = i / kDelayFir, j = i % kDelayFir - kHalf;  // cm = c * 5 + m
     const float* q = p + cm * 22;
     double acc = exp((double)q[2]);
     for (int k = 1; k <= kHalf; ++k) acc += 2.0 * exp((double)q[2 + k]) * cospi(2.0 * k * j / 39.0);
     const double h0 = acc / 39.0;
     const double win = 0.5 + 0.5 * cospi((double)j / kHalf);
-    taps[(int64_t)node * kDelayCoef + i] = (float)(win * h0);
+    taps[(int64_t)node * kCoef + i] = (float)(win * h0);
   }
-  if (threadIdx.x < 2 * kDelayTaps) {
-    const int cm = threadIdx.x, m = cm % kDelayTaps;
+  if (threadIdx.x < 2 * M) {
+    const int cm = threadIdx.x, m = cm % M;
     const float* q = p + cm * 22;
     const float kScale = (float)(4410.0 / (2.0 * 3.14159265358979323846));
     const float ph = atan2f(q[1], q[0]);
     const int r = (int)rintf(-ph * kScale);
     const int d = ((r % kDelaySlot) + kDelaySlot) % kDelaySlot;
-    offs[(int64_t)node * 2 * kDelayTaps + cm] = m * kDelaySlot + d;
+    offs[(int64_t)node * 2 * M + cm] = m * kDelaySlot + d;
   }
 }
 
@@ -105,7 +109,7 @@ __device__ __forceinline__ void apply_taps(const float* w, const float* c, float
   }
 }
 
-template <bool ADJ>
+template <bool ADJ, int M>
 __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* out,
                                                             const float* taps,
                                                             const int32_t* offs, int node_begin,
@@ -116,18 +120,18 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
   const int slot = g.param_row[node];
   const int64_t T = g.T, t0 = (int64_t)tile * kHop, Tn = node_len(g, node);
   if (t0 >= Tn) return;  // tile past the node's length (uniform over the block)
-  const float* cn = taps + (int64_t)slot * kDelayCoef;
+  const float* cn = taps + (int64_t)slot * delay_coef(M);
   for (int c = 0; c < 2; ++c) {
     float acc[kPer];
 #pragma unroll
     for (int i = 0; i < kPer; ++i) acc[i] = 0.f;
-    for (int m = 0; m < kDelayTaps; ++m) {
-      const int d = offs[(int64_t)slot * 2 * kDelayTaps + c * kDelayTaps + m];
+    for (int m = 0; m < M; ++m) {
+      const int d = offs[(int64_t)slot * 2 * M + c * M + m];
       const int64_t base = ADJ ? t0 + d - kHalf : t0 - d - kHalf;
       __syncthreads();
       stage_window<ADJ>(g, node, c, base, kWin, w);
       __syncthreads();
-      apply_taps<ADJ>(w, cn + (c * kDelayTaps + m) * kDelayFir, acc);
+      apply_taps<ADJ>(w, cn + (c * M + m) * kDelayFir, acc);
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i) ys[c][kPer * threadIdx.x + i] = acc[i];
@@ -149,19 +153,20 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
 // graph merged with longer ones gets the same bits as alone). More tiles amortise the block
 // reduction of the 39 sums per channel-tap; fewer give short steps more blocks.
 
-// Tap gradients: part[slot][group][c*5+m][j] = sum over the group's tiles of
+// Tap gradients: part[slot][group][c*M+m][j] = sum over the group's tiles of
 // sum_t ybar_c[t] u_c[t - d - j]. One block per (node, group, channel-slot): the ten sums of a
 // group are independent, so splitting them over blocks keeps ten times more stage-and-compute
 // chains in flight (the kernel is bound by their latency). Logical blocks are laid out node,
 // group, channel-slot and spread XCD-contiguously, so the five slots of a channel, which stage
 // the same adjoint tiles, share an L2.
+template <int M>
 __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, const int32_t* offs,
                                                                int node_begin, int tiles,
                                                                int groups, float* part) {
   __shared__ float w[kWin];
   __shared__ float yb[kHop];
   __shared__ float red[4][kDelayFir];
-  constexpr int kCM = 2 * kDelayTaps;
+  constexpr int kCM = 2 * M;
   const int nb = (int)(gridDim.x * gridDim.y);
   const int lb = xcd_logical_block((int)(blockIdx.y * gridDim.x + blockIdx.x), nb);
   const int per_node = groups * kCM;
@@ -172,8 +177,8 @@ __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, cons
   const int tile_end = min(min(tiles, tiles_n), (group + 1) * g.tap_tiles);
   const int o0 = kPer * threadIdx.x;
   {
-    const int c = cm / kDelayTaps;
-    const int d = offs[(int64_t)slot * 2 * kDelayTaps + cm];
+    const int c = cm / M;
+    const int d = offs[(int64_t)slot * 2 * M + cm];
     float acc[kDelayFir];
 #pragma unroll
     for (int jj = 0; jj < kDelayFir; ++jj) acc[jj] = 0.f;
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, cons
     __syncthreads();
     if (threadIdx.x < kDelayFir) {
       const int jj = threadIdx.x;
-      part[(((int64_t)slot * groups + group) * 2 * kDelayTaps + cm) * kDelayFir + jj] =
+      part[(((int64_t)slot * groups + group) * 2 * M + cm) * kDelayFir + jj] =
           red[0][jj] + red[1][jj] + red[2][jj] + red[3][jj];
     }
   }
@@ -210,13 +215,15 @@ __global__ __launch_bounds__(kBlock) void delay_tapgrad_kernel(GraphView g, cons
 
 // Sum tap-gradient partials over groups and map them to the log-magnitudes:
 // dL/dlogmag_k = A_k (kappa_k / 39) sum_j cbar[j] v[j] cos(2 pi k j / 39).
+template <int M>
 __global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, const float* part,
                                                             int groups, float* dP) {
-  __shared__ double cb[kDelayCoef];
+  constexpr int kRow = delay_row(M), kCoef = delay_coef(M);
+  __shared__ double cb[kCoef];
   const int slot = blockIdx.x;
-  for (int i = threadIdx.x; i < kDelayCoef; i += kBlock) {
+  for (int i = threadIdx.x; i < kCoef; i += kBlock) {
     double s = 0.0;
-    for (int gi = 0; gi < groups; ++gi) s += part[((int64_t)slot * groups + gi) * kDelayCoef + i];
+    for (int gi = 0; gi < groups; ++gi) s += part[((int64_t)slot * groups + gi) * kCoef + i];
     const int j = i % kDelayFir - kHalf;
     cb[i] = s * (0.5 + 0.5 * cospi((double)j / kHalf));
   }
@@ -241,15 +248,17 @@ __global__ __launch_bounds__(kBlock) void delay_grad_kernel(const float* P, cons
 // above, each thread taking the k = 1 + thread, 1 + thread + 256, ... terms; the inner sum over n
 // steps the phasor e^(2 pi i k n / N) by multiplication, restarting from an exact value every 256
 // steps; per-thread partials are added in a fixed order.
+template <int M>
 __global__ __launch_bounds__(kBlock) void delay_phasor_grad_kernel(const float* P,
                                                                    const float* taps,
                                                                    const float* R, int64_t Lr,
                                                                    float* dP) {
+  constexpr int kRow = delay_row(M);
   __shared__ double G[kDelaySlot];
   __shared__ double2 red[kBlock / 64];
-  const int slot = blockIdx.x, cm = blockIdx.y;  // cm = channel * 5 + slot
-  const int c = cm / kDelayTaps, m = cm % kDelayTaps;
-  const float* tp = taps + (int64_t)slot * kDelayCoef + cm * kDelayFir;
+  const int slot = blockIdx.x, cm = blockIdx.y;  // cm = channel * M + slot
+  const int c = cm / M, m = cm % M;
+  const float* tp = taps + (int64_t)slot * delay_coef(M) + cm * kDelayFir;
   const float* Rc = R + ((int64_t)slot * 2 + c) * Lr + (int64_t)m * kDelaySlot;
   for (int n = threadIdx.x; n < kDelaySlot; n += kBlock) {
     double acc = 0.0;
@@ -308,45 +317,66 @@ int delay_groups(int64_t T, int tap_tiles) {
   return (delay_tiles(T) + tap_tiles - 1) / tap_tiles;
 }
 
-hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s) {
+// Calls body(std::integral_constant<int, M>) for the slot counts the library supports.
+template <typename F>
+hipError_t with_slots(int M, F&& body) {
+  if (M == kDelayTaps) return body(std::integral_constant<int, kDelayTaps>{});
+  if (M == kDelayTapsLong) return body(std::integral_constant<int, kDelayTapsLong>{});
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_delay_design(int M, const float* P, int n, float* taps, int32_t* offs,
+                               hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  delay_design_kernel<<<n, kBlock, 0, s>>>(P, taps, offs);
-  return hipGetLastError();
+  return with_slots(M, [&](auto m) {
+    delay_design_kernel<decltype(m)::value><<<n, kBlock, 0, s>>>(P, taps, offs);
+    return hipGetLastError();
+  });
 }
 
-hipError_t launch_delay_fwd(const GraphView& g, float* U, const float* taps, const int32_t* offs,
-                            int node_begin, int n_nodes, hipStream_t s) {
+hipError_t launch_delay_fwd(int M, const GraphView& g, float* U, const float* taps,
+                            const int32_t* offs, int node_begin, int n_nodes, hipStream_t s) {
   const int tiles = delay_tiles(g.T);
-  delay_conv_kernel<false><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, U, taps, offs, node_begin,
-                                                                   tiles);
-  return hipGetLastError();
+  return with_slots(M, [&](auto m) {
+    delay_conv_kernel<false, decltype(m)::value><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(
+        g, U, taps, offs, node_begin, tiles);
+    return hipGetLastError();
+  });
 }
 
-hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
+hipError_t launch_delay_bwd(int M, const GraphView& g, float* dU, const float* taps,
                             const int32_t* offs, int node_begin, int n_nodes, float* part,
                             hipStream_t s) {
   const int tiles = delay_tiles(g.T);
-  delay_conv_kernel<true><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, dU, taps, offs, node_begin,
-                                                                  tiles);
   const int groups = delay_groups(g.T, g.tap_tiles);
-  delay_tapgrad_kernel<<<dim3(groups * 2 * kDelayTaps, n_nodes), kBlock, 0, s>>>(
-      g, offs, node_begin, tiles, groups, part);
-  return hipGetLastError();
+  return with_slots(M, [&](auto m) {
+    constexpr int kM = decltype(m)::value;
+    delay_conv_kernel<true, kM><<<dim3(tiles, n_nodes), kBlock, 0, s>>>(g, dU, taps, offs,
+                                                                        node_begin, tiles);
+    delay_tapgrad_kernel<kM><<<dim3(groups * 2 * kM, n_nodes), kBlock, 0, s>>>(
+        g, offs, node_begin, tiles, groups, part);
+    return hipGetLastError();
+  });
 }
 
-hipError_t launch_delay_grad(const float* P, const float* part, int n, int groups, float* dP,
-                             hipStream_t s) {
+hipError_t launch_delay_grad(int M, const float* P, const float* part, int n, int groups,
+                             float* dP, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  delay_grad_kernel<<<n, kBlock, 0, s>>>(P, part, groups, dP);
-  return hipGetLastError();
+  return with_slots(M, [&](auto m) {
+    delay_grad_kernel<decltype(m)::value><<<n, kBlock, 0, s>>>(P, part, groups, dP);
+    return hipGetLastError();
+  });
 }
 
-hipError_t launch_delay_phasor_grad(const float* P, const float* taps, const float* R, int n,
-                                    float* dP, hipStream_t s) {
+hipError_t launch_delay_phasor_grad(int M, const float* P, const float* taps, const float* R,
+                                    int n, float* dP, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  delay_phasor_grad_kernel<<<dim3(n, 2 * kDelayTaps), kBlock, 0, s>>>(P, taps, R, kDelaySurLen,
-                                                                      dP);
-  return hipGetLastError();
+  return with_slots(M, [&](auto m) {
+    constexpr int kM = decltype(m)::value;
+    delay_phasor_grad_kernel<kM><<<dim3(n, 2 * kM), kBlock, 0, s>>>(P, taps, R,
+                                                                    delay_sur_len(kM), dP);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace grafx

@@ -96,32 +96,34 @@ hipError_t launch_comp_ar_bwd(const GraphView& g, float* dU, const float* P, int
                               hipStream_t s);
 
 // ---- delay (k_delay.hip) -------------------------------------------------------------------
-constexpr int kDelayTaps = 5, kDelayFir = 39, kDelaySlot = 4410;
-constexpr int kDelayCoef = 2 * kDelayTaps * kDelayFir;  // 390 per node
+// M 100 ms slots per channel: M = 5 (node type delay, 500 ms) or M = 20 (delay_long, 2 s).
+constexpr int kDelayTaps = 5, kDelayTapsLong = 20, kDelayFir = 39, kDelaySlot = 4410;
+constexpr int delay_coef(int M) { return 2 * M * kDelayFir; }  // filter taps per node
+constexpr int delay_row(int M) { return 2 * M * 22; }          // parameters per node
 int delay_tiles(int64_t T);
 constexpr int kTapTilesMin = 4;  // smallest tap-gradient group (sizes the partials)
 int delay_groups(int64_t T, int tap_tiles);  // tile groups per node in the tap-gradient pass
-// taps: float [n][390]; offs: int32 [n][10]
-hipError_t launch_delay_design(const float* P, int n, float* taps, int32_t* offs, hipStream_t s);
-hipError_t launch_delay_fwd(const GraphView& g, float* U, const float* taps, const int32_t* offs,
-                            int node_begin, int n_nodes, hipStream_t s);
-// part: float [n][groups][390]
-hipError_t launch_delay_bwd(const GraphView& g, float* dU, const float* taps,
+// taps: float [n][delay_coef(M)]; offs: int32 [n][2 M]
+hipError_t launch_delay_design(int M, const float* P, int n, float* taps, int32_t* offs,
+                               hipStream_t s);
+hipError_t launch_delay_fwd(int M, const GraphView& g, float* U, const float* taps,
+                            const int32_t* offs, int node_begin, int n_nodes, hipStream_t s);
+// part: float [n][groups][delay_coef(M)]
+hipError_t launch_delay_bwd(int M, const GraphView& g, float* dU, const float* taps,
                             const int32_t* offs, int node_begin, int n_nodes, float* part,
                             hipStream_t s);
-hipError_t launch_delay_grad(const float* P, const float* part, int n, int groups, float* dP,
-                             hipStream_t s);
-// Delay-time surrogate: lags -19 .. 5 x 4410 + 19 of the input/adjoint cross-correlation (the
+hipError_t launch_delay_grad(int M, const float* P, const float* part, int n, int groups,
+                             float* dP, hipStream_t s);
+// Delay-time surrogate: lags -19 .. M x 4410 + 19 of the input/adjoint cross-correlation (the
 // output adjoint delayed by kDelaySurShift, so that the lags start at 0), rounded up to whole
-// 2048-lag partitions
-constexpr int kDelaySurShift = (kDelayFir - 1) / 2;                       // 19
-constexpr int kDelaySurLags = kDelayTaps * kDelaySlot + kDelayFir - 1;    // 22088
-constexpr int kDelaySurParts = (kDelaySurLags + 2047) / 2048;             // 11
-constexpr int64_t kDelaySurLen = (int64_t)kDelaySurParts * 2048;
-// R: float [n][2][kDelaySurLen] correlation (launch_xcorr); writes the phasor entries of dP
+// 2048-lag partitions (M = 5: 11 partitions; M = 20: 44)
+constexpr int kDelaySurShift = (kDelayFir - 1) / 2;  // 19
+constexpr int delay_sur_parts(int M) { return (M * kDelaySlot + kDelayFir - 1 + 2047) / 2048; }
+constexpr int64_t delay_sur_len(int M) { return (int64_t)delay_sur_parts(M) * 2048; }
+// R: float [n][2][delay_sur_len(M)] correlation (launch_xcorr); writes the phasor entries of dP
 // (after launch_delay_grad, which sets them to 0)
-hipError_t launch_delay_phasor_grad(const float* P, const float* taps, const float* R, int n,
-                                    float* dP, hipStream_t s);
+hipError_t launch_delay_phasor_grad(int M, const float* P, const float* taps, const float* R,
+                                    int n, float* dP, hipStream_t s);
 
 // ---- reverb (k_reverb.hip) ------------------------------------------------------------------
 constexpr int kRvFft = 384, kRvHop = 192;  // STFT of the noise and of the masks

@@ -66,13 +66,20 @@ def run(w, seed, surrogate=True):
                                                                          ref["S"])}
     for t, p in P.items():
         errs[synth.TYPE_NAMES[t]] = grad_err(p.grad.cpu().numpy(), ref[t])
-    dd = P[synth.DELAY].grad.cpu().numpy().reshape(-1, 2, 5, 22)
-    rd = ref[synth.DELAY].reshape(-1, 2, 5, 22)
-    # the phasor entries alone (log-magnitude entries set to the oracle's), judged like the whole
-    # tensor: each (re z, im z) pair against its largest entry over the graph's delay nodes
-    only = rd.copy()
-    only[..., :2] = dd[..., :2]
-    errs["phasor"] = grad_err(only.reshape(rd.shape[0], -1), rd.reshape(rd.shape[0], -1))
+    out = {}
+    for t, M in ((synth.DELAY, 5), (synth.DELAY_LONG, 20)):
+        if t not in P:
+            continue
+        dd = P[t].grad.cpu().numpy().reshape(-1, 2, M, 22)
+        rd = ref[t].reshape(-1, 2, M, 22)
+        # the phasor entries alone (log-magnitude entries set to the oracle's), judged like the
+        # whole tensor: each (re z, im z) pair against its largest entry over the type's nodes
+        only = rd.copy()
+        only[..., :2] = dd[..., :2]
+        errs[f"phasor_{synth.TYPE_NAMES[t]}"] = grad_err(only.reshape(rd.shape[0], -1),
+                                                         rd.reshape(rd.shape[0], -1))
+        out[t] = (dd, rd)
+    dd, rd = out.get(synth.DELAY, out.get(synth.DELAY_LONG))
     return errs, dd, rd
 
 

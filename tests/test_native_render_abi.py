@@ -32,7 +32,7 @@ def console():
 def params(sched, skip=None):
     arr = _lib.ptr_array()
     for t in range(_lib.NUM_TYPES):
-        if sched.type_count[t] and t != skip and t in (3, 4, 5, 6, 7, 8, 9, 10, 11):
+        if sched.type_count[t] and t != skip and t in (3, 4, 5, 6, 7, 8, 9, 10, 11, 12):
             arr[t] = addr(10 + t)
     return arr
 
