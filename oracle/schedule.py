@@ -39,7 +39,8 @@ import dataclasses
 import numpy as np
 
 IN, OUT = 0, 1
-NUM_TYPES = 11
+NUM_TYPES = 13  # in, out, mix, gain_pan, eq, compressor, imager, delay, tanh, noisegate,
+#                  compressor_ar, reverb, delay_long
 
 ONE_BY_ONE, GREEDY, BEAM, OPTIMAL = 0, 1, 2, 3
 METHOD_NAMES = {"one_by_one": ONE_BY_ONE, "greedy": GREEDY, "beam": BEAM, "optimal": OPTIMAL}

@@ -99,7 +99,7 @@ def test_error_codes_match_oracle():
     assert _err([0, 3, 1], [[0, 1, 1], [1, 2, 0]]) == "GRAFX_E_GRAPH"
     assert _err([0, 3, 1, 3], [[0, 1, 2], [1, 2, 3]]) == "GRAFX_E_GRAPH"
     assert _err([0, 3], [[0], [1]]) == "GRAFX_E_GRAPH"
-    assert _err([0, 12, 1], [[0, 1], [1, 2]]) == "GRAFX_E_TYPE"
+    assert _err([0, 13, 1], [[0, 1], [1, 2]]) == "GRAFX_E_TYPE"
     assert _err([0, 3, 1], [[0, 1], [1, 2]], edge_type=np.ones((2, 2))) == "GRAFX_E_TYPE"
     assert _err([0, 3, 1], [[0, 1], [1, 7]]) == "GRAFX_E_GRAPH"
     assert _err([0, 3, 1], [[0, 1], [1, 2]], method="beam", beam_width=0) == "GRAFX_E_ARG"
@@ -245,3 +245,14 @@ def test_concurrent_threaded_searches():
                 assert np.array_equal(a, b), f
     finally:
         set_schedule_threads(prev)
+
+
+def test_reverb_and_long_delay_schedule_like_the_oracle():
+    """Graphs with the reverb (type 11) and the 2 s delay (type 12) get the oracle's schedule,
+    read/write lists and parameter rows under every method."""
+    for seed in range(4):
+        w = synth.random_workload(1200 + seed, 12, 64, types=(synth.MIX, synth.REVERB,
+                                                              synth.DELAY_LONG, synth.EQ,
+                                                              synth.DELAY))
+        for code, name in METHODS:
+            assert_same(w.graph, code, name, beam=8)

@@ -200,7 +200,7 @@ def test_errors():
         osch.schedule(np.array([0, 3]), np.array([[0], [1]]))
     assert e.value.kind == "graph"  # no output
     with pytest.raises(osch.ScheduleError) as e:
-        osch.schedule(np.array([0, 12, 1]), ok_e)
+        osch.schedule(np.array([0, 13, 1]), ok_e)
     assert e.value.kind == "type"
     with pytest.raises(osch.ScheduleError) as e:
         osch.schedule(ok_t, ok_e, edge_type=np.ones((2, 2)))
