@@ -412,6 +412,25 @@ grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* sched, const floa
 grafx_status grafx_schedule_set_delay_surrogate(grafx_schedule_t* sched, int32_t enable);
 
 /*
+ * grafx_delay_phasor_regularise -- the optimiser-side treatment of the delay-time gradients that
+ * the paper applies with the surrogate (Sec. 3 "Multitap delay": each delay's gradient is
+ * normalised and z is regularised towards the unit circle; the paper gives neither the norm nor
+ * the regulariser, so this is one reading). For every phasor of n nodes of one delay type, in
+ * place on dP: the pair (dL/dRe z, dL/dIm z) is scaled to unit length (a zero pair stays zero),
+ * then the gradient of weight * (|z| - 1)^2, i.e. 2 weight (|z| - 1) z / |z| (zero at z = 0), is
+ * added. Log-magnitude entries are not touched.
+ *   delay_type  GRAFX_DELAY (rows of 220) or GRAFX_DELAY_LONG (rows of 880)
+ *   n           number of rows (>= 0)
+ *   P, dP       device float32 [n][row]: the parameters and their gradient (as written by
+ *               grafx_render_backward with the surrogate on)
+ *   weight      regulariser weight, finite and >= 0
+ * Errors: GRAFX_E_TYPE (other type), GRAFX_E_SHAPE (n < 0, misaligned), GRAFX_E_ARG (NULL
+ * buffers with n > 0, bad weight), GRAFX_E_HIP.
+ */
+grafx_status grafx_delay_phasor_regularise(int32_t delay_type, int32_t n, const float* P,
+                                           float* dP, float weight, hipStream_t stream);
+
+/*
  * grafx_workspace_error -- the error word of the dynamics kernels (compressor, noisegate,
  * compressor_ar; the chunked scan of Eq. 8) in a render workspace: enqueues on `stream` a copy of
  * the 32-bit word into `word` (host or device memory; read it after the stream has completed).

@@ -26,7 +26,7 @@ EXPORTS = ("grafx_schedule", "grafx_schedule_with_lengths", "grafx_schedule_free
            "grafx_encoder_params", "grafx_schedule_set_tuning", "grafx_schedule_get_tuning",
            "grafx_set_schedule_threads", "grafx_workspace_error", "grafx_last_error",
            "grafx_render_noalloc", "grafx_schedule_set_reverb_noise",
-           "grafx_schedule_set_delay_surrogate")
+           "grafx_schedule_set_delay_surrogate", "grafx_delay_phasor_regularise")
 
 
 class GrafxError(RuntimeError):
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
         "grafx_schedule_get_tuning": (i32, [vp, i32, c_i32p]),
         "grafx_schedule_set_reverb_noise": (i32, [vp, vp, i64]),
         "grafx_schedule_set_delay_surrogate": (i32, [vp, i32]),
+        "grafx_delay_phasor_regularise": (i32, [i32, i32, vp, vp, ctypes.c_float, vp]),
         "grafx_workspace_error": (i32, [vp, i64, vp, sz, vp, vp]),
         "grafx_last_error": (ctypes.c_char_p, []),
     }

@@ -235,6 +235,21 @@ class _Render(torch.autograd.Function):
         return (None, None, dS, *dP)
 
 
+def delay_phasor_regularise(delay_type, P: torch.Tensor, dP: torch.Tensor,
+                            weight: float) -> None:
+    """grafx_delay_phasor_regularise, in place on dP: unit-length phasor gradients plus the
+    gradient of weight * (|z| - 1)^2 (delay_type: "delay" / "delay_long" or their codes)."""
+    t = TYPE_CODES[delay_type] if isinstance(delay_type, str) else int(delay_type)
+    for x in (P, dP):
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2 or \
+                x.shape[1] != N_PARAMS[t]:
+            raise ValueError(f"P and dP must be contiguous float32 [n, {N_PARAMS[t]}]")
+    if P.shape != dP.shape:
+        raise ValueError("P and dP must have one shape")
+    check(load().grafx_delay_phasor_regularise(t, P.shape[0], P.data_ptr(), dP.data_ptr(),
+                                               float(weight), _stream(dP.device)))
+
+
 def render(sched: Schedule, S: torch.Tensor, P: dict, return_U: bool = False):
     """Batched render of the scheduled graph (paper Algorithm 1). S: [K, 2, T] float32 on the
     GPU; P: type (code or name) -> float32 [|V_t|, N_t]. Returns Y [|V_N|, 2, T] (and U

@@ -603,6 +603,22 @@ grafx_status grafx_schedule_set_reverb_noise(grafx_schedule_t* h, const float* n
   return GRAFX_OK;
 }
 
+grafx_status grafx_delay_phasor_regularise(int32_t delay_type, int32_t n, const float* P,
+                                           float* dP, float weight, hipStream_t stream) {
+  clear_error();
+  if (delay_type != GRAFX_DELAY && delay_type != GRAFX_DELAY_LONG)
+    return fail(GRAFX_E_TYPE, "delay_type must be GRAFX_DELAY or GRAFX_DELAY_LONG");
+  if (n < 0) return fail(GRAFX_E_SHAPE, "n must be >= 0");
+  if (n > 0 && (!P || !dP)) return fail(GRAFX_E_ARG, "P or dP is NULL");
+  if (!(weight >= 0.0f) || weight > 3.0e38f)
+    return fail(GRAFX_E_ARG, "weight must be finite and >= 0");
+  if ((P && !aligned(P, 4)) || (dP && !aligned(dP, 4)))
+    return fail(GRAFX_E_SHAPE, "P and dP must be 4-byte aligned");
+  return hip_status(launch_delay_phasor_regularise(kDelaySlots[delay_family(delay_type)], n, P,
+                                                   dP, weight, stream),
+                    "delay_phasor_regularise launch");
+}
+
 grafx_status grafx_schedule_set_delay_surrogate(grafx_schedule_t* h, int32_t enable) {
   clear_error();
   if (!h) return fail(GRAFX_E_ARG, "schedule is NULL");

@@ -309,6 +309,25 @@ __global__ __launch_bounds__(kBlock) void delay_phasor_grad_kernel(const float* 
   }
 }
 
+// Optimiser-side treatment of the phasor gradients (the paper normalises each delay's gradient and
+// pulls z towards the unit circle, without constants): every (re z, im z) gradient pair is scaled
+// to unit length (a zero pair stays zero), then the gradient of weight * (|z| - 1)^2,
+// 2 weight (|z| - 1) z / |z| (zero at z = 0), is added. One thread per phasor.
+__global__ __launch_bounds__(kBlock) void delay_phasor_regularise_kernel(int M, int n,
+                                                                         const float* P, float* dP,
+                                                                         float weight) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;  // phasor index: node * 2 M + c * M + m
+  if (i >= n * 2 * M) return;
+  const int64_t o = (int64_t)i * 22;  // rows are [channel][slot][22], contiguous per node
+  const double gr = dP[o], gi = dP[o + 1];
+  const double gn = sqrt(gr * gr + gi * gi);
+  const double zr = P[o], zi = P[o + 1];
+  const double r = sqrt(zr * zr + zi * zi);
+  const double s = r > 0.0 ? 2.0 * (double)weight * (r - 1.0) / r : 0.0;
+  dP[o] = (float)((gn > 0.0 ? gr / gn : 0.0) + s * zr);
+  dP[o + 1] = (float)((gn > 0.0 ? gi / gn : 0.0) + s * zi);
+}
+
 }  // namespace
 
 int delay_tiles(int64_t T) { return (int)((T + kHop - 1) / kHop); }
@@ -366,6 +385,15 @@ hipError_t launch_delay_grad(int M, const float* P, const float* part, int n, in
     delay_grad_kernel<decltype(m)::value><<<n, kBlock, 0, s>>>(P, part, groups, dP);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_delay_phasor_regularise(int M, int n, const float* P, float* dP, float weight,
+                                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int phasors = n * 2 * M;
+  delay_phasor_regularise_kernel<<<(phasors + kBlock - 1) / kBlock, kBlock, 0, s>>>(M, n, P, dP,
+                                                                                   weight);
+  return hipGetLastError();
 }
 
 hipError_t launch_delay_phasor_grad(int M, const float* P, const float* taps, const float* R,

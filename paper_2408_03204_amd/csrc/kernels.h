@@ -124,6 +124,9 @@ constexpr int64_t delay_sur_len(int M) { return (int64_t)delay_sur_parts(M) * 20
 // (after launch_delay_grad, which sets them to 0)
 hipError_t launch_delay_phasor_grad(int M, const float* P, const float* taps, const float* R,
                                     int n, float* dP, hipStream_t s);
+// dP phasor entries: unit-length per phasor, plus the gradient of weight * (|z| - 1)^2
+hipError_t launch_delay_phasor_regularise(int M, int n, const float* P, float* dP, float weight,
+                                          hipStream_t s);
 
 // ---- reverb (k_reverb.hip) ------------------------------------------------------------------
 constexpr int kRvFft = 384, kRvHop = 192;  // STFT of the noise and of the masks

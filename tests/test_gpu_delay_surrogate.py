@@ -114,3 +114,29 @@ def test_delay_phasors_have_no_gradient_by_default():
     errs, dd, rd = run(w, 8, surrogate=False)
     check(errs)
     assert np.all(dd[..., :2] == 0.0) and np.all(rd[..., :2] == 0.0)
+
+
+@pytest.mark.parametrize("delay_type,M", [(synth.DELAY, 5), (synth.DELAY_LONG, 20)])
+def test_phasor_regularise_matches_the_oracle_helpers(delay_type, M):
+    """Unit-length phasor gradients plus the unit-circle penalty's gradient, against the oracle's
+    helpers (their constants are not in the paper: parity unpinned, the arithmetic is checked)."""
+    from oracle import reverb as RV
+    from paper_2408_03204_amd import delay_phasor_regularise
+    rng = np.random.default_rng(17 + M)
+    n, weight = 3, 0.37
+    P = rng.normal(size=(n, 2, M, 22)).astype(np.float32)
+    dP = rng.normal(size=(n, 2, M, 22)).astype(np.float32)
+    dP[0, 1, 2, :2] = 0.0  # a zero pair stays zero before the penalty
+    P[1, 0, 1, :2] = 0.0   # z = 0: no penalty gradient
+    g = dP[..., :2].astype(np.float64)
+    z = P[..., 0].astype(np.float64) + 1j * P[..., 1].astype(np.float64)
+    _, pen = RV.unit_circle_penalty(z, weight)
+    want = dP.astype(np.float64).copy()
+    want[..., :2] = RV.normalise_phasor_grads(g) + pen
+    Pd = torch.as_tensor(P.reshape(n, -1)).cuda()
+    dPd = torch.as_tensor(dP.reshape(n, -1)).cuda()
+    delay_phasor_regularise(delay_type, Pd, dPd, weight)
+    torch.cuda.synchronize()
+    got = dPd.cpu().numpy().reshape(n, 2, M, 22).astype(np.float64)
+    assert np.array_equal(got[..., 2:], dP[..., 2:])
+    assert np.max(np.abs(got - want)) < 1e-5 * max(1.0, np.max(np.abs(want)))

@@ -240,3 +240,16 @@ def test_delay_surrogate_setting():
     assert s.workspace_bytes(1 << 16, True) > bwd
     s.set_delay_surrogate(False)
     assert s.workspace_bytes(1 << 16, True) == bwd
+
+
+def test_delay_phasor_regularise_rejects_bad_arguments():
+    lib = load()
+    f = lib.grafx_delay_phasor_regularise
+    assert f(4, 1, addr(1), addr(2), 1.0, None) == 4  # GRAFX_E_TYPE: not a delay type
+    assert f(7, -1, addr(1), addr(2), 1.0, None) == E_SHAPE
+    assert f(7, 1, None, addr(2), 1.0, None) == E_ARG
+    assert f(12, 1, addr(1), None, 1.0, None) == E_ARG
+    assert f(7, 1, addr(1), addr(2), -1.0, None) == E_ARG
+    assert f(7, 1, addr(1), addr(2), float("nan"), None) == E_ARG
+    assert f(7, 1, addr(1, 2), addr(2), 1.0, None) == E_SHAPE
+    assert f(7, 0, None, None, 0.0, None) in (OK, 8)  # nothing to do (no launch needed)
