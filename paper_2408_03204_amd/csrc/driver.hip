@@ -110,7 +110,8 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.rv_Y0 = take(n_rv * rv_nb * kRvStride * sizeof(float4));
     L.rv_G = take(n_rv * rv_P * kRvStride * sizeof(float4));
     L.rv_hbar = take(n_rv * 2 * rv_L * sizeof(float));
-    L.rv_part = take(n_rv * 2 * rv_M * (kRvFft / 2 + 1) * sizeof(double));
+    L.rv_part = take(n_rv * (n_rv ? (size_t)rv_grad_blocks(h->rv_len) : 0) * 2 *
+                     (kRvFft / 2 + 1) * sizeof(double2));
     // delay-time surrogate: input-window and adjoint-block spectra, cross-spectra, correlation
     for (int f = 0; f < 2; ++f) {
       const size_t n_sur = h->delay_surrogate ? (size_t)h->type_count[kDelayType[f]] : 0;

@@ -130,49 +130,83 @@ __global__ __launch_bounds__(kBlock) void rv_noise_stft_kernel(const float* nois
 }
 
 // ---- impulse response -------------------------------------------------------------------------
-// Block (hop s, reverb slot), thread t: sample n = 192 s + t of h_m and h_s, from the second half
-// of frame s and the first half of frame s + 1, then left/right.
-__global__ __launch_bounds__(kHop) void rv_ir_kernel(const float* P, const double2* Un, int64_t L,
-                                                     int M, float* h) {
-  __shared__ double2 tw[kF];
-  __shared__ double2 X[2][2][kK];  // [mid, side][frame s, s + 1][bin]
-  const int s = blockIdx.x, slot = blockIdx.y;
+// Sample 192 s + t of h_x (t < 192) is the sum of frame s at q = 192 + t and frame s + 1 at q = t.
+// Since e^(2 pi i k (192 + t) / 384) = (-1)^k e^(2 pi i k t / 384), that is one real inverse DFT
+// per hop s of the combined spectrum Y_s[k] = c_k / 384 (X_{s+1}[k] + (-1)^k X_s[k]), X_m the
+// masked frame spectrum and c_k = 1 at k = 0, 192, else 2: h_x[192 s + t] = sum_k Re(Y_s[k]
+// e^(2 pi i k t / 384)). A block takes kIrHops hops of one reverb slot: Y of both channels in LDS
+// (double), then each thread sums, for three samples t = r, r + 64, r + 128 and four hops, both
+// channels (24 accumulators), stepping the three twiddles by multiplication (restarted from exact
+// values every 64 bins); a wave's lanes all read the same Y entry (LDS broadcast).
+constexpr int kIrHops = 8;                 // hops per block
+constexpr int kIrHopsPerWave = 4;          // hops per wave (two waves)
+constexpr int kIrThreads = 128;
+
+__global__ __launch_bounds__(kIrThreads) void rv_ir_kernel(const float* P, const double2* Un,
+                                                           int64_t L, int M, float* h) {
+  __shared__ double2 Y[2][kIrHops][kK];
+  const int s0 = blockIdx.x * kIrHops, slot = blockIdx.y;
   const float* p = P + (int64_t)slot * kRvParams;
-  fill_tw384(tw);
-  for (int i = threadIdx.x; i < 2 * 2 * kK; i += kHop) {
-    const int x = i / (2 * kK), f = (i / kK) % 2, k = i % kK;
-    const int m = s + f;
-    const double mu = mask_at(p, x, k, m);
-    const double2 u = Un[((int64_t)x * M + m) * kK + k];
-    X[x][f][k] = make_double2(u.x * mu, u.y * mu);
+  for (int i = threadIdx.x; i < 2 * kIrHops * kK; i += kIrThreads) {
+    const int x = i / (kIrHops * kK), j = (i / kK) % kIrHops, k = i % kK;
+    const int s = s0 + j;
+    double2 y = make_double2(0.0, 0.0);
+    if (s < M - 1) {
+      const double mu0 = mask_at(p, x, k, s), mu1 = mask_at(p, x, k, s + 1);
+      const double2 u0 = Un[((int64_t)x * M + s) * kK + k];
+      const double2 u1 = Un[((int64_t)x * M + s + 1) * kK + k];
+      const double sg = (k & 1) ? -1.0 : 1.0;
+      const double c = (k == 0 || k == kK - 1) ? 1.0 / kF : 2.0 / kF;
+      y = make_double2(c * (u1.x * mu1 + sg * u0.x * mu0), c * (u1.y * mu1 + sg * u0.y * mu0));
+    }
+    Y[x][j][k] = y;
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  double hx[2];
+  const int r = threadIdx.x & 63, hg = threadIdx.x >> 6;  // sample group, hop group (= wave)
+  double acc[3][kIrHopsPerWave][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    double acc = 0.0;
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      // real inverse DFT at q: (X[0] + (-1)^q X[192] + 2 sum_{k=1}^{191} Re(X[k] e^(i theta))) / N
-      const int q = f == 0 ? kHop + t : t;
-      const double2* Xf = X[x][f];
-      const double a = Xf[0].x + ((q & 1) ? -Xf[kK - 1].x : Xf[kK - 1].x);
-      double b = 0.0;
-      for (int k = 1; k < kK - 1; ++k) {
-        const double2 w = tw[(k * q) % kF];
-        b = fma(Xf[k].x, w.x, b);
-        b = fma(-Xf[k].y, w.y, b);
+    for (int j = 0; j < kIrHopsPerWave; ++j) acc[i][j][0] = acc[i][j][1] = 0.0;
+  double sr[3], si[3];  // twiddle steps e^(2 pi i t / 384)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) sincospi(2.0 * (r + 64 * i) / kF, &si[i], &sr[i]);
+  for (int k0 = 0; k0 < kK; k0 += 64) {
+    double wr[3], wi[3];  // e^(2 pi i k0 t / 384), exactly
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      sincospi(2.0 * (double)((k0 * (r + 64 * i)) % kF) / kF, &wi[i], &wr[i]);
+    const int k1 = min(k0 + 64, kK);
+    for (int k = k0; k < k1; ++k) {
+#pragma unroll
+      for (int j = 0; j < kIrHopsPerWave; ++j) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const double2 y = Y[x][hg * kIrHopsPerWave + j][k];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i][j][x] = fma(y.x, wr[i], fma(-y.y, wi[i], acc[i][j][x]));
+        }
       }
-      acc += (a + 2.0 * b) / kF;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double t = wr[i] * sr[i] - wi[i] * si[i];
+        wi[i] = fma(wr[i], si[i], wi[i] * sr[i]);
+        wr[i] = t;
+      }
     }
-    hx[x] = acc;
   }
-  const int64_t n = (int64_t)kHop * s + t;
-  if (n < L) {
-    float* hs = h + (int64_t)slot * 2 * L;
-    hs[n] = (float)(0.5 * (hx[0] + hx[1]));
-    hs[L + n] = (float)(0.5 * (hx[0] - hx[1]));
+  float* hs = h + (int64_t)slot * 2 * L;
+#pragma unroll
+  for (int j = 0; j < kIrHopsPerWave; ++j) {
+    const int s = s0 + hg * kIrHopsPerWave + j;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int64_t n = (int64_t)kHop * s + r + 64 * i;
+      if (s < M - 1 && n < L) {
+        hs[n] = (float)(0.5 * (acc[i][j][0] + acc[i][j][1]));
+        hs[L + n] = (float)(0.5 * (acc[i][j][0] - acc[i][j][1]));
+      }
+    }
   }
 }
 
@@ -335,53 +369,113 @@ __global__ __launch_bounds__(kBlock) void rv_hbar_kernel(const float4* Gs, int p
   }
 }
 
-// Per frame m and mid/side x: fbar[q] = hbar_x[192 m - 192 + q] (hbar_m = (hbar_l + hbar_r) / 2,
-// hbar_s = (hbar_l - hbar_r) / 2), V[k] = sum_q fbar[q] e^(2 pi i k q / 384), and the gradient with
-// respect to the log-mask entry (k, m): (c_k / 384) Re(Un[k] V[k]) mu[k] (c_k = 1 at k = 0 and
-// 192, else 2).
-__global__ __launch_bounds__(kBlock) void rv_frame_grad_kernel(const float* P, const double2* Un,
-                                                               const float* hbar, int64_t L, int M,
-                                                               double* part) {
-  __shared__ double2 tw[kF];
-  __shared__ double fb[kF];
-  const int m = blockIdx.x, x = blockIdx.y, slot = blockIdx.z;
-  fill_tw384(tw);
+// Mask gradient. Frame m of channel x (mid, side) reads fbar[q] = hbar_x[192 m - 192 + q]
+// (hbar_m = (hbar_l + hbar_r) / 2, hbar_s = (hbar_l - hbar_r) / 2), and the gradient with respect
+// to the log-mask entry (k, m) is (c_k / 384) Re(Un[k] V_m[k]) mu[k] with
+// V_m[k] = sum_q fbar[q] e^(2 pi i k q / 384) = D_{m-1}[k] + (-1)^k D_m[k], where
+// D_s[k] = sum_{t<192} hbar_x[192 s + t] e^(2 pi i k t / 384) is the DFT of one hop segment. A
+// block takes kGradFrames frames of one reverb slot: the kGradFrames + 1 segments it needs (both
+// channels) in LDS, thread k - 1 forms D_s[k] of all of them for one bin k = 1..192 (the twiddle
+// stepped by multiplication, restarted exactly every 64 samples; the DC bin is a plain sum), then
+// the frames' gradients, summed into (sum_m G, sum_m m G) per bin in frame order. Per-block
+// partials: part[slot][block][x][k] = (a, d).
+constexpr int kGradFrames = 8;
+constexpr int kGradSegs = kGradFrames + 1;
+
+__global__ __launch_bounds__(kHop) void rv_mask_grad_kernel(const float* P, const double2* Un,
+                                                            const float* hbar, int64_t L, int M,
+                                                            double2* part) {
+  __shared__ double2 seg[kGradSegs][kHop];  // (mid, side) per sample
+  __shared__ double dc[kGradSegs][2];
+  const int blk = blockIdx.x, slot = blockIdx.y, nblk = gridDim.x;
+  const int m0 = blk * kGradFrames;
   const float* hb = hbar + (int64_t)slot * 2 * L;
-  for (int q = threadIdx.x; q < kF; q += kBlock) {
-    const int64_t n = (int64_t)kHop * m - kHop + q;
-    double v = 0.0;
-    if (n >= 0 && n < L) v = 0.5 * ((double)hb[n] + (x == 0 ? 1.0 : -1.0) * (double)hb[L + n]);
-    fb[q] = v;
+  for (int i = threadIdx.x; i < kGradSegs * kHop; i += kHop) {
+    const int j = i / kHop, t = i % kHop;
+    const int64_t n = (int64_t)kHop * (m0 - 1 + j) + t;  // segment s = m0 - 1 + j
+    double2 v = make_double2(0.0, 0.0);
+    if (n >= 0 && n < L) {
+      const double l = hb[n], r = hb[L + n];
+      v = make_double2(0.5 * (l + r), 0.5 * (l - r));
+    }
+    seg[j][t] = v;
   }
   __syncthreads();
-  const float* p = P + (int64_t)slot * kRvParams;
-  for (int k = threadIdx.x; k < kK; k += kBlock) {
-    double re = 0.0, im = 0.0;
-    for (int q = 0; q < kF; ++q) {
-      const double2 w = tw[(k * q) % kF];
-      re = fma(fb[q], w.x, re);
-      im = fma(fb[q], w.y, im);
+  if (threadIdx.x < 2 * kGradSegs) {  // the DC bin: plain sums
+    const int j = threadIdx.x >> 1, x = threadIdx.x & 1;
+    double a = 0.0;
+    for (int t = 0; t < kHop; ++t) a += x ? seg[j][t].y : seg[j][t].x;
+    dc[j][x] = a;
+  }
+  const int k = threadIdx.x + 1;  // 1..192
+  double dr[kGradSegs][2], di[kGradSegs][2];
+#pragma unroll
+  for (int j = 0; j < kGradSegs; ++j) dr[j][0] = dr[j][1] = di[j][0] = di[j][1] = 0.0;
+  double sr, si;
+  sincospi(2.0 * k / kF, &si, &sr);
+  for (int t0 = 0; t0 < kHop; t0 += 64) {
+    double wr, wi;
+    sincospi(2.0 * (double)((k * t0) % kF) / kF, &wi, &wr);
+    for (int t = t0; t < t0 + 64; ++t) {
+#pragma unroll
+      for (int j = 0; j < kGradSegs; ++j) {
+        const double2 v = seg[j][t];
+        dr[j][0] = fma(v.x, wr, dr[j][0]);
+        di[j][0] = fma(v.x, wi, di[j][0]);
+        dr[j][1] = fma(v.y, wr, dr[j][1]);
+        di[j][1] = fma(v.y, wi, di[j][1]);
+      }
+      const double tt = wr * sr - wi * si;
+      wi = fma(wr, si, wi * sr);
+      wr = tt;
     }
-    const double2 u = Un[((int64_t)x * M + m) * kK + k];
-    const double c = (k == 0 || k == kK - 1) ? 1.0 : 2.0;
-    part[(((int64_t)slot * 2 + x) * M + m) * kK + k] =
-        c / kF * (u.x * re - u.y * im) * mask_at(p, x, k, m);
+  }
+  __syncthreads();  // dc ready
+  const float* p = P + (int64_t)slot * kRvParams;
+  double2* out = part + ((int64_t)slot * nblk + blk) * 2 * kK;
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    double a = 0.0, d = 0.0, a0 = 0.0, d0 = 0.0;
+    const double sg = (k & 1) ? -1.0 : 1.0;
+    const double ck = (k == kK - 1) ? 1.0 / kF : 2.0 / kF;
+#pragma unroll
+    for (int f = 0; f < kGradFrames; ++f) {
+      const int m = m0 + f;
+      if (m >= M) break;
+      const double vr = dr[f][x] + sg * dr[f + 1][x], vi = di[f][x] + sg * di[f + 1][x];
+      const double2 u = Un[((int64_t)x * M + m) * kK + k];
+      const double g = ck * (u.x * vr - u.y * vi) * mask_at(p, x, k, m);
+      a += g;
+      d = fma((double)m, g, d);
+      if (threadIdx.x == 0) {  // the DC bin
+        const double2 u0 = Un[((int64_t)x * M + m) * kK];
+        const double g0 = (1.0 / kF) * (u0.x * (dc[f][x] + dc[f + 1][x])) * mask_at(p, x, 0, m);
+        a0 += g0;
+        d0 = fma((double)m, g0, d0);
+      }
+    }
+    out[x * kK + k] = make_double2(a, d);
+    if (threadIdx.x == 0) out[x * kK] = make_double2(a0, d0);
   }
 }
 
-// dH0[k] = sum_m G[m][k], dHD[k] = sum_m m G[m][k], in frame order (bin 191 adds the Nyquist
-// bin, which shares its mask).
-__global__ __launch_bounds__(kBlock) void rv_param_grad_kernel(const double* part, int M,
+// dH0[k] = sum_m G[m][k], dHD[k] = sum_m m G[m][k]: the blocks' partials in block order (bin 191
+// adds the Nyquist bin, which shares its mask).
+__global__ __launch_bounds__(kBlock) void rv_param_grad_kernel(const double2* part, int nblk,
                                                                float* dP) {
   const int slot = blockIdx.x, x = blockIdx.y, k = threadIdx.x;
   if (k >= kRvBins) return;
-  const double* ps = part + ((int64_t)slot * 2 + x) * M * kK;
   double a = 0.0, d = 0.0;
-  for (int m = 0; m < M; ++m) {
-    double gm = ps[(int64_t)m * kK + k];
-    if (k == kRvBins - 1) gm += ps[(int64_t)m * kK + kK - 1];
-    a += gm;
-    d = fma((double)m, gm, d);
+  for (int b = 0; b < nblk; ++b) {
+    const double2* pb = part + (((int64_t)slot * nblk + b) * 2 + x) * kK;
+    double2 v = pb[k];
+    if (k == kRvBins - 1) {
+      const double2 w = pb[kK - 1];
+      v.x += w.x;
+      v.y += w.y;
+    }
+    a += v.x;
+    d += v.y;
   }
   float* out = dP + (int64_t)slot * kRvParams + x * 2 * kRvBins;
   out[k] = (float)a;
@@ -393,13 +487,14 @@ __global__ __launch_bounds__(kBlock) void rv_param_grad_kernel(const double* par
 int rv_frames(int64_t L) { return (int)((L + kHop - 1) / kHop) + 1; }
 int rv_parts(int64_t L) { return (int)((L + kB - 1) / kB); }
 int rv_blocks(int64_t T) { return (int)((T + kB - 1) / kB); }
+int rv_grad_blocks(int64_t L) { return (rv_frames(L) + kGradFrames - 1) / kGradFrames; }
 
 hipError_t launch_rv_design(const float* P, int n, const float* noise, int64_t L, double2* Un,
                             float* h, float4* Hs, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int M = rv_frames(L), parts = rv_parts(L);
   rv_noise_stft_kernel<<<dim3(M, 2), kBlock, 0, s>>>(noise, L, M, Un);
-  rv_ir_kernel<<<dim3(M - 1, n), kHop, 0, s>>>(P, Un, L, M, h);
+  rv_ir_kernel<<<dim3((M - 1 + kIrHops - 1) / kIrHops, n), kIrThreads, 0, s>>>(P, Un, L, M, h);
   rv_partition_kernel<<<dim3(parts, n), kBlock, 0, s>>>(h, L, parts, Hs);
   return hipGetLastError();
 }
@@ -447,8 +542,11 @@ hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const dou
   const int nb = rv_blocks(T), parts = rv_parts(L), M = rv_frames(L);
   const hipError_t e = launch_xcorr(n, nb, parts, L, Y0, Z, Gs, hbar, s);
   if (e != hipSuccess) return e;
-  rv_frame_grad_kernel<<<dim3(M, 2, n), kBlock, 0, s>>>(P, Un, hbar, L, M, part);
-  rv_param_grad_kernel<<<dim3(n, 2), kBlock, 0, s>>>(part, M, dP);
+  const int nblk = rv_grad_blocks(L);
+  rv_mask_grad_kernel<<<dim3(nblk, n), kHop, 0, s>>>(P, Un, hbar, L, M,
+                                                     reinterpret_cast<double2*>(part));
+  rv_param_grad_kernel<<<dim3(n, 2), kBlock, 0, s>>>(reinterpret_cast<const double2*>(part),
+                                                     nblk, dP);
   return hipGetLastError();
 }
 

@@ -138,6 +138,7 @@ constexpr int kRvStride = 2064;            // float4 entries per stored spectrum
 int rv_frames(int64_t L);  // STFT frames of an L-sample noise
 int rv_parts(int64_t L);   // FIR partitions of an L-tap response
 int rv_blocks(int64_t T);  // output blocks of a T-sample row
+int rv_grad_blocks(int64_t L);  // blocks of the mask-gradient pass (frames in groups of 8)
 // noise: float [2][L] (mid, side); Un: double2 [2][frames][193] (noise STFT); h: float
 // [n][2][L] (left, right FIR); Hs: float4 [n][parts][kRvStride] (per-channel one-sided partition
 // spectra (left re, left im, right re, right im), scaled by 1 / 4096)
@@ -164,7 +165,8 @@ hipError_t launch_xcorr_spectra(const GraphView& g, int node_begin, int n_nodes,
 hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const float4* Y0, const float4* X,
                         float4* Gs, float* R, hipStream_t s);
 // After the last adjoint step, every reverb slot: Gs: float4 [n][parts][kRvStride] partition
-// cross-spectra; hbar: float [n][2][L]; part: double [n][2][frames][193]; dP: float [n][768]
+// cross-spectra; hbar: float [n][2][L]; part: double [n][grad blocks][2][193][2]; dP: float
+// [n][768]
 hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const double2* Un,
                           const float4* Z, const float4* Y0, float4* Gs, float* hbar,
                           double* part, float* dP, hipStream_t s);
