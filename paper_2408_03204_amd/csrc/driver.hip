@@ -25,7 +25,7 @@ namespace {
 struct WsLayout {
   size_t eq_h, eq_H, comp_agg, comp_carry, comp_tickets, delay_taps[2], delay_offs[2];
   size_t ar_slots, ar_carry, ar_pat, ar_tickets;
-  size_t rv_Un, rv_h, rv_H, rv_Z;
+  size_t rv_Un, rv_h, rv_H, rv_Z, rv_C;
   size_t fwd_end;
   size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part[2];
   size_t ar_ragg, ar_part;
@@ -89,6 +89,8 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
   L.rv_h = take(n_rv * 2 * rv_L * sizeof(float));
   L.rv_H = take(n_rv * rv_P * kRvStride * sizeof(float4));
   L.rv_Z = take(n_rv * rv_nb * kRvStride * sizeof(float4));
+  L.rv_C = take(n_rv * (n_rv ? (size_t)rv_conv_tiles(h->rv_len) : 0) * rv_nb * kRvStride *
+                sizeof(float4));
   L.fwd_end = off;
   if (with_bwd) {
     const size_t tiles = pointwise_tiles(T);
@@ -274,7 +276,7 @@ hipError_t enqueue_fwd_step(const grafx_schedule_t* h, const GraphView& g, const
     }
     case GRAFX_REVERB:
       return launch_rv_fwd(g, U, b, cnt, h->rv_len, at<float4>(ws, L.rv_H), at<float4>(ws, L.rv_Z),
-                           stream);
+                           at<float4>(ws, L.rv_C), stream);
     default:
       return hipErrorInvalidValue;
   }
@@ -327,7 +329,7 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
                                 error_word(ws, L), stream);
     case GRAFX_REVERB:
       return launch_rv_bwd(g, dU, b, cnt, h->rv_len, at<float4>(ws, L.rv_H),
-                           at<float4>(ws, L.rv_Y0), stream);
+                           at<float4>(ws, L.rv_Y0), at<float4>(ws, L.rv_C), stream);
     default:
       return hipErrorInvalidValue;
   }

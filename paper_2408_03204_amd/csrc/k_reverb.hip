@@ -251,14 +251,89 @@ __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int nod
   store_separated(v, lds, out + ((int64_t)slot * nb + b) * kRvStride, 1.0f);
 }
 
-// ---- partitioned product and inverse ------------------------------------------------------------
-// Forward (CORR false): output block b = second half of IFFT(sum_{p <= b} X[b - p] H[p]).
-// Adjoint (CORR true): input-adjoint block b = first half of IFFT(sum_p Yf[b + p] conj(H[p])) with
-// Yf[c] = Y0[c + 1] + (-1)^k Y0[c] (zero past the last block).
+// ---- partitioned product, bin-major -------------------------------------------------------------
+// For one one-sided bin k the partitioned product is a short convolution along the block index:
+// forward C[b] = sum_p X[b - p] H[p], adjoint C[b] = sum_p Yf[b + p] conj(H[p]) with
+// Yf[c] = Y0[c + 1] + (-1)^k Y0[c] (per channel, complex). A thread owns one bin of one node and
+// one tile of kConvTile partitions: the tile's partition spectra stay in registers, and the blocks
+// enter a register ring one per step (the loop is unrolled by the tile size, so the ring is
+// indexed statically), so every stored spectrum is read once per tile instead of once per
+// (block, partition) pair. Each tile writes its partial C to the workspace; the inverse kernel
+// adds the tiles in order. One wave per block (bins 0..2048 in 33 waves).
+constexpr int kConvTile = 22;
+constexpr int kBinWave = 64;
+constexpr int kBinWaves = (kN / 2 + kBinWave) / kBinWave;  // 33
+
+__device__ __forceinline__ float4 cmac2(float4 acc, float4 a, float4 b) {
+  // per channel (x, y) and (z, w): acc += a * b (complex)
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+  acc.z = fma(a.z, b.z, fma(-a.w, b.w, acc.z));
+  acc.w = fma(a.z, b.w, fma(a.w, b.z, acc.w));
+  return acc;
+}
+
 template <bool CORR>
-__global__ __launch_bounds__(kBlock) void rv_product_kernel(GraphView g, float* out, int node_begin,
-                                                            int nb, int parts, const float4* S,
-                                                            const float4* Hs) {
+__global__ __launch_bounds__(kBinWave) void rv_conv_bins_kernel(GraphView g, int node_begin,
+                                                                int nb, int parts, int tiles,
+                                                                const float4* S, const float4* Hs,
+                                                                float4* C) {
+  const int k = blockIdx.x * kBinWave + threadIdx.x;
+  const int tile = blockIdx.y, node = node_begin + blockIdx.z;
+  if (k > kN / 2) return;  // no barriers in this kernel
+  const int slot = g.param_row[node];
+  const int p0 = tile * kConvTile;
+  const float4* Sk = S + (int64_t)slot * nb * kRvStride + k;
+  const float4* Hk = Hs + ((int64_t)slot * parts + p0) * kRvStride + k;
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 h[kConvTile], ring[kConvTile];
+#pragma unroll
+  for (int i = 0; i < kConvTile; ++i) {
+    // loads from clamped, valid addresses and a select on the value (a select between a global
+    // address and a local zero would turn every load into a flat access)
+    float4 v = Hk[(int64_t)max(min(i, parts - 1 - p0), 0) * kRvStride];
+    if (CORR) v = make_float4(v.x, -v.y, v.z, -v.w);
+    h[i] = p0 + i < parts ? v : zero;
+    ring[i] = zero;
+  }
+  const float sg = (k & 1) ? -1.f : 1.f;
+  float4 y_next = zero;  // adjoint: Y0[c + 1] of the entry c being formed
+  float4* Ck = C + ((int64_t)slot * tiles + tile) * nb * kRvStride + k;
+  for (int q0 = 0; q0 < nb; q0 += kConvTile) {
+#pragma unroll
+    for (int j = 0; j < kConvTile; ++j) {
+      const int q = q0 + j;
+      if (q < nb) {  // uniform over the wave
+      // step q: the entry of partition p0 enters ring[j]; partition p0 + i reads the entry that
+      // entered i steps earlier, ring[(j - i) mod kConvTile]
+      const int b = CORR ? nb - 1 - q : q;
+      const int c = CORR ? b + p0 : b - p0;
+      float4 e;
+      if (CORR) {
+        const float4 yv = Sk[(int64_t)min(c, nb - 1) * kRvStride];
+        const float4 y = c < nb ? yv : zero;
+        e = make_float4(y_next.x + sg * y.x, y_next.y + sg * y.y, y_next.z + sg * y.z,
+                        y_next.w + sg * y.w);
+        y_next = y;
+      } else {
+        const float4 xv = Sk[(int64_t)max(c, 0) * kRvStride];
+        e = c >= 0 ? xv : zero;
+      }
+      ring[j] = e;
+      float4 acc = zero;
+#pragma unroll
+      for (int i = 0; i < kConvTile; ++i) acc = cmac2(acc, ring[(j - i + kConvTile) % kConvTile], h[i]);
+      Ck[(int64_t)b * kRvStride] = acc;
+      }
+    }
+  }
+}
+
+// Output block b: the tiles' partial spectra added in tile order, the packed spectrum rebuilt
+// through LDS, one inverse transform; forward keeps its second half, adjoint its first.
+template <bool CORR>
+__global__ __launch_bounds__(kBlock) void rv_inverse_kernel(GraphView g, float* out, int node_begin,
+                                                            int nb, int tiles, const float4* C) {
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
   const int b = blockIdx.x, node = node_begin + blockIdx.y;
@@ -268,35 +343,19 @@ __global__ __launch_bounds__(kBlock) void rv_product_kernel(GraphView g, float* 
   if ((int64_t)kB * b >= Tn) return;  // block past the node's length (uniform over the block)
   Twiddles tw;
   load_twiddles(tw, w1lds);
-  const float4* Ss = S + (int64_t)slot * nb * kRvStride;
-  const float4* Hn = Hs + (int64_t)slot * parts * kRvStride;
-  const float sgn = (j & 1) ? -1.f : 1.f;  // (-1)^k for every bin k = j + 256 r of this thread
+  const float4* Cb = C + ((int64_t)slot * tiles * nb + b) * kRvStride;
   float2 al[kHalfBins], ar[kHalfBins];
 #pragma unroll
-  for (int r = 0; r < kHalfBins; ++r) al[r] = ar[r] = make_float2(0.f, 0.f);
-  const int np = CORR ? min(parts, nb - b) : min(parts, b + 1);
-  for (int p = 0; p < np; ++p) {
-    const float4* hp = Hn + (int64_t)p * kRvStride;
-    const float4* z0 = Ss + (int64_t)(CORR ? b + p : b - p) * kRvStride;
-    const bool has_next = CORR && b + p + 1 < nb;
-#pragma unroll
-    for (int r = 0; r < kHalfBins; ++r) {
-      const int k = j + 256 * r;
-      if (k > kN / 2) break;
-      float4 z = z0[k];
-      if (CORR) {
-        z = make_float4(sgn * z.x, sgn * z.y, sgn * z.z, sgn * z.w);
-        if (has_next) {
-          const float4 z1 = z0[kRvStride + k];
-          z = make_float4(z.x + z1.x, z.y + z1.y, z.z + z1.z, z.w + z1.w);
-        }
+  for (int r = 0; r < kHalfBins; ++r) {
+    const int k = j + 256 * r;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k <= kN / 2)
+      for (int t = 0; t < tiles; ++t) {
+        const float4 v = Cb[(int64_t)t * nb * kRvStride + k];
+        acc = make_float4(acc.x + v.x, acc.y + v.y, acc.z + v.z, acc.w + v.w);
       }
-      const float4 hh = hp[k];
-      const float2 hl = CORR ? make_float2(hh.x, -hh.y) : make_float2(hh.x, hh.y);
-      const float2 hr = CORR ? make_float2(hh.z, -hh.w) : make_float2(hh.z, hh.w);
-      al[r] = cadd(al[r], cmul(make_float2(z.x, z.y), hl));
-      ar[r] = cadd(ar[r], cmul(make_float2(z.z, z.w), hr));
-    }
+    al[r] = make_float2(acc.x, acc.y);
+    ar[r] = make_float2(acc.z, acc.w);
   }
   float2 v[16];
   pack_spectrum(al, ar, lds, v);
@@ -313,27 +372,54 @@ __global__ __launch_bounds__(kBlock) void rv_product_kernel(GraphView g, float* 
   }
 }
 
-// ---- FIR gradient (the partitioned cross-correlation) ---------------------------------------------
+// ---- FIR gradient (the partitioned cross-correlation), bin-major ---------------------------------
 // Cross-spectrum of partition p per channel, one-sided bins: G_c[k] = sum_{b >= p} Y0_c[b][k]
-// conj(X_c[b - p][k]), summed in block order in double, scaled by 1 / 4096.
-__global__ __launch_bounds__(kBlock) void rv_cross_kernel(int nb, int parts, const float4* Y0,
-                                                          const float4* X, float4* Gs) {
-  const int p = blockIdx.x, k = blockIdx.y * kBlock + threadIdx.x;
-  const int slot = blockIdx.z;
+// conj(X_c[b - p][k]), summed in block order in double, scaled by 1 / 4096. A thread owns one bin
+// of one slot and kCrossTile partitions: the input spectra enter a register ring one block per
+// step (as in the product), the block's Y0 is read once for the whole tile.
+constexpr int kCrossTile = 11;
+
+__global__ __launch_bounds__(kBinWave) void rv_cross_kernel(int nb, int parts, const float4* Y0,
+                                                            const float4* X, float4* Gs) {
+  const int k = blockIdx.x * kBinWave + threadIdx.x;
+  const int p0 = blockIdx.y * kCrossTile, slot = blockIdx.z;
   if (k > kN / 2) return;
   const float4* ys = Y0 + (int64_t)slot * nb * kRvStride + k;
   const float4* xs = X + (int64_t)slot * nb * kRvStride + k;
-  double lre = 0.0, lim = 0.0, rre = 0.0, rim = 0.0;
-  for (int b = p; b < nb; ++b) {
-    const float4 y = ys[(int64_t)b * kRvStride], x = xs[(int64_t)(b - p) * kRvStride];
-    lre += (double)y.x * x.x + (double)y.y * x.y;
-    lim += (double)y.y * x.x - (double)y.x * x.y;
-    rre += (double)y.z * x.z + (double)y.w * x.w;
-    rim += (double)y.w * x.z - (double)y.z * x.w;
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 ring[kCrossTile];
+  double acc[kCrossTile][4];
+#pragma unroll
+  for (int i = 0; i < kCrossTile; ++i) {
+    ring[i] = zero;
+    acc[i][0] = acc[i][1] = acc[i][2] = acc[i][3] = 0.0;
+  }
+  for (int b0 = 0; b0 < nb; b0 += kCrossTile) {
+#pragma unroll
+    for (int j = 0; j < kCrossTile; ++j) {
+      const int b = b0 + j;
+      if (b < nb) {  // uniform
+      const float4 xv = xs[(int64_t)max(b - p0, 0) * kRvStride];
+      ring[j] = b - p0 >= 0 ? xv : zero;  // X[b - p0]
+      const float4 y = ys[(int64_t)b * kRvStride];
+#pragma unroll
+      for (int i = 0; i < kCrossTile; ++i) {  // partition p0 + i: X[b - p0 - i]
+        const float4 x = ring[(j - i + kCrossTile) % kCrossTile];
+        acc[i][0] += (double)y.x * x.x + (double)y.y * x.y;
+        acc[i][1] += (double)y.y * x.x - (double)y.x * x.y;
+        acc[i][2] += (double)y.z * x.z + (double)y.w * x.w;
+        acc[i][3] += (double)y.w * x.z - (double)y.z * x.w;
+      }
+      }
+    }
   }
   constexpr double s = 1.0 / kN;
-  Gs[((int64_t)slot * parts + p) * kRvStride + k] =
-      make_float4((float)(s * lre), (float)(s * lim), (float)(s * rre), (float)(s * rim));
+#pragma unroll
+  for (int i = 0; i < kCrossTile; ++i)
+    if (p0 + i < parts)
+      Gs[((int64_t)slot * parts + p0 + i) * kRvStride + k] =
+          make_float4((float)(s * acc[i][0]), (float)(s * acc[i][1]), (float)(s * acc[i][2]),
+                      (float)(s * acc[i][3]));
 }
 
 // hbar_c[2048 p + i] = first half of the inverse transform of G (left: real part, right:
@@ -511,27 +597,31 @@ hipError_t launch_xcorr_spectra(const GraphView& g, int node_begin, int n_nodes,
 hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const float4* Y0, const float4* X,
                         float4* Gs, float* R, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  rv_cross_kernel<<<dim3(parts, (kN / 2 + kBlock) / kBlock, n), kBlock, 0, s>>>(nb, parts, Y0, X,
-                                                                                 Gs);
+  rv_cross_kernel<<<dim3(kBinWaves, (parts + kCrossTile - 1) / kCrossTile, n), kBinWave, 0, s>>>(
+      nb, parts, Y0, X, Gs);
   rv_hbar_kernel<<<dim3(parts, n), kBlock, 0, s>>>(Gs, parts, len, R);
   return hipGetLastError();
 }
 
+int rv_conv_tiles(int64_t L) { return (rv_parts(L) + kConvTile - 1) / kConvTile; }
+
 hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nodes, int64_t L,
-                         const float4* Hs, float4* Z, hipStream_t s) {
-  const int nb = rv_blocks(g.T), parts = rv_parts(L);
+                         const float4* Hs, float4* Z, float4* C, hipStream_t s) {
+  const int nb = rv_blocks(g.T), parts = rv_parts(L), tiles = rv_conv_tiles(L);
   rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Z);
-  rv_product_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, U, node_begin, nb, parts, Z,
-                                                                Hs);
+  rv_conv_bins_kernel<false><<<dim3(kBinWaves, tiles, n_nodes), kBinWave, 0, s>>>(
+      g, node_begin, nb, parts, tiles, Z, Hs, C);
+  rv_inverse_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, U, node_begin, nb, tiles, C);
   return hipGetLastError();
 }
 
 hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
-                         const float4* Hs, float4* Y0, hipStream_t s) {
-  const int nb = rv_blocks(g.T), parts = rv_parts(L);
+                         const float4* Hs, float4* Y0, float4* C, hipStream_t s) {
+  const int nb = rv_blocks(g.T), parts = rv_parts(L), tiles = rv_conv_tiles(L);
   rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Y0);
-  rv_product_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, dU, node_begin, nb, parts, Y0,
-                                                               Hs);
+  rv_conv_bins_kernel<true><<<dim3(kBinWaves, tiles, n_nodes), kBinWave, 0, s>>>(
+      g, node_begin, nb, parts, tiles, Y0, Hs, C);
+  rv_inverse_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, dU, node_begin, nb, tiles, C);
   return hipGetLastError();
 }
 

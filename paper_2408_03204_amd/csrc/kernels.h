@@ -145,13 +145,15 @@ int rv_grad_blocks(int64_t L);  // blocks of the mask-gradient pass (frames in g
 hipError_t launch_rv_design(const float* P, int n, const float* noise, int64_t L, double2* Un,
                             float* h, float4* Hs, hipStream_t s);
 // Z: float4 [n][blocks][kRvStride] per-channel one-sided spectra of the input windows (kept for
-// the adjoint)
+// the adjoint); C: float4 [n][rv_conv_tiles(L)][blocks][kRvStride] partial product spectra
+// (scratch, shared by the forward and the adjoint)
+int rv_conv_tiles(int64_t L);
 hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nodes, int64_t L,
-                         const float4* Hs, float4* Z, hipStream_t s);
+                         const float4* Hs, float4* Z, float4* C, hipStream_t s);
 // Y0: float4 [n][blocks][kRvStride] spectra of the output-adjoint blocks (kept for the FIR
 // gradient)
 hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
-                         const float4* Hs, float4* Y0, hipStream_t s);
+                         const float4* Hs, float4* Y0, float4* C, hipStream_t s);
 // Partitioned cross-correlation R_c[n] = sum_t ybar_c[t + s_a] u_c[t + s_i - n], n in [0, len),
 // of a node's output adjoint and its input sum (the reverb's FIR gradient; the delay's surrogate
 // gradient), over nb blocks of 2048 (nb x 2048 must cover every t with a non-zero term). Spectra
