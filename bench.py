@@ -48,10 +48,13 @@ WORKLOADS = {"console": "mixing_console", "tiny": "tiny_console", "large": "larg
 TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "delay", "tanh",
               "noisegate", "compressor_ar", "reverb", "delay_long")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
-KERNEL_SRC = {"mix": "k_pointwise.hip", "out": "k_pointwise.hip", "gain_pan": "k_pointwise.hip",
-              "imager": "k_pointwise.hip", "tanh": "k_pointwise.hip", "eq": "k_eq.hip",
-              "compressor": "k_comp.hip", "noisegate": "k_comp.hip", "compressor_ar": "k_comp_ar.hip",
-              "delay": "k_delay.hip", "reverb": "k_reverb.hip", "delay_long": "k_delay.hip"}
+# (the kernel file, then the local headers whose code it compiles in, hashed in this order)
+KERNEL_SRC = {"mix": ("k_pointwise.hip",), "out": ("k_pointwise.hip",),
+              "gain_pan": ("k_pointwise.hip",), "imager": ("k_pointwise.hip",),
+              "tanh": ("k_pointwise.hip",), "eq": ("k_eq.hip", "fft4096.h"),
+              "compressor": ("k_comp.hip", "dynamics.h"), "noisegate": ("k_comp.hip", "dynamics.h"),
+              "compressor_ar": ("k_comp_ar.hip", "dynamics.h"), "delay": ("k_delay.hip",),
+              "reverb": ("k_reverb.hip", "fft4096.h"), "delay_long": ("k_delay.hip",)}
 
 
 def parse():
@@ -165,8 +168,8 @@ def stored_traffic(kernel_type: str, direction: str, workload: str):
         return None
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2408_03204_amd", "csrc",
-                                KERNEL_SRC[kernel_type]), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, "paper_2408_03204_amd", "csrc", f), "rb").read()
+                       for f in KERNEL_SRC[kernel_type])
         key = f"{direction}:{kernel_type}:{workload}"
         ent = rec.get(key)
         if ent and ent.get("src_sha256") == hashlib.sha256(src).hexdigest():

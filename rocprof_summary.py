@@ -15,7 +15,8 @@ HBM traffic per kernel from two PMC runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_
 program that first copies `copy_mib` MiB device-to-device: each counter is scaled by
 (true bytes of that copy) / (what the counter reads for it). Also writes the traffic of one
 step-kernel type to a JSON file keyed "<dir>:<type>:<workload>", with the SHA-256 of the kernel's
-source so the figure is only used while that source is unchanged:
+source (a comma-separated list: the kernel file and the headers it includes, hashed in that
+order) so the figure is only used while that source is unchanged:
 
     python rocprof_summary.py pmc <fetch.db> <write.db> <copy_mib> \\
         <steps> <kernel substring> <key> <source file> <json out> <command...>
@@ -118,7 +119,8 @@ def pmc(fetch_db: str, write_db: str, copy_mib: float, steps: int, kernel: str, 
     rec[key] = {"kernel": name, "launches_per_step": n / steps,
                 "fetch_bytes_per_launch": fe * 1024 / n, "write_bytes_per_launch": wr * 1024 / n,
                 "bytes_per_launch": (fe + wr) * 1024 / n,
-                "src_sha256": hashlib.sha256(open(source, "rb").read()).hexdigest(),
+                "src_sha256": hashlib.sha256(b"".join(
+                    open(f, "rb").read() for f in source.split(","))).hexdigest(),
                 "command": cmd}
     with open(json_out, "w") as fh:
         json.dump(rec, fh, indent=1, sort_keys=True)

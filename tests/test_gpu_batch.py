@@ -16,9 +16,11 @@ from paper_2408_03204_amd import RenderBuffers, Schedule, merge_graphs, merge_in
 pytestmark = pytest.mark.gpu
 
 
-def _alone(w, dY, dev):
+def _alone(w, dY, dev, noise=None):
     g = w.graph
     sched = Schedule(g.node_type, g.edges, "beam")
+    if noise is not None:
+        sched.set_reverb_noise(torch.as_tensor(noise, device=dev))
     S = torch.as_tensor(w.sources, device=dev)
     P = {t: torch.as_tensor(p, device=dev) for t, p in w.params.items() if p.shape[0] > 0}
     rb = RenderBuffers(sched, w.T, dev, with_backward=True)
@@ -30,13 +32,15 @@ def _alone(w, dY, dev):
     return (rb.Y.cpu().numpy(), {t: d.cpu().numpy() for t, d in dP.items()}, dS.cpu().numpy())
 
 
-def _check_merged(ws, tag):
+def _check_merged(ws, tag, noise=None):
     dev = torch.device("cuda")
     m = merge_graphs([(w.graph.node_type, w.graph.edges, w.T) for w in ws])
     say(f"[batch {tag}] {len(ws)} graphs, lengths {[w.T for w in ws]}, {len(m['node_type'])} "
         f"nodes, stride {m['T']}")
     S, P = merge_inputs(m, [w.sources for w in ws], [w.params for w in ws])
     sched = Schedule(m["node_type"], m["edges"], "beam", lengths=m["lengths"])
+    if noise is not None:
+        sched.set_reverb_noise(torch.as_tensor(noise, device=dev))
     Sd = torch.as_tensor(S, device=dev)
     Pd = {t: torch.as_tensor(p, device=dev) for t, p in P.items()}
     rng = np.random.default_rng(5)
@@ -57,7 +61,7 @@ def _check_merged(ws, tag):
     dP = {t: d.cpu().numpy() for t, d in dPd.items()}
     for i, w in enumerate(ws):
         g = w.graph
-        Ya, dPa, dSa = _alone(w, dY_each[i], dev)
+        Ya, dPa, dSa = _alone(w, dY_each[i], dev, noise)
         n_out, o0, k0 = g.count(synth.OUT), m["output_offset"][i], m["input_offset"][i]
         K = g.count(synth.IN)
         assert np.array_equal(Y[o0:o0 + n_out, :, :w.T], Ya), (tag, i, "Y")
@@ -65,7 +69,8 @@ def _check_merged(ws, tag):
         for t, d in dPa.items():
             r0 = int(m["param_offset"][i][t])
             assert np.array_equal(dP[t][r0:r0 + d.shape[0]], d), (tag, i, "dP", t)
-        Y64 = OR.render(g.node_type, g.edges, w.sources, OR.as_params64(w.params)).numpy()
+        Y64 = OR.render(g.node_type, g.edges, w.sources, OR.as_params64(w.params),
+                        reverb_noise=noise).numpy()
         e = rel_err(Ya.astype(np.float64), Y64)
         assert e <= RENDER_TOL, (tag, i, e)
     say("   merged == alone bit for bit (Y, dS, dP); alone vs oracle within tolerance")
@@ -80,3 +85,14 @@ def test_merged_random_graphs(lengths):
 def test_merged_batched_consoles():
     ws = synth.batched_graphs(6, 21, T_choices=(2 ** 12, 2 ** 13, 2 ** 14), src_range=(4, 12))
     _check_merged(ws, "consoles")
+
+
+def test_merged_graphs_with_reverbs_and_2s_delays():
+    """Reverbs (one noise for the whole batch) and 2 s delays in graphs of different lengths:
+    merged == alone bit for bit, alone within the render tolerance of the oracle."""
+    types = (synth.MIX, synth.GAIN_PAN, synth.REVERB, synth.DELAY_LONG, synth.EQ)
+    ws = [synth.random_workload(seed, 9, T, types=types, edge_p=0.35)
+          for seed, T in ((1402, 5 * 2048 + 300), (1411, 2048), (1413, 9001))]
+    assert all(w.graph.count(synth.REVERB) >= 1 and w.graph.count(synth.DELAY_LONG) >= 1
+               for w in ws)
+    _check_merged(ws, "reverb + 2 s delay", noise=synth.reverb_noise(14, 7000))
