@@ -42,3 +42,11 @@ def test_long_delay(T, surrogate):
     w = long_delay_graph(T, 91, 1e-4 if surrogate else 0.0)
     errs, _, _ = run(w, 9, surrogate=surrogate)
     check(errs)
+
+
+def test_long_delay_at_the_largest_length():
+    T = 2 ** 20
+    say(f"[delay 2 s, 2^20] T={T}")
+    w = long_delay_graph(T, 92, 1e-4)
+    errs, _, _ = run(w, 10, surrogate=True)
+    check(errs)

@@ -136,3 +136,12 @@ def test_reverb_requires_noise():
     P = {t: torch.as_tensor(p).cuda() for t, p in w.params.items() if p.shape[0] > 0}
     with pytest.raises(Exception, match="noise"):
         render(sched, S, P)
+
+
+def test_reverb_at_the_largest_length():
+    """One reverb at the large console's length, T = 2^20 (512 blocks, every partition of the
+    2 s response in play over the whole signal), forward and adjoint against the oracle."""
+    T = 2 ** 20
+    say(f"[reverb 2^20] T={T} L={synth.REVERB_LEN}")
+    w, noise = single_reverb(T, synth.REVERB_LEN, 65, n_in=1)
+    check(run(w, noise, 6))
