@@ -105,3 +105,44 @@ def test_graph_replay_with_dynamics_variants():
         _same(_snapshot(gs), eager)
         gs.run()
         _same(_snapshot(gs), eager)
+
+
+def test_graph_replay_with_reverbs_and_2s_delays():
+    """The reverb console with 2 s delays and the delay surrogate on: IR synthesis, partitioned
+    products, cross-spectra and phasor gradients replay bit for bit (no memset, no allocation in
+    the captured step), with eager steps between replays and after a parameter update."""
+    T = 2 ** 15 + 1234
+    w = synth.reverb_console(T=T)
+    g = w.graph
+    # every imager becomes a 2 s delay (same position in the graph, parameters drawn)
+    nt = np.where(g.node_type == synth.IMAGER, synth.DELAY_LONG, g.node_type).astype(np.int32)
+    g2 = synth.Graph(nt, g.edges)
+    params = synth.draw_params(synth.rng_for(78, 2), g2)
+    dev = torch.device("cuda")
+    sched = Schedule(g2.node_type, g2.edges, "beam")
+    sched.set_reverb_noise(torch.as_tensor(w.reverb_noise, device=dev))
+    sched.set_delay_surrogate(True)
+    S = torch.as_tensor(w.sources, device=dev)
+    P = {t: torch.as_tensor(p, device=dev) for t, p in params.items() if p.shape[0] > 0}
+    assert synth.REVERB in P and synth.DELAY_LONG in P
+    with torch.no_grad():
+        tgt = (0.5 * render(sched, S, P)).contiguous()
+    say(f"[graph reverb] {g2.num_nodes} nodes, reverbs {int((nt == synth.REVERB).sum())}, "
+        f"2 s delays {int((nt == synth.DELAY_LONG).sum())}")
+    gs = GradStep(sched, S, P, tgt)
+    gs.run()
+    eager = _snapshot(gs)
+    assert float(gs.grads[synth.DELAY_LONG].reshape(-1, 2, 20, 22)[..., :2].abs().max()) > 0
+    gs.capture()
+    for rep in range(3):
+        gs.replay()
+        _same(_snapshot(gs), eager)
+        gs.run()
+        _same(_snapshot(gs), eager)
+    with torch.no_grad():
+        for p in P.values():
+            p.mul_(0.999)
+    gs.run()
+    eager2 = _snapshot(gs)
+    gs.replay()
+    _same(_snapshot(gs), eager2)
