@@ -259,8 +259,11 @@ __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int nod
 // enter a register ring one per step (the loop is unrolled by the tile size, so the ring is
 // indexed statically), so every stored spectrum is read once per tile instead of once per
 // (block, partition) pair. Each tile writes its partial C to the workspace; the inverse kernel
-// adds the tiles in order. One wave per block (bins 0..2048 in 33 waves).
+// adds the tiles in order. One wave per block (bins 0..2048 in 33 waves). The block range is cut
+// into segments of kConvSeg steps, one wave each, so that a node's chain of dependent loads is
+// short; a segment first re-forms the kConvTile - 1 entries before it (its ring warm-up).
 constexpr int kConvTile = 22;
+constexpr int kConvSeg = 64;
 constexpr int kBinWave = 64;
 constexpr int kBinWaves = (kN / 2 + kBinWave) / kBinWave;  // 33
 
@@ -276,10 +279,10 @@ __device__ __forceinline__ float4 cmac2(float4 acc, float4 a, float4 b) {
 template <bool CORR>
 __global__ __launch_bounds__(kBinWave) void rv_conv_bins_kernel(GraphView g, int node_begin,
                                                                 int nb, int parts, int tiles,
-                                                                const float4* S, const float4* Hs,
-                                                                float4* C) {
+                                                                int nseg, const float4* S,
+                                                                const float4* Hs, float4* C) {
   const int k = blockIdx.x * kBinWave + threadIdx.x;
-  const int tile = blockIdx.y, node = node_begin + blockIdx.z;
+  const int tile = blockIdx.y / nseg, seg = blockIdx.y % nseg, node = node_begin + blockIdx.z;
   if (k > kN / 2) return;  // no barriers in this kernel
   const int slot = g.param_row[node];
   const int p0 = tile * kConvTile;
@@ -297,13 +300,22 @@ __global__ __launch_bounds__(kBinWave) void rv_conv_bins_kernel(GraphView g, int
     ring[i] = zero;
   }
   const float sg = (k & 1) ? -1.f : 1.f;
-  float4 y_next = zero;  // adjoint: Y0[c + 1] of the entry c being formed
   float4* Ck = C + ((int64_t)slot * tiles + tile) * nb * kRvStride + k;
-  for (int q0 = 0; q0 < nb; q0 += kConvTile) {
+  // steps [qs, qe) are stored; entries from q_start (a multiple of the tile, at least
+  // kConvTile - 1 steps before qs) are formed
+  const int qs = seg * kConvSeg, qe = min(nb, qs + kConvSeg);
+  const int q_start = max(0, qs - (kConvTile - 1)) / kConvTile * kConvTile;
+  float4 y_next = zero;  // adjoint: Y0[c + 1] of the entry c being formed
+  if (CORR) {
+    const int c1 = nb - q_start + p0;  // c + 1 of the first entry
+    const float4 yv = Sk[(int64_t)min(c1, nb - 1) * kRvStride];
+    y_next = c1 < nb ? yv : zero;
+  }
+  for (int q0 = q_start; q0 < qe; q0 += kConvTile) {
 #pragma unroll
     for (int j = 0; j < kConvTile; ++j) {
       const int q = q0 + j;
-      if (q < nb) {  // uniform over the wave
+      if (q < qe) {  // uniform over the wave
       // step q: the entry of partition p0 enters ring[j]; partition p0 + i reads the entry that
       // entered i steps earlier, ring[(j - i) mod kConvTile]
       const int b = CORR ? nb - 1 - q : q;
@@ -320,10 +332,13 @@ __global__ __launch_bounds__(kBinWave) void rv_conv_bins_kernel(GraphView g, int
         e = c >= 0 ? xv : zero;
       }
       ring[j] = e;
-      float4 acc = zero;
+      if (q >= qs) {
+        float4 acc = zero;
 #pragma unroll
-      for (int i = 0; i < kConvTile; ++i) acc = cmac2(acc, ring[(j - i + kConvTile) % kConvTile], h[i]);
-      Ck[(int64_t)b * kRvStride] = acc;
+        for (int i = 0; i < kConvTile; ++i)
+          acc = cmac2(acc, ring[(j - i + kConvTile) % kConvTile], h[i]);
+        Ck[(int64_t)b * kRvStride] = acc;
+      }
       }
     }
   }
@@ -609,8 +624,9 @@ hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nod
                          const float4* Hs, float4* Z, float4* C, hipStream_t s) {
   const int nb = rv_blocks(g.T), parts = rv_parts(L), tiles = rv_conv_tiles(L);
   rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Z);
-  rv_conv_bins_kernel<false><<<dim3(kBinWaves, tiles, n_nodes), kBinWave, 0, s>>>(
-      g, node_begin, nb, parts, tiles, Z, Hs, C);
+  const int nseg = (nb + kConvSeg - 1) / kConvSeg;
+  rv_conv_bins_kernel<false><<<dim3(kBinWaves, tiles * nseg, n_nodes), kBinWave, 0, s>>>(
+      g, node_begin, nb, parts, tiles, nseg, Z, Hs, C);
   rv_inverse_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, U, node_begin, nb, tiles, C);
   return hipGetLastError();
 }
@@ -619,8 +635,9 @@ hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_no
                          const float4* Hs, float4* Y0, float4* C, hipStream_t s) {
   const int nb = rv_blocks(g.T), parts = rv_parts(L), tiles = rv_conv_tiles(L);
   rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Y0);
-  rv_conv_bins_kernel<true><<<dim3(kBinWaves, tiles, n_nodes), kBinWave, 0, s>>>(
-      g, node_begin, nb, parts, tiles, Y0, Hs, C);
+  const int nseg = (nb + kConvSeg - 1) / kConvSeg;
+  rv_conv_bins_kernel<true><<<dim3(kBinWaves, tiles * nseg, n_nodes), kBinWave, 0, s>>>(
+      g, node_begin, nb, parts, tiles, nseg, Y0, Hs, C);
   rv_inverse_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, dU, node_begin, nb, tiles, C);
   return hipGetLastError();
 }
