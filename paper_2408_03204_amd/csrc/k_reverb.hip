@@ -389,9 +389,10 @@ __global__ __launch_bounds__(kBlock) void rv_inverse_kernel(GraphView g, float* 
 
 // ---- FIR gradient (the partitioned cross-correlation), bin-major ---------------------------------
 // Cross-spectrum of partition p per channel, one-sided bins: G_c[k] = sum_{b >= p} Y0_c[b][k]
-// conj(X_c[b - p][k]), summed in block order in double, scaled by 1 / 4096. A thread owns one bin
-// of one slot and kCrossTile partitions: the input spectra enter a register ring one block per
-// step (as in the product), the block's Y0 is read once for the whole tile.
+// conj(X_c[b - p][k]), scaled by 1 / 4096. A thread owns one bin of one slot and kCrossTile
+// partitions: the input spectra enter a register ring one block per step (as in the product),
+// the block's Y0 is read once for the whole tile. Each group of kCrossTile consecutive blocks is
+// summed in float (at most kCrossTile terms), the groups in double, in block order.
 constexpr int kCrossTile = 11;
 
 __global__ __launch_bounds__(kBinWave) void rv_cross_kernel(int nb, int parts, const float4* Y0,
@@ -410,6 +411,9 @@ __global__ __launch_bounds__(kBinWave) void rv_cross_kernel(int nb, int parts, c
     acc[i][0] = acc[i][1] = acc[i][2] = acc[i][3] = 0.0;
   }
   for (int b0 = 0; b0 < nb; b0 += kCrossTile) {
+    float4 part[kCrossTile];
+#pragma unroll
+    for (int i = 0; i < kCrossTile; ++i) part[i] = zero;
 #pragma unroll
     for (int j = 0; j < kCrossTile; ++j) {
       const int b = b0 + j;
@@ -420,12 +424,19 @@ __global__ __launch_bounds__(kBinWave) void rv_cross_kernel(int nb, int parts, c
 #pragma unroll
       for (int i = 0; i < kCrossTile; ++i) {  // partition p0 + i: X[b - p0 - i]
         const float4 x = ring[(j - i + kCrossTile) % kCrossTile];
-        acc[i][0] += (double)y.x * x.x + (double)y.y * x.y;
-        acc[i][1] += (double)y.y * x.x - (double)y.x * x.y;
-        acc[i][2] += (double)y.z * x.z + (double)y.w * x.w;
-        acc[i][3] += (double)y.w * x.z - (double)y.z * x.w;
+        part[i].x = fma(y.x, x.x, fma(y.y, x.y, part[i].x));
+        part[i].y = fma(y.y, x.x, fma(-y.x, x.y, part[i].y));
+        part[i].z = fma(y.z, x.z, fma(y.w, x.w, part[i].z));
+        part[i].w = fma(y.w, x.z, fma(-y.z, x.w, part[i].w));
       }
       }
+    }
+#pragma unroll
+    for (int i = 0; i < kCrossTile; ++i) {
+      acc[i][0] += part[i].x;
+      acc[i][1] += part[i].y;
+      acc[i][2] += part[i].z;
+      acc[i][3] += part[i].w;
     }
   }
   constexpr double s = 1.0 / kN;

@@ -16,9 +16,10 @@ from paper_2408_03204_amd import RenderBuffers, Schedule, merge_graphs, merge_in
 pytestmark = pytest.mark.gpu
 
 
-def _alone(w, dY, dev, noise=None):
+def _alone(w, dY, dev, noise=None, surrogate=False):
     g = w.graph
     sched = Schedule(g.node_type, g.edges, "beam")
+    sched.set_delay_surrogate(surrogate)
     if noise is not None:
         sched.set_reverb_noise(torch.as_tensor(noise, device=dev))
     S = torch.as_tensor(w.sources, device=dev)
@@ -32,13 +33,14 @@ def _alone(w, dY, dev, noise=None):
     return (rb.Y.cpu().numpy(), {t: d.cpu().numpy() for t, d in dP.items()}, dS.cpu().numpy())
 
 
-def _check_merged(ws, tag, noise=None):
+def _check_merged(ws, tag, noise=None, surrogate=False):
     dev = torch.device("cuda")
     m = merge_graphs([(w.graph.node_type, w.graph.edges, w.T) for w in ws])
     say(f"[batch {tag}] {len(ws)} graphs, lengths {[w.T for w in ws]}, {len(m['node_type'])} "
         f"nodes, stride {m['T']}")
     S, P = merge_inputs(m, [w.sources for w in ws], [w.params for w in ws])
     sched = Schedule(m["node_type"], m["edges"], "beam", lengths=m["lengths"])
+    sched.set_delay_surrogate(surrogate)
     if noise is not None:
         sched.set_reverb_noise(torch.as_tensor(noise, device=dev))
     Sd = torch.as_tensor(S, device=dev)
@@ -61,7 +63,7 @@ def _check_merged(ws, tag, noise=None):
     dP = {t: d.cpu().numpy() for t, d in dPd.items()}
     for i, w in enumerate(ws):
         g = w.graph
-        Ya, dPa, dSa = _alone(w, dY_each[i], dev, noise)
+        Ya, dPa, dSa = _alone(w, dY_each[i], dev, noise, surrogate)
         n_out, o0, k0 = g.count(synth.OUT), m["output_offset"][i], m["input_offset"][i]
         K = g.count(synth.IN)
         assert np.array_equal(Y[o0:o0 + n_out, :, :w.T], Ya), (tag, i, "Y")
@@ -88,11 +90,12 @@ def test_merged_batched_consoles():
 
 
 def test_merged_graphs_with_reverbs_and_2s_delays():
-    """Reverbs (one noise for the whole batch) and 2 s delays in graphs of different lengths:
-    merged == alone bit for bit, alone within the render tolerance of the oracle."""
+    """Reverbs (one noise for the whole batch) and 2 s delays with the delay-time surrogate in
+    graphs of different lengths: merged == alone bit for bit (phasor gradients included), alone
+    within the render tolerance of the oracle."""
     types = (synth.MIX, synth.GAIN_PAN, synth.REVERB, synth.DELAY_LONG, synth.EQ)
     ws = [synth.random_workload(seed, 9, T, types=types, edge_p=0.35)
           for seed, T in ((1402, 5 * 2048 + 300), (1411, 2048), (1413, 9001))]
     assert all(w.graph.count(synth.REVERB) >= 1 and w.graph.count(synth.DELAY_LONG) >= 1
                for w in ws)
-    _check_merged(ws, "reverb + 2 s delay", noise=synth.reverb_noise(14, 7000))
+    _check_merged(ws, "reverb + 2 s delay", noise=synth.reverb_noise(14, 7000), surrogate=True)
