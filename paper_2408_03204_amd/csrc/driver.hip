@@ -29,8 +29,8 @@ struct WsLayout {
   size_t fwd_end;
   size_t part_gp, part_im, part_tanh, comp_ragg, comp_part, eq_C, eq_spec, eq_s, delay_part[2];
   size_t ar_ragg, ar_part;
-  size_t rv_Y0, rv_G, rv_hbar, rv_part;
-  size_t dl_X[2], dl_Y0[2], dl_G[2], dl_R[2];
+  size_t rv_Y0, rv_G, rv_hbar, rv_part, rv_len;
+  size_t dl_X[2], dl_Y0[2], dl_G[2], dl_R[2], dl_len[2];
   size_t total;
 };
 
@@ -114,6 +114,7 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
     L.rv_hbar = take(n_rv * 2 * rv_L * sizeof(float));
     L.rv_part = take(n_rv * (n_rv ? (size_t)rv_grad_blocks(h->rv_len) : 0) * 2 *
                      (kRvFft / 2 + 1) * sizeof(double2));
+    L.rv_len = take(n_rv * sizeof(int32_t));  // each reverb node's length, by slot
     // delay-time surrogate: input-window and adjoint-block spectra, cross-spectra, correlation
     for (int f = 0; f < 2; ++f) {
       const size_t n_sur = h->delay_surrogate ? (size_t)h->type_count[kDelayType[f]] : 0;
@@ -122,6 +123,7 @@ WsLayout ws_layout(const grafx_schedule_t* h, int64_t T, bool with_bwd) {
       L.dl_Y0[f] = take(n_sur * sur_nb * kRvStride * sizeof(float4));
       L.dl_G[f] = take(n_sur * delay_sur_parts(kDelaySlots[f]) * kRvStride * sizeof(float4));
       L.dl_R[f] = take(n_sur * 2 * delay_sur_len(kDelaySlots[f]) * sizeof(float));
+      L.dl_len[f] = take(n_sur * sizeof(int32_t));
     }
   }
   L.total = off;
@@ -314,10 +316,11 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
       // R[n] = sum_t ybar[t - 19] u[t - n]: lag n - 19 of the plain correlation
       const int nb = rv_blocks(g.T + kDelaySurShift);
       if (e == hipSuccess && h->delay_surrogate)
-        e = launch_xcorr_spectra(g, b, cnt, false, 0, nb, at<float4>(ws, L.dl_X[f]), stream);
+        e = launch_xcorr_spectra(g, b, cnt, false, 0, nb, at<float4>(ws, L.dl_X[f]), nullptr,
+                                 stream);
       if (e == hipSuccess && h->delay_surrogate)
         e = launch_xcorr_spectra(g, b, cnt, true, -kDelaySurShift, nb, at<float4>(ws, L.dl_Y0[f]),
-                                 stream);
+                                 at<int32_t>(ws, L.dl_len[f]), stream);
       return e;
     }
     case GRAFX_COMPRESSOR_AR:
@@ -329,7 +332,8 @@ hipError_t enqueue_bwd_step(const grafx_schedule_t* h, const GraphView& g, const
                                 error_word(ws, L), stream);
     case GRAFX_REVERB:
       return launch_rv_bwd(g, dU, b, cnt, h->rv_len, at<float4>(ws, L.rv_H),
-                           at<float4>(ws, L.rv_Y0), at<float4>(ws, L.rv_C), stream);
+                           at<float4>(ws, L.rv_Y0), at<float4>(ws, L.rv_C),
+                           at<int32_t>(ws, L.rv_len), stream);
     default:
       return hipErrorInvalidValue;
   }
@@ -498,7 +502,9 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
     e = launch_delay_grad(M, par(t), at<float>(ws, L.delay_part[f]), n_del,
                           delay_groups(T, h->tap_tiles), dpar(t), stream);
     if (e == hipSuccess && h->delay_surrogate)
+      // R[n] = sum_t ybar[t - 19] u[t - n] has no term for n >= the node's length + 19
       e = launch_xcorr(n_del, rv_blocks(T + kDelaySurShift), delay_sur_parts(M), delay_sur_len(M),
+                       at<int32_t>(ws, L.dl_len[f]), kDelaySurShift,
                        at<float4>(ws, L.dl_Y0[f]), at<float4>(ws, L.dl_X[f]),
                        at<float4>(ws, L.dl_G[f]), at<float>(ws, L.dl_R[f]), stream);
     if (e == hipSuccess && h->delay_surrogate)
@@ -508,7 +514,7 @@ grafx_status grafx_render_backward(const grafx_schedule_t* h, const void* dev_pl
   if (e == hipSuccess && dpar(GRAFX_REVERB))
     e = launch_rv_grad(h->type_count[GRAFX_REVERB], T, h->rv_len, par(GRAFX_REVERB),
                        at<double2>(ws, L.rv_Un), at<float4>(ws, L.rv_Z), at<float4>(ws, L.rv_Y0),
-                       at<float4>(ws, L.rv_G), at<float>(ws, L.rv_hbar), at<double>(ws, L.rv_part),
+                       at<int32_t>(ws, L.rv_len), at<float4>(ws, L.rv_G), at<float>(ws, L.rv_hbar), at<double>(ws, L.rv_part),
                        dpar(GRAFX_REVERB), stream);
   return hip_status(e, "render_backward launch");
 }

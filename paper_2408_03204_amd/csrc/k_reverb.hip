@@ -238,7 +238,8 @@ __global__ __launch_bounds__(kBlock) void rv_partition_kernel(const float* h, in
 // zero window. Stored at the node's parameter slot.
 template <bool ADJ>
 __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int node_begin, int nb,
-                                                            int shift, float4* out) {
+                                                            int shift, float4* out,
+                                                            int32_t* slot_len) {
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
   const int b = blockIdx.x, node = node_begin + blockIdx.y;
@@ -246,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int nod
   Twiddles tw;
   load_twiddles(tw, w1lds);
   float2 v[16];
+  if (slot_len && b == 0 && threadIdx.x == 0) slot_len[slot] = (int32_t)node_len(g, node);
   gather_window<ADJ>(g, node, kB * b - kB + shift, v, ADJ ? 8 : 0, 16);
   fft4096<false>(v, lds, tw);
   store_separated(v, lds, out + ((int64_t)slot * nb + b) * kRvStride, 1.0f);
@@ -449,8 +451,12 @@ __global__ __launch_bounds__(kBinWave) void rv_cross_kernel(int nb, int parts, c
 }
 
 // hbar_c[2048 p + i] = first half of the inverse transform of G (left: real part, right:
-// imaginary part of the packed transform G_l + i G_r).
+// imaginary part of the packed transform G_l + i G_r). Lags from valid_len[slot] + valid_shift on
+// have no term (the shifted signals no longer overlap) and are written as exact zeros, not as
+// rounding residue; valid_len is the node's own length, so a node of a merged batch gets the
+// bits it gets alone.
 __global__ __launch_bounds__(kBlock) void rv_hbar_kernel(const float4* Gs, int parts, int64_t L,
+                                                         const int32_t* valid_len, int valid_shift,
                                                          float* hbar) {
   __shared__ float2 lds[kLds];
   __shared__ float2 w1lds[kW1Lds];
@@ -471,12 +477,13 @@ __global__ __launch_bounds__(kBlock) void rv_hbar_kernel(const float4* Gs, int p
   pack_spectrum(al, ar, lds, v);
   fft4096<true>(v, lds, tw);
   float* hb = hbar + (int64_t)slot * 2 * L;
+  const int64_t valid = (int64_t)valid_len[slot] + valid_shift;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int64_t n = (int64_t)kB * p + j + 256 * r;
     if (n < L) {
-      hb[n] = v[r].x;
-      hb[L + n] = v[r].y;
+      hb[n] = n < valid ? v[r].x : 0.f;
+      hb[L + n] = n < valid ? v[r].y : 0.f;
     }
   }
 }
@@ -612,20 +619,23 @@ hipError_t launch_rv_design(const float* P, int n, const float* noise, int64_t L
 }
 
 hipError_t launch_xcorr_spectra(const GraphView& g, int node_begin, int n_nodes, bool adj,
-                                int shift, int nb, float4* out, hipStream_t s) {
+                                int shift, int nb, float4* out, int32_t* slot_len, hipStream_t s) {
   if (adj)
-    rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, shift, out);
+    rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, shift, out,
+                                                                 slot_len);
   else
-    rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, shift, out);
+    rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, shift, out,
+                                                                  slot_len);
   return hipGetLastError();
 }
 
-hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const float4* Y0, const float4* X,
-                        float4* Gs, float* R, hipStream_t s) {
+hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const int32_t* valid_len,
+                        int valid_shift, const float4* Y0, const float4* X, float4* Gs, float* R,
+                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
   rv_cross_kernel<<<dim3(kBinWaves, (parts + kCrossTile - 1) / kCrossTile, n), kBinWave, 0, s>>>(
       nb, parts, Y0, X, Gs);
-  rv_hbar_kernel<<<dim3(parts, n), kBlock, 0, s>>>(Gs, parts, len, R);
+  rv_hbar_kernel<<<dim3(parts, n), kBlock, 0, s>>>(Gs, parts, len, valid_len, valid_shift, R);
   return hipGetLastError();
 }
 
@@ -634,7 +644,7 @@ int rv_conv_tiles(int64_t L) { return (rv_parts(L) + kConvTile - 1) / kConvTile;
 hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nodes, int64_t L,
                          const float4* Hs, float4* Z, float4* C, hipStream_t s) {
   const int nb = rv_blocks(g.T), parts = rv_parts(L), tiles = rv_conv_tiles(L);
-  rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Z);
+  rv_spectra_kernel<false><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Z, nullptr);
   const int nseg = (nb + kConvSeg - 1) / kConvSeg;
   rv_conv_bins_kernel<false><<<dim3(kBinWaves, tiles * nseg, n_nodes), kBinWave, 0, s>>>(
       g, node_begin, nb, parts, tiles, nseg, Z, Hs, C);
@@ -643,9 +653,10 @@ hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nod
 }
 
 hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
-                         const float4* Hs, float4* Y0, float4* C, hipStream_t s) {
+                         const float4* Hs, float4* Y0, float4* C, int32_t* slot_len,
+                         hipStream_t s) {
   const int nb = rv_blocks(g.T), parts = rv_parts(L), tiles = rv_conv_tiles(L);
-  rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Y0);
+  rv_spectra_kernel<true><<<dim3(nb, n_nodes), kBlock, 0, s>>>(g, node_begin, nb, 0, Y0, slot_len);
   const int nseg = (nb + kConvSeg - 1) / kConvSeg;
   rv_conv_bins_kernel<true><<<dim3(kBinWaves, tiles * nseg, n_nodes), kBinWave, 0, s>>>(
       g, node_begin, nb, parts, tiles, nseg, Y0, Hs, C);
@@ -654,11 +665,12 @@ hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_no
 }
 
 hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const double2* Un,
-                          const float4* Z, const float4* Y0, float4* Gs, float* hbar,
-                          double* part, float* dP, hipStream_t s) {
+                          const float4* Z, const float4* Y0, const int32_t* slot_len, float4* Gs,
+                          float* hbar, double* part, float* dP, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int nb = rv_blocks(T), parts = rv_parts(L), M = rv_frames(L);
-  const hipError_t e = launch_xcorr(n, nb, parts, L, Y0, Z, Gs, hbar, s);
+  // hbar[n] = sum_t ybar[t] u[t - n] has no term for n >= the node's length
+  const hipError_t e = launch_xcorr(n, nb, parts, L, slot_len, 0, Y0, Z, Gs, hbar, s);
   if (e != hipSuccess) return e;
   const int nblk = rv_grad_blocks(L);
   rv_mask_grad_kernel<<<dim3(nblk, n), kHop, 0, s>>>(P, Un, hbar, L, M,

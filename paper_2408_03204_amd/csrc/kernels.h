@@ -153,25 +153,29 @@ hipError_t launch_rv_fwd(const GraphView& g, float* U, int node_begin, int n_nod
 // Y0: float4 [n][blocks][kRvStride] spectra of the output-adjoint blocks (kept for the FIR
 // gradient)
 hipError_t launch_rv_bwd(const GraphView& g, float* dU, int node_begin, int n_nodes, int64_t L,
-                         const float4* Hs, float4* Y0, float4* C, hipStream_t s);
+                         const float4* Hs, float4* Y0, float4* C, int32_t* slot_len,
+                         hipStream_t s);
 // Partitioned cross-correlation R_c[n] = sum_t ybar_c[t + s_a] u_c[t + s_i - n], n in [0, len),
 // of a node's output adjoint and its input sum (the reverb's FIR gradient; the delay's surrogate
 // gradient), over nb blocks of 2048 (nb x 2048 must cover every t with a non-zero term). Spectra
 // per node parameter slot: input windows (adj false, shift s_i: [2048 b - 2048 + s_i,
 // 2048 b + 2048 + s_i)) or single output-adjoint blocks (adj true, shift s_a:
-// [2048 b + s_a, 2048 b + 2048 + s_a)), float4 [slots][nb][kRvStride]; then, for n slots, Gs:
-// float4 [n][parts][kRvStride] cross-spectra and R: float [n][2][len] (parts = ceil(len / 2048)).
+// [2048 b + s_a, 2048 b + 2048 + s_a)), float4 [slots][nb][kRvStride], and, if slot_len is not
+// null, each node's length at its slot; then, for n slots, Gs: float4 [n][parts][kRvStride]
+// cross-spectra and R: float [n][2][len] (parts = ceil(len / 2048)); lags from
+// valid_len[slot] + valid_shift on (where no term of the sum exists) are stored as exact zeros.
 // Input samples before 0 must not reach a term (s_i <= 0): the input windows start at b = 0.
 hipError_t launch_xcorr_spectra(const GraphView& g, int node_begin, int n_nodes, bool adj,
-                                int shift, int nb, float4* out, hipStream_t s);
-hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const float4* Y0, const float4* X,
-                        float4* Gs, float* R, hipStream_t s);
+                                int shift, int nb, float4* out, int32_t* slot_len, hipStream_t s);
+hipError_t launch_xcorr(int n, int nb, int parts, int64_t len, const int32_t* valid_len,
+                        int valid_shift, const float4* Y0, const float4* X, float4* Gs, float* R,
+                        hipStream_t s);
 // After the last adjoint step, every reverb slot: Gs: float4 [n][parts][kRvStride] partition
 // cross-spectra; hbar: float [n][2][L]; part: double [n][grad blocks][2][193][2]; dP: float
 // [n][768]
 hipError_t launch_rv_grad(int n, int64_t T, int64_t L, const float* P, const double2* Un,
-                          const float4* Z, const float4* Y0, float4* Gs, float* hbar,
-                          double* part, float* dP, hipStream_t s);
+                          const float4* Z, const float4* Y0, const int32_t* slot_len, float4* Gs,
+                          float* hbar, double* part, float* dP, hipStream_t s);
 
 // ---- MRSTFT loss (k_mrstft.hip) -------------------------------------------------------------
 size_t mrstft_ws_bytes(int rows, int64_t T);
