@@ -7,9 +7,8 @@
 // bin 191's mask); every frame goes back through a real inverse DFT, and the frames are
 // overlap-added without a synthesis window (the periodic Hann window sums to one at half
 // overlap). Mid/side become left/right as in the imager: h_l = (h_m + h_s) / 2,
-// h_r = (h_m - h_s) / 2. The noise STFT and the inverse DFTs are direct sums in double
-// (384-point frames, 193 one-sided bins); a block makes one hop of h from the two frames that
-// overlap there, so no two blocks write one sample.
+// h_r = (h_m - h_s) / 2. The noise STFT is a direct sum in double; a hop of h is one real inverse
+// DFT (in double) of the two masked frames that overlap there, combined in the frequency domain.
 //
 // Filtering: y_c[t] = sum_n h_c[n] u_c[t - n], a causal FIR as long as the noise (two seconds in
 // the paper), as uniformly partitioned overlap-save. The FIR is cut into partitions of 2048 taps,
@@ -18,8 +17,10 @@
 // block b is the sum over partitions p of the spectrum of input window b - p times that of
 // partition p, and the second half of its inverse transform is the block. Both channels ride in
 // one complex transform (left + i right) and are separated into one-sided per-channel spectra
-// (bins 0..2048) when stored, so a product bin needs one load per operand and each thread forms
-// bins k and 4096 - k of the packed output spectrum from one product.
+// (bins 0..2048) when stored. The sum over partitions runs bin-major (a thread per bin, the
+// partition spectra in registers, the blocks streaming through), its partial spectra per tile of
+// partitions go through the workspace, and a second kernel rebuilds each block's packed spectrum
+// and transforms it back.
 //
 // Adjoint: the input adjoint is the correlation ubar_c[s] = sum_n h_c[n] ybar_c[s + n], the same
 // partitioned product with the conjugate partition spectra over forward-looking windows
@@ -30,7 +31,7 @@
 // partition p, the inverse transform of sum_b Y0_c[b][k] conj(X_c[b - p][k]) (X: the forward's
 // input-window spectra, kept in the workspace), first half. It goes back through mid/side, the
 // overlap-add (each frame reads its own slice of hbar), the inverse DFT and the mask to dH0 and
-// dHD, with per-frame partials summed in frame order.
+// dHD, with partials per group of frames summed in a fixed order.
 #include "device_common.h"
 #include "fft4096.h"
 #include "grafx_internal.h"
