@@ -43,28 +43,32 @@ __device__ __forceinline__ void load_twiddles(Twiddles& tw, float2* w1lds) {
 template <bool INV>
 __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds, const Twiddles& tw) {
   const int j = threadIdx.x;
+  // The padded index pad(i) of the three access patterns splits into a per-thread base and a
+  // multiple of r known at compile time (an immediate offset of the LDS instruction):
+  // pad(16 j + r) = 17 j + r, pad(j + 256 r) = j + j / 16 + 272 r and
+  // pad(256 (j / 16) + j mod 16 + 16 r) = 272 (j / 16) + j mod 16 + 17 r.
+  float2* const l0 = lds + 17 * j;
+  float2* const l1 = lds + j + (j >> 4);
+  float2* const l2 = lds + (j >> 4) * 272 + (j & 15);
   // pass 0 (sub-transform size 1): no twiddles
   dft16<INV>(v);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) lds[pad(16 * j + r)] = v[r];
+  for (int r = 0; r < 16; ++r) l0[r] = v[r];
   __syncthreads();
   // pass 1 (sub-transform size 16)
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = lds[pad(j + 256 * r)];
+  for (int r = 0; r < 16; ++r) v[r] = l1[272 * r];
   const float2* w1 = tw.w1 + (j & 15) * kW1Row;
 #pragma unroll
   for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], INV ? cconj(w1[r]) : w1[r]);
   dft16<INV>(v);
   __syncthreads();
-  {
-    const int base = (j >> 4) * 256 + (j & 15);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[pad(base + 16 * r)] = v[r];
-  }
+  for (int r = 0; r < 16; ++r) l2[17 * r] = v[r];
   __syncthreads();
   // pass 2 (sub-transform size 256): outputs land at j + 256 r
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = lds[pad(j + 256 * r)];
+  for (int r = 0; r < 16; ++r) v[r] = l1[272 * r];
 #pragma unroll
   for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], INV ? cconj(tw.w2[r]) : tw.w2[r]);
   dft16<INV>(v);
@@ -81,27 +85,30 @@ __device__ __forceinline__ void gather_window(const GraphView& g, int node, int 
   const int e0 = ADJ ? g.out_ptr[node] : g.in_ptr[node];
   const int e1 = ADJ ? g.out_ptr[node + 1] : g.in_ptr[node + 1];
   const int j = threadIdx.x;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-  for (int e = e0; e < e1; ++e) {
-    const int other = ADJ ? g.out_dst[e] : g.in_src[e];
+  auto load_row = [&](int e, float2 (&x)[16]) {
+    // the edge, its row and the row's length are the same in every lane: keep them scalar
+    const int other = __builtin_amdgcn_readfirstlane(ADJ ? g.out_dst[e] : g.in_src[e]);
     const float* row = ADJ ? adj_row(g, other) : out_row(g, other);
-    const int64_t L = node_len(g, other);
+    const int L = __builtin_amdgcn_readfirstlane((int)node_len(g, other));
     const auto rl = row_rsrc(row, L), rr = row_rsrc(row + T, L);
-    float2 x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int t = w0 + j + 256 * r;
       x[r] = (r < r_lo || r >= r_hi) ? make_float2(0.f, 0.f)
                                      : make_float2(bload(rl, t), bload(rr, t));
     }
-    if (e == e0) {
+  };
+  if (e0 == e1) {  // no incoming rows
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = x[r];
-    } else {
+    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+    return;
+  }
+  load_row(e0, v);  // the first row is loaded in place, later rows are added to it
+  for (int e = e0 + 1; e < e1; ++e) {
+    float2 x[16];
+    load_row(e, x);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = cadd(v[r], x[r]);
-    }
+    for (int r = 0; r < 16; ++r) v[r] = cadd(v[r], x[r]);
   }
 }
 

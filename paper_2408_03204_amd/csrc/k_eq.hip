@@ -128,13 +128,12 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
   }
   fft4096<true>(v, lds, tw);
   float* y = U + (int64_t)node * 2 * T;
+  const auto yl = row_rsrc(y, Tn), yr = row_rsrc(y + T, Tn);  // stores past Tn are dropped
 #pragma unroll
   for (int r = 4; r < 12; ++r) {
     const int t = t0 + j + 256 * (r - 4);
-    if (t < Tn) {
-      y[t] = v[r].x;
-      y[T + t] = v[r].y;
-    }
+    bstore(yl, t, v[r].x);
+    bstore(yr, t, v[r].y);
   }
 }
 
@@ -172,12 +171,13 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
     v[r].y *= hk;
   }
   fft4096<true>(v, lds, tw);
+  {
+    const auto dl = row_rsrc(d, Tn), dr = row_rsrc(d + T, Tn);  // stores past Tn are dropped
 #pragma unroll
-  for (int r = 4; r < 12; ++r) {
-    const int t = t0 + j + 256 * (r - 4);
-    if (t < Tn) {
-      d[t] = v[r].x;
-      d[T + t] = v[r].y;
+    for (int r = 4; r < 12; ++r) {
+      const int t = t0 + j + 256 * (r - 4);
+      bstore(dl, t, v[r].x);
+      bstore(dr, t, v[r].y);
     }
   }
   gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded
