@@ -174,11 +174,50 @@ __device__ __forceinline__ void dft8(float2* v) {
   for (int i = 0; i < 8; ++i) v[i] = o[i];
 }
 
-template <bool INV>
+// x + y and x - y where ZX / ZY state that x / y is known to be zero, so no instruction is spent
+// on it (the result equals the full sum up to the sign of an exact zero)
+template <bool ZX, bool ZY>
+__device__ __forceinline__ float2 cadd_z(float2 x, float2 y) {
+  if constexpr (ZX && ZY) return make_float2(0.f, 0.f);
+  else if constexpr (ZX) return y;
+  else if constexpr (ZY) return x;
+  else return cadd(x, y);
+}
+template <bool ZX, bool ZY>
+__device__ __forceinline__ float2 csub_z(float2 x, float2 y) {
+  if constexpr (ZX && ZY) return make_float2(0.f, 0.f);
+  else if constexpr (ZX) return make_float2(-y.x, -y.y);
+  else if constexpr (ZY) return x;
+  else return csub(x, y);
+}
+
+// dft4 whose inputs a_i are known to be zero where Z_i
+template <bool INV, bool Z0, bool Z1, bool Z2, bool Z3>
+__device__ __forceinline__ void dft4_z(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = cadd_z<Z0, Z2>(a0, a2), t1 = csub_z<Z0, Z2>(a0, a2);
+  const float2 t2 = cadd_z<Z1, Z3>(a1, a3), t3 = mul_mi<INV>(csub_z<Z1, Z3>(a1, a3));
+  constexpr bool ZE = Z0 && Z2, ZO = Z1 && Z3;
+  a0 = cadd_z<ZE, ZO>(t0, t2);
+  a2 = csub_z<ZE, ZO>(t0, t2);
+  a1 = cadd_z<ZE, ZO>(t1, t3);
+  a3 = csub_z<ZE, ZO>(t1, t3);
+}
+
+// First-stage dft4 of the radix-16 DFT over inputs N2, N2 + 4, N2 + 8, N2 + 12; bit r of LIVE
+// clear means that input r is known to be zero.
+template <bool INV, unsigned LIVE, int N2>
+__device__ __forceinline__ void dft16_stage1(float2* v) {
+  dft4_z<INV, !((LIVE >> N2) & 1u), !((LIVE >> (N2 + 4)) & 1u), !((LIVE >> (N2 + 8)) & 1u),
+         !((LIVE >> (N2 + 12)) & 1u)>(v[N2], v[N2 + 4], v[N2 + 8], v[N2 + 12]);
+}
+
+template <bool INV, unsigned LIVE = 0xFFFFu>
 __device__ __forceinline__ void dft16(float2* v) {
   // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+  dft16_stage1<INV, LIVE, 0>(v);
+  dft16_stage1<INV, LIVE, 1>(v);
+  dft16_stage1<INV, LIVE, 2>(v);
+  dft16_stage1<INV, LIVE, 3>(v);
   // after this, v[n2 + 4 k1] holds Y[n2][k1]; twiddle by w16^(n2 k1)
   v[5] = cmul(v[5], w16<INV>(1));
   v[6] = cmul(v[6], w16<INV>(2));

@@ -39,8 +39,10 @@ __device__ __forceinline__ void load_twiddles(Twiddles& tw, float2* w1lds) {
 }
 
 // In-place 4096-point DFT (forward: exp(-2 pi i nk/N); inverse: exp(+...), unnormalised).
-// On entry v[r] holds x[j + 256 r] for thread j; on exit v[r] holds X[j + 256 r].
-template <bool INV>
+// On entry v[r] holds x[j + 256 r] for thread j; on exit v[r] holds X[j + 256 r]. Bit r of LIVE
+// clear states that v[r] is zero on entry in every thread (a zero-padded window), which the first
+// pass skips.
+template <bool INV, unsigned LIVE = 0xFFFFu>
 __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds, const Twiddles& tw) {
   const int j = threadIdx.x;
   // The padded index pad(i) of the three access patterns splits into a per-thread base and a
@@ -51,7 +53,7 @@ __device__ __forceinline__ void fft4096(float2 (&v)[16], float2* lds, const Twid
   float2* const l1 = lds + j + (j >> 4);
   float2* const l2 = lds + (j >> 4) * 272 + (j & 15);
   // pass 0 (sub-transform size 1): no twiddles
-  dft16<INV>(v);
+  dft16<INV, LIVE>(v);
 #pragma unroll
   for (int r = 0; r < 16; ++r) l0[r] = v[r];
   __syncthreads();

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
     }
   }
   gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded
-  fft4096<false>(v, lds, tw);
+  fft4096<false, 0x0FF0u>(v, lds, tw);
   // Re C[k] = Re(W'[k] conj(U[k])); fold F[k] = Re C[k] + Re C[N - k], k = 0..N/2 (bins of other
   // threads: through the transform's LDS, free again after its last barrier)
   float* cre = reinterpret_cast<float*>(lds);

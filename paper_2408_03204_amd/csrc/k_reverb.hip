@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void rv_partition_kernel(const float* h, in
     const int64_t n = (int64_t)kB * p + j + 256 * r;
     v[r] = (r < 8 && n < L) ? make_float2(hl[n], hl[L + n]) : make_float2(0.f, 0.f);
   }
-  fft4096<false>(v, lds, tw);
+  fft4096<false, 0x00FFu>(v, lds, tw);
   store_separated(v, lds, Hs + ((int64_t)slot * parts + p) * kRvStride, 1.0f / kN);
 }
 
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void rv_spectra_kernel(GraphView g, int nod
   float2 v[16];
   if (slot_len && b == 0 && threadIdx.x == 0) slot_len[slot] = (int32_t)node_len(g, node);
   gather_window<ADJ>(g, node, kB * b - kB + shift, v, ADJ ? 8 : 0, 16);
-  fft4096<false>(v, lds, tw);
+  fft4096<false, ADJ ? 0xFF00u : 0xFFFFu>(v, lds, tw);
   store_separated(v, lds, out + ((int64_t)slot * nb + b) * kRvStride, 1.0f);
 }
 

@@ -11,6 +11,15 @@ replay's first start and last end, as a fraction of that span, over all replays:
 
     python rocprof_summary.py gaps <run_results.db> <replays> <command...>
 
+VALU issue per kernel from one PMC run (`--pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_WAVES SQ_BUSY_CYCLES`):
+VALU instructions per wave, and the fraction of the VALU issue rate a kernel's launches use, i.e.
+SQ_INSTS_VALU x 4 cycles (a wave64 instruction on a 16-lane SIMD) over 1024 SIMDs x the launch
+time, both at the 2.4 GHz peak clock and at the clock the shader engines ran at (SQ_BUSY_CYCLES
+per engine over the launch time, 32 engines); launches with fewer than `min_blocks` blocks are
+left out:
+
+    python rocprof_summary.py valu <run_results.db> <min_blocks> <command...>
+
 HBM traffic per kernel from two PMC runs (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`) of a
 program that first copies `copy_mib` MiB device-to-device: each counter is scaled by
 (true bytes of that copy) / (what the counter reads for it). Also writes the traffic of one
@@ -84,6 +93,38 @@ def gaps(db: str, replays: int, cmd: str) -> None:
     print(f"\nall replays: gaps {tot_gap:.1f} us of {tot_span:.1f} us = {tot_gap / tot_span:.4f}")
 
 
+def valu(db: str, min_blocks: int, cmd: str) -> None:
+    c = sqlite3.connect(db)
+    rows = c.execute("select dispatch_id, kernel_name, counter_name, value, duration, grid_size, "
+                     "workgroup_size from counters_collection")
+    disp: dict = collections.defaultdict(dict)
+    for d, k, n, v, dur, gs, wg in rows:
+        disp[d].update(k=k, dur=dur, blocks=gs // wg)
+        disp[d][n] = v
+    agg: dict = collections.defaultdict(lambda: collections.Counter())
+    for x in disp.values():
+        if x["blocks"] < min_blocks:
+            continue
+        a = agg[short(x["k"])]
+        a["n"] += 1
+        a["dur"] += x["dur"]
+        for n in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_WAVES", "SQ_BUSY_CYCLES"):
+            a[n] += x.get(n, 0)
+    print(f"# rocprofv3 PMC summary: VALU issue per kernel (launches of at least {min_blocks} "
+          f"blocks)\n# command: {cmd}\n")
+    print(f"{'kernel':46s} {'calls':>5s} {'avg_us':>8s} {'valu/wave':>9s} {'lds/wave':>8s} "
+          f"{'clk_GHz':>7s} {'issue@2.4':>9s} {'issue@clk':>9s}")
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["dur"]):
+        if not a["SQ_WAVES"]:
+            continue
+        t = a["dur"] * 1e-9
+        clk = a["SQ_BUSY_CYCLES"] / 32 / t / 1e9
+        busy = a["SQ_INSTS_VALU"] * 4 / 1024 / t / 1e9  # GHz-equivalent of VALU issue
+        print(f"{k[:46]:46s} {a['n']:5d} {a['dur'] / 1e3 / a['n']:8.1f} "
+              f"{a['SQ_INSTS_VALU'] / a['SQ_WAVES']:9.0f} {a['SQ_INSTS_LDS'] / a['SQ_WAVES']:8.0f} "
+              f"{clk:7.2f} {busy / 2.4:9.3f} {busy / clk:9.3f}")
+
+
 def _counter(db: str, name: str):
     c = sqlite3.connect(db)
     return list(c.execute("select dispatch_id, kernel_name, value from counters_collection "
@@ -132,6 +173,8 @@ if __name__ == "__main__":
         trace(sys.argv[2], " ".join(sys.argv[3:]))
     elif sys.argv[1] == "gaps":
         gaps(sys.argv[2], int(sys.argv[3]), " ".join(sys.argv[4:]))
+    elif sys.argv[1] == "valu":
+        valu(sys.argv[2], int(sys.argv[3]), " ".join(sys.argv[4:]))
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6],
             sys.argv[7], sys.argv[8], sys.argv[9], " ".join(sys.argv[10:]))
