@@ -49,12 +49,18 @@ TYPE_NAMES = ("in", "out", "mix", "gain_pan", "eq", "compressor", "imager", "del
               "noisegate", "compressor_ar", "reverb", "delay_long")
 # kernel source of each step type (to tie a stored PMC traffic figure to the code it came from)
 # (the kernel file, then the local headers whose code it compiles in, hashed in this order)
-KERNEL_SRC = {"mix": ("k_pointwise.hip",), "out": ("k_pointwise.hip",),
-              "gain_pan": ("k_pointwise.hip",), "imager": ("k_pointwise.hip",),
-              "tanh": ("k_pointwise.hip",), "eq": ("k_eq.hip", "fft4096.h"),
-              "compressor": ("k_comp.hip", "dynamics.h"), "noisegate": ("k_comp.hip", "dynamics.h"),
-              "compressor_ar": ("k_comp_ar.hip", "dynamics.h"), "delay": ("k_delay.hip",),
-              "reverb": ("k_reverb.hip", "fft4096.h"), "delay_long": ("k_delay.hip",)}
+KERNEL_SRC = {"mix": ("k_pointwise.hip", "device_common.h"),
+              "out": ("k_pointwise.hip", "device_common.h"),
+              "gain_pan": ("k_pointwise.hip", "device_common.h"),
+              "imager": ("k_pointwise.hip", "device_common.h"),
+              "tanh": ("k_pointwise.hip", "device_common.h"),
+              "eq": ("k_eq.hip", "fft4096.h", "device_common.h"),
+              "compressor": ("k_comp.hip", "dynamics.h", "device_common.h"),
+              "noisegate": ("k_comp.hip", "dynamics.h", "device_common.h"),
+              "compressor_ar": ("k_comp_ar.hip", "dynamics.h", "device_common.h"),
+              "delay": ("k_delay.hip", "device_common.h"),
+              "reverb": ("k_reverb.hip", "fft4096.h", "device_common.h"),
+              "delay_long": ("k_delay.hip", "device_common.h")}
 
 
 def parse():
