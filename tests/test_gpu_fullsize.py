@@ -51,9 +51,10 @@ def test_console_full_step_against_oracle(console):
     L64 = OM.mrstft(Y64, tgt64)
     g64 = torch.autograd.grad(L64, [P64[t] for t in keys])
     e_y = rel_err(Y.detach().cpu().numpy().astype(np.float64), Y64.detach().numpy())
-    say(f"   Y rel err {e_y:.3e}; loss {float(L):.8f} vs {float(L64):.8f}")
+    loss, loss64 = float(L.detach()), float(L64.detach())
+    say(f"   Y rel err {e_y:.3e}; loss {loss:.8f} vs {loss64:.8f}")
     assert e_y <= RENDER_TOL
-    assert abs(float(L) - float(L64)) <= 1e-5 * abs(float(L64))
+    assert abs(loss - loss64) <= 1e-5 * abs(loss64)
     for t, a, b in zip(keys, grads, g64):
         e = grad_err(a.cpu().numpy(), b.numpy())
         say(f"   dP[{t}] rel err {e:.3e}")
