@@ -23,8 +23,9 @@ def test_mrstft_loss_and_grad(rows, T):
     y64 = torch.as_tensor(y, dtype=torch.float64).requires_grad_(True)
     L64 = OM.mrstft(y64, torch.as_tensor(tgt, dtype=torch.float64))
     (g64,) = torch.autograd.grad(L64, [y64]) if L64.requires_grad else (torch.zeros_like(y64),)
-    say("   loss", float(L), float(L64))
-    assert abs(float(L) - float(L64)) <= 1e-5 * max(1.0, abs(float(L64)))
+    loss, loss64 = float(L.detach()), float(L64.detach())
+    say("   loss", loss, loss64)
+    assert abs(loss - loss64) <= 1e-5 * max(1.0, abs(loss64))
     e = grad_err(Y.grad.cpu().numpy(), g64.numpy())
     say("   grad err", e)
     assert e <= GRAD_TOL
