@@ -1,9 +1,9 @@
 """GPU parity of the compressor with distinct attack and release ballistics (Eq. 8 unrestricted)
 against the FP64 oracle's literal per-sample loop, forward and adjoint. The kernel iterates on
 the attack/release branch pattern and falls back to a serial recursion for any chunk that has
-not settled after a given number of passes; GRAFX_AR_MAX_PASSES lowers that number so that the
-fallback runs (1 pass: almost every chunk falls back; 2-3: some do). That number is the
-schedule's GRAFX_TUNE_AR_MAX_PASSES setting, set here through the C ABI."""
+not settled after a given number of passes. That number is the schedule's
+GRAFX_TUNE_AR_MAX_PASSES setting, lowered here through the C ABI so that the fallback runs
+(1 pass: almost every chunk falls back; 2-3: some do)."""
 import numpy as np
 import pytest
 import torch
