@@ -66,6 +66,15 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, float 
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, idx * 4, 0, 0);
 }
 
+// The same store marked non-temporal (cache policy bit 1): for the signal rows a step writes,
+// which only later steps read back, after the caches have turned over.
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, int idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, idx * 4, 0, 2);
+}
+
+// A plain non-temporal store of one float.
+__device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; remap the hardware block id so
 // that every XCD works through one contiguous range of logical blocks (neighbouring time tiles
 // of a node then share an L2, which serves their overlapping halos).

@@ -185,8 +185,8 @@ __device__ __forceinline__ void store_chunk(float* row, int64_t T, int64_t Tn, i
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int idx = tid + kBlock * q;
-    bstore(rl, t0 + idx, sl[lpos(idx)]);
-    bstore(rr, t0 + idx, sr[lpos(idx)]);
+    bstore_nt(rl, t0 + idx, sl[lpos(idx)]);
+    bstore_nt(rr, t0 + idx, sr[lpos(idx)]);
   }
 }
 

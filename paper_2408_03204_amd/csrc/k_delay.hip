@@ -141,8 +141,8 @@ __global__ __launch_bounds__(kBlock) void delay_conv_kernel(GraphView g, float* 
   for (int idx = threadIdx.x; idx < kHop; idx += kBlock) {
     const int64_t t = t0 + idx;
     if (t < Tn) {
-      y[t] = ys[0][idx];
-      y[T + t] = ys[1][idx];
+      store_nt(y + t, ys[0][idx]);
+      store_nt(y + T + t, ys[1][idx]);
     }
   }
   (void)tiles;

@@ -132,8 +132,8 @@ __global__ __launch_bounds__(kBlock) void eq_fwd_kernel(GraphView g, float* U, c
 #pragma unroll
   for (int r = 4; r < 12; ++r) {
     const int t = t0 + j + 256 * (r - 4);
-    bstore(yl, t, v[r].x);
-    bstore(yr, t, v[r].y);
+    bstore_nt(yl, t, v[r].x);
+    bstore_nt(yr, t, v[r].y);
   }
 }
 
@@ -176,8 +176,8 @@ __global__ __launch_bounds__(kBlock) void eq_bwd_kernel(GraphView g, float* dU, 
 #pragma unroll
     for (int r = 4; r < 12; ++r) {
       const int t = t0 + j + 256 * (r - 4);
-      bstore(dl, t, v[r].x);
-      bstore(dr, t, v[r].y);
+      bstore_nt(dl, t, v[r].x);
+      bstore_nt(dr, t, v[r].y);
     }
   }
   gather_window<false>(g, node, t0 - kN / 4, v, 4, 12);  // input tile, zero-padded

@@ -50,6 +50,13 @@ __device__ __forceinline__ void fwd_op(float& l, float& r, Gains k) {
   }
 }
 
+// Streaming store of 4 floats (16-byte aligned): marked non-temporal, since a step's output rows
+// are read back only by later steps, long after the caches have turned over.
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void nt_store4(float* p, float a, float b, float c, float d) {
+  __builtin_nontemporal_store(v4f{a, b, c, d}, reinterpret_cast<v4f*>(p));
+}
+
 __device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, int idx) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 4, 0, 0));
 }
@@ -118,8 +125,8 @@ __global__ __launch_bounds__(kBlock) void pointwise_fwd_kernel(GraphView g, floa
     for (int q = 0; q < 4; ++q) fwd_op<TYPE>(l[u][q], r[u][q], k);
     if constexpr (V4) {
       if (t < Tn) {
-        *reinterpret_cast<float4*>(y + t) = make_float4(l[u][0], l[u][1], l[u][2], l[u][3]);
-        *reinterpret_cast<float4*>(y + T + t) = make_float4(r[u][0], r[u][1], r[u][2], r[u][3]);
+        nt_store4(y + t, l[u][0], l[u][1], l[u][2], l[u][3]);
+        nt_store4(y + T + t, r[u][0], r[u][1], r[u][2], r[u][3]);
       }
     } else {
 #pragma unroll
@@ -147,7 +154,7 @@ __device__ __forceinline__ void load_n(const float* p, float* out) {
 
 template <bool V4>
 __device__ __forceinline__ void store_n(float* p, const float* v) {
-  if constexpr (V4) *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  if constexpr (V4) nt_store4(p, v[0], v[1], v[2], v[3]);
   else *p = v[0];
 }
 

@@ -384,8 +384,8 @@ __global__ __launch_bounds__(kBlock) void rv_inverse_kernel(GraphView g, float* 
     const int64_t t = (int64_t)kB * b + j + 256 * r;
     if (t < Tn) {
       const float2 o = v[CORR ? r : r + 8];
-      y[t] = o.x;
-      y[T + t] = o.y;
+      store_nt(y + t, o.x);
+      store_nt(y + T + t, o.y);
     }
   }
 }
