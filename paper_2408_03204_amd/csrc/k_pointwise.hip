@@ -57,8 +57,9 @@ __device__ __forceinline__ void nt_store4(float* p, float a, float b, float c, f
   __builtin_nontemporal_store(v4f{a, b, c, d}, reinterpret_cast<v4f*>(p));
 }
 
+// Input rows are read once per consumer: loads marked non-temporal (cache policy bit 1).
 __device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, int idx) {
-  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 4, 0, 0));
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 4, 0, 2));
 }
 
 // n (4 or 1) consecutive floats of a row through a length-bounded buffer resource
