@@ -61,6 +61,11 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int idx) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
 }
 
+// The same load marked non-temporal (cache policy bit 1), for rows read once.
+__device__ __forceinline__ float bload_nt(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 2));
+}
+
 // Raw buffer store: an element index outside the resource's range is dropped by the hardware.
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, idx * 4, 0, 0);

@@ -150,8 +150,8 @@ __device__ __forceinline__ void stage(const GraphView& g, int node, int t0, floa
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int t = t0 + (int)threadIdx.x + kBlock * q;
-      xl[q] = bload(rl, t);
-      xr[q] = bload(rr, t);
+      xl[q] = bload_nt(rl, t);
+      xr[q] = bload_nt(rr, t);
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void pointwise_fwd_kernel(GraphView g, floa
 template <bool V4>
 __device__ __forceinline__ void load_n(const float* p, float* out) {
   if constexpr (V4) {
-    const float4 a = *reinterpret_cast<const float4*>(p);
+    const v4f a = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
     out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
   } else {
     out[0] = *p;
